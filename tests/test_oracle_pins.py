@@ -1,0 +1,333 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test names the passage of arXiv:2105.09688 (or the mathematical fact) it
+checks.  None of them calls the HIP library; they run on any CPU.
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from paper_2105_09688_amd import workloads as W
+
+mp.mp.dps = 50
+
+
+# --------------------------------------------------------------------------- Philox
+def _numpy_block(ctr, key):
+    """The block numpy's independent Philox4x64-10 returns for counter ``ctr``.
+
+    numpy advances its counter before every block, so it is started one
+    below (with borrow across the four words)."""
+    c = [int(v) for v in ctr]
+    for w in range(4):
+        if c[w] > 0:
+            c[w] -= 1
+            break
+        c[w] = 2 ** 64 - 1
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(c, dtype=np.uint64))
+    return bg.random_raw(4)
+
+
+def test_philox_bitwise_equals_numpy(oracle_mod):
+    rng = np.random.default_rng(123)
+    cases = [([0, 0, 0, 0], [0, 0]), ([1, 0, 0, 0], [0, 0]), ([0, 0, 0, 1 << 32], [7, 0]),
+             ([2 ** 64 - 1] * 4, [2 ** 64 - 1] * 2)]
+    for _ in range(200):
+        cases.append((list(rng.integers(0, 2 ** 63, 4, dtype=np.uint64) * 2 + rng.integers(0, 2, 4).astype(np.uint64)),
+                      list(rng.integers(0, 2 ** 63, 2, dtype=np.uint64))))
+    for ctr, key in cases:
+        mine = oracle_mod.philox4x64_10(ctr, key)
+        ref = _numpy_block(ctr, key)
+        assert np.array_equal(mine, ref), (ctr, key, mine, ref)
+
+
+def test_normals_are_standard_gaussian(oracle_mod):
+    """Box-Muller output: moments, independence of the four streams and a KS test."""
+    from scipy import stats
+    n = 20000
+    z = np.array([oracle_mod.normals4(0, 0, i, 3, 1) for i in range(n)])  # [n, 4]
+    flat = z.ravel()
+    assert abs(flat.mean()) < 4.0 / math.sqrt(flat.size)
+    assert abs(flat.var() - 1.0) < 4.0 * math.sqrt(2.0 / flat.size)
+    assert abs(stats.skew(flat)) < 4.0 * math.sqrt(6.0 / flat.size)
+    assert abs(stats.kurtosis(flat)) < 4.0 * math.sqrt(24.0 / flat.size)
+    for k in range(4):
+        assert stats.kstest(z[:, k], "norm").pvalue > 1e-3
+    corr = np.corrcoef(z.T)
+    assert np.max(np.abs(corr - np.eye(4))) < 4.0 / math.sqrt(n)
+    # different tags / grid indices / ensembles give different numbers
+    assert not np.array_equal(oracle_mod.normals4(0, 0, 5, 3, 1), oracle_mod.normals4(0, 1, 5, 3, 1))
+    assert not np.array_equal(oracle_mod.normals4(0, 0, 5, 3, 1), oracle_mod.normals4(0, 0, 5, 4, 1))
+    assert not np.array_equal(oracle_mod.normals4(0, 0, 5, 3, 1), oracle_mod.normals4(0, 0, 5, 3, 2))
+
+
+# --------------------------------------------------------------------------- implicit step (2.3)
+def _cardano(x, a, h):
+    """Real root of y + a h y^3 = x (hyperbolic form of Cardano's formula)."""
+    x = mp.mpf(x)
+    k = 2 / mp.sqrt(3 * a * h)
+    return k * mp.sinh(mp.asinh(3 * mp.sqrt(3 * a * h) / 2 * x) / 3)
+
+
+@pytest.mark.parametrize("log2h", [4, 6, 8, 10, 12, 14])
+def test_implicit_cubic_matches_cardano(oracle_mod, log2h):
+    h = 2.0 ** -log2h
+    for x in np.linspace(-20.0, 20.0, 81):
+        y, _ = oracle_mod.implicit([x], h, rho=0.0, a=1.0)
+        ref = _cardano(x, 1, mp.mpf(h))
+        assert abs(mp.mpf(y[0]) - ref) <= 4e-16 * max(abs(ref), mp.mpf(1e-300)), (x, h)
+
+
+def test_implicit_radial_d3_matches_cardano(oracle_mod):
+    rng = np.random.default_rng(5)
+    for _ in range(100):
+        x = rng.normal(size=3) * 3
+        h = 2.0 ** -rng.integers(3, 12)
+        y, _ = oracle_mod.implicit(x, h, rho=0.0, a=1.0)
+        r = _cardano(np.linalg.norm(x), 1, mp.mpf(h))
+        for k in range(3):
+            assert abs(mp.mpf(y[k]) - r * mp.mpf(x[k]) / mp.mpf(np.linalg.norm(x))) < 1e-15 * (1 + abs(r))
+
+
+def test_implicit_solves_defining_equation_general_family(oracle_mod):
+    """c = x + h v(c, mu) of (2.3), checked in 50-digit arithmetic for the
+    whole coefficient family (linear part, cubic, m2- and mean-dependence)."""
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        d = int(rng.integers(1, 5))
+        x = rng.normal(size=d) * 2
+        xbar = rng.normal(size=d)
+        h = float(2.0 ** -rng.integers(2, 10))
+        rho, a, kappa, lam = rng.normal(), abs(rng.normal()), abs(rng.normal()), rng.normal()
+        m2 = abs(rng.normal()) * 2
+        if 1 - h * (rho - kappa * m2) <= 0.05:
+            continue
+        c, _ = oracle_mod.implicit(x, h, rho=rho, a=a, kappa=kappa, lam=lam, xbar=xbar, m2=m2)
+        cm = [mp.mpf(v) for v in c]
+        n2 = sum(v * v for v in cm)
+        for k in range(d):
+            v = (mp.mpf(rho) - mp.mpf(kappa) * mp.mpf(m2)) * cm[k] - mp.mpf(a) * n2 * cm[k] + mp.mpf(lam) * mp.mpf(xbar[k])
+            res = cm[k] - mp.mpf(x[k]) - mp.mpf(h) * v
+            assert abs(res) < 1e-14 * (1 + abs(mp.mpf(x[k]))), (d, k, float(res))
+
+
+@pytest.mark.parametrize("h", [0.01, 0.05, 0.09])
+def test_implicit_linear_closed_form_remark_4_3(oracle_mod, h):
+    """Remark 4.3: for v(x) = 10 x the implicit solution is y = x / (1 - 10 h)."""
+    for x in [-3.0, -0.5, 0.0, 1.0, 7.25]:
+        y, _ = oracle_mod.implicit([x], h, rho=10.0, a=0.0)
+        assert y[0] == pytest.approx(x / (1 - 10 * h), rel=1e-15, abs=0)
+
+
+def test_implicit_lemma_4_1_inequalities(oracle_mod):
+    """(4.3)-(4.6) with L_v = 0 (v = -|x|^2 x):  |v_h(x)| <= |v(x)|,
+    |F_h(x) - F_h(y)| <= |x - y|, <x - y, v_h(x) - v_h(y)> <= 0."""
+    rng = np.random.default_rng(11)
+    for _ in range(500):
+        d = int(rng.integers(1, 4))
+        h = float(2.0 ** -rng.integers(1, 10))
+        x, z = rng.normal(size=d) * 3, rng.normal(size=d) * 3
+        fx, _ = oracle_mod.implicit(x, h, a=1.0)
+        fz, _ = oracle_mod.implicit(z, h, a=1.0)
+        vh_x = -np.dot(fx, fx) * fx
+        vh_z = -np.dot(fz, fz) * fz
+        v_x = -np.dot(x, x) * x
+        assert np.linalg.norm(vh_x) <= np.linalg.norm(v_x) * (1 + 1e-12) + 1e-300
+        assert np.linalg.norm(fx - fz) <= np.linalg.norm(x - z) * (1 + 1e-12)
+        assert np.dot(x - z, vh_x - vh_z) <= 1e-12 * (1 + np.linalg.norm(x - z) ** 2)
+        assert np.linalg.norm(fx) <= np.linalg.norm(x) * (1 + 1e-15)
+
+
+def test_implicit_rejects_step_without_unique_root(oracle_mod):
+    from oracle import OracleError
+    with pytest.raises(OracleError):
+        oracle_mod.implicit([1.0], 0.2, rho=10.0, a=0.0)  # 1 - h rho < 0
+
+
+# --------------------------------------------------------------------------- interaction term
+def _pair_sum_mp(Y, ell):
+    d, N = Y.shape
+    out = np.zeros((d, N))
+    for i in range(N):
+        acc = [mp.mpf(0)] * d
+        for j in range(N):
+            diff = [mp.mpf(Y[k, j]) - mp.mpf(Y[k, i]) for k in range(d)]
+            e = mp.exp(-sum(t * t for t in diff) / (2 * mp.mpf(ell) ** 2))
+            acc = [acc[k] + diff[k] * e for k in range(d)]
+        for k in range(d):
+            out[k, i] = float(acc[k] / N)
+    return out
+
+
+@pytest.mark.parametrize("d,N,ell", [(1, 2, 1.0), (1, 7, 1.0), (2, 5, 1.0), (3, 8, 0.5)])
+def test_pair_sum_brute_force_small_N(oracle_mod, d, N, ell):
+    Y = W.random_cloud(d, N, seed=d * 100 + N)
+    got = oracle_mod.pair_sum(Y, ell)
+    ref = _pair_sum_mp(Y, ell)
+    assert np.allclose(got, ref, rtol=1e-14, atol=1e-15)
+
+
+def test_pair_sum_two_particles_closed_form(oracle_mod):
+    y1, y2 = 0.3, -1.2
+    K = oracle_mod.pair_sum(np.array([[y1, y2]]), 1.0)
+    k1 = 0.5 * (y2 - y1) * math.exp(-0.5 * (y2 - y1) ** 2)
+    assert K[0, 0] == pytest.approx(k1, rel=1e-15)
+    assert K[0, 1] == pytest.approx(-k1, rel=1e-15)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_pair_sum_invariants(oracle_mod, d):
+    """Odd kernel: zero net force; translation invariance; permutation equivariance."""
+    N = 300
+    Y = W.random_cloud(d, N, seed=d)
+    K = oracle_mod.pair_sum(Y, 0.7)
+    scale = np.max(np.abs(K))
+    assert np.all(np.abs(K.sum(axis=1)) <= 64 * N * np.finfo(float).eps * max(scale, 1e-300) * N)
+    K2 = oracle_mod.pair_sum(Y + 3.5, 0.7)
+    assert np.allclose(K, K2, rtol=0, atol=1e-13)
+    perm = np.random.default_rng(d).permutation(N)
+    K3 = oracle_mod.pair_sum(Y[:, perm], 0.7)
+    assert np.allclose(K[:, perm], K3, rtol=0, atol=1e-14)
+
+
+def test_drift_terms(oracle_mod):
+    """b = c0 y + lam mean(mu_Y) + g * pair term, each checked against numpy on its own."""
+    Y = W.random_cloud(2, 50, seed=3)
+    K = oracle_mod.pair_sum(Y, 1.3)
+    B = oracle_mod.drift(Y, c0=0.7, lam=-0.4, g=2.0, ell=1.3)
+    ref = 0.7 * Y + (-0.4) * Y.mean(axis=1, keepdims=True) + 2.0 * K
+    assert np.allclose(B, ref, rtol=1e-14, atol=1e-15)
+
+
+# --------------------------------------------------------------------------- one full step, brute force
+def test_full_step_brute_force_small_N(oracle_mod):
+    """(2.3)-(2.4) at N = 6 in 50-digit arithmetic: implicit root by mpmath
+    findroot, exact sums, the same Brownian increments."""
+    w = W.small_parity(n_ens=1, N=6, h=2.0 ** -6, h_fine=2.0 ** -8)
+    w["sigma"] = dict(s0=[0.05], s1=[0.3], s2=[0.2])
+    e, N, h, n = 0, 6, 2.0 ** -6, 3
+    X = W.random_cloud(1, N, seed=9, loc=0.5)
+    Xn, Y = oracle_mod.step(w, e, h, n, X)
+    r = 4
+    ys = []
+    for i in range(N):
+        x = mp.mpf(X[0, i])
+        ys.append(mp.findroot(lambda y: y + mp.mpf(h) * y ** 3 - x, x))
+    ybar = sum(ys) / N
+    for i in range(N):
+        pair = sum((ys[j] - ys[i]) * mp.exp(-(ys[i] - ys[j]) ** 2 / 2) for j in range(N)) / N
+        b = ys[i] + pair
+        sig = mp.mpf(0.05) + mp.mpf(0.3) * ys[i] + mp.mpf(0.2) * ybar
+        zsum = sum(mp.mpf(oracle_mod.normals4(0, 0, i, n * r + m, e)[0]) for m in range(r))
+        dW = mp.sqrt(mp.mpf(2.0 ** -8)) * zsum
+        xn = ys[i] + b * mp.mpf(h) + sig * dW
+        assert abs(mp.mpf(Y[0, i]) - ys[i]) < 1e-15
+        assert abs(mp.mpf(Xn[0, i]) - xn) < 2e-15 * (1 + abs(xn)), (i, float(xn), Xn[0, i])
+
+
+def test_initial_state_and_moments(oracle_mod):
+    w = W.small_parity(n_ens=1, N=4000)
+    X = oracle_mod.init_state(w, 0, 4000)
+    m, v = oracle_mod.moments(X)
+    assert m[0] == pytest.approx(float(X.mean()), rel=1e-14)
+    assert v[0] == pytest.approx(float(X.var()), rel=1e-13)
+    assert abs(m[0] - 1.0) < 4 * 0.5 / math.sqrt(4000)
+    assert abs(v[0] - 0.25) < 4 * 0.25 * math.sqrt(2 / 4000)
+
+
+# --------------------------------------------------------------------------- whole scheme: linear MV-SDE
+def test_ou_mean_recursion_pathwise(oracle_mod):
+    """Section 3.4.1 family (v = rho x, b = lam E[X], sigma = eta): the scheme
+    gives exactly  mean(X_{n+1}) = (1 + h lam)/(1 - h rho) mean(X_n) + eta mean_i dW_i."""
+    rho, lam, eta, h, N = -0.8, 0.6, 0.4, 2.0 ** -5, 64
+    w = W.ou(rho=rho, lam=lam, eta=eta, x0=1.0, x0_std=0.3, N=N, h=h, T=0.5, h_fine=2.0 ** -7)
+    X = oracle_mod.init_state(w, 0, N)
+    mean = X.mean()
+    r = 4
+    for n in range(16):
+        X, _ = oracle_mod.step(w, 0, h, n, X)
+        dW = np.array([math.sqrt(2.0 ** -7) * sum(oracle_mod.normals4(0, 0, i, n * r + m, 0)[0] for m in range(r))
+                       for i in range(N)])
+        mean = (1 + h * lam) / (1 - h * rho) * mean + eta * dW.mean()
+        assert X.mean() == pytest.approx(mean, rel=1e-12, abs=1e-13)
+
+
+def test_ou_moments_closed_form(oracle_mod):
+    """E[X_t] = x0 e^{(rho+lam)t},  E[X_t^2] = x0^2 e^{2(rho+lam)t} + eta^2/(2 rho)(e^{2 rho t} - 1)
+    (Section 3.4.1), deterministic x0; tolerance O(h) plus 5 standard errors."""
+    rho, lam, eta, x0, T = -1.0, 0.5, 0.8, 1.0, 1.0
+    h, N = 2.0 ** -9, 20000
+    w = W.ou(rho=rho, lam=lam, eta=eta, x0=x0, N=N, h=h, T=T)
+    X = oracle_mod.run(w)[0][0]
+    m_ref = x0 * math.exp((rho + lam) * T)
+    s_ref = x0 ** 2 * math.exp(2 * (rho + lam) * T) + eta ** 2 / (2 * rho) * (math.exp(2 * rho * T) - 1)
+    se_m = X.std() / math.sqrt(N)
+    se_s = (X ** 2).std() / math.sqrt(N)
+    assert abs(X.mean() - m_ref) < 5 * se_m + 2 * h
+    assert abs((X ** 2).mean() - s_ref) < 5 * se_s + 4 * h
+
+
+def test_ou_expected_variance_recursion(oracle_mod):
+    """E V_{n+1} = E V_n / (1 - h rho)^2 + eta^2 h (N-1)/N for the empirical
+    variance V (b only shifts the mean); averaged over 400 ensembles."""
+    rho, eta, h, N, n_ens, M = -0.5, 0.7, 2.0 ** -4, 16, 400, 8
+    w = W.ou(rho=rho, lam=0.3, eta=eta, x0=0.0, x0_std=0.0, N=N, h=h, n_ens=n_ens, T=M * h)
+    Xs = oracle_mod.run(w)
+    V = np.array([X[0].var() for X in Xs])
+    ev = 0.0
+    for _ in range(M):
+        ev = ev / (1 - h * rho) ** 2 + eta ** 2 * h * (N - 1) / N
+    sd = V.std() / math.sqrt(n_ens)
+    assert abs(V.mean() - ev) < 5 * sd
+
+
+# --------------------------------------------------------------------------- strong rate (Theorem 2.6)
+def _ginzburg_landau(N, n_ens, h_fine):
+    """Section 3.1, SSM version 1: v = -x^3, b = (s'^2/2) x + c E[X], sigma = s' x,
+    s' = 1.5, c = 0.5, x0 = 1, T = 1."""
+    return dict(d=1, T=1.0, seed=0, h_fine=h_fine, systems=[(N, e, h_fine) for e in range(n_ens)],
+                v=dict(rho=0.0, a=1.0), b=dict(c0=1.5 ** 2 / 2, lam=0.5, g=0.0, ell=1.0),
+                sigma=dict(s0=[0.0], s1=[1.5], s2=[0.0]), x0_mean=[1.0], x0_std=[0.0])
+
+
+def test_strong_rate_one_half_ginzburg_landau(oracle_mod):
+    """Theorem 2.6 (2): rMSE = O(h^{1/2}); Section 3.1 observes a rate of about
+    1/2 for the Ginzburg-Landau example.  Proxy solution at h = 2^-14 on the
+    same Brownian paths (Section 3), h = 2^-6 .. 2^-10."""
+    base = _ginzburg_landau(N=250, n_ens=8, h_fine=2.0 ** -14)
+    ref = oracle_mod.run(base)
+    hs, errs = [], []
+    for l in range(6, 11):
+        h = 2.0 ** -l
+        hs.append(h)
+        errs.append(oracle_mod.strong_error(oracle_mod.run(W.with_h(base, h)), ref))
+    slope = oracle_mod.ols_slope(hs, errs)
+    assert 0.4 <= slope <= 0.7, (slope, errs)
+
+
+def test_strong_rate_gaussian_interaction_at_least_one_half(oracle_mod):
+    """Same check for the d=1 Gaussian-interaction coefficients: the theorem
+    bounds the rate from below by 1/2.  (The multiplicative noise here is weak,
+    sigma sigma' ~ 0.1, so the first-order drift error dominates at these h
+    and the observed rate is close to 1.)"""
+    base = W.small_parity(n_ens=10, N=200, h_fine=2.0 ** -12)
+    ref = oracle_mod.run(W.with_h(base, 2.0 ** -12))
+    hs, errs = [], []
+    for l in range(4, 9):
+        h = 2.0 ** -l
+        hs.append(h)
+        errs.append(oracle_mod.strong_error(oracle_mod.run(W.with_h(base, h)), ref))
+    slope = oracle_mod.ols_slope(hs, errs)
+    assert 0.45 <= slope <= 1.3, (slope, errs)
+    assert all(e1 > e2 for e1, e2 in zip(errs, errs[1:]))
+
+
+def test_run_rejects_step_violating_theorem_2_6(oracle_mod):
+    from oracle import OracleError
+    w = W.ou(rho=6.0, lam=0.0, eta=0.1, h=2.0 ** -3, T=0.25)  # 1 - h(2 rho + 1) < 0
+    with pytest.raises(OracleError):
+        oracle_mod.run(w)
+    w["allow_unstable_h"] = True
+    oracle_mod.run(w)
