@@ -1,0 +1,226 @@
+/*
+ * ssm.h -- C ABI of libssm, an MI355X (gfx950) implementation of the
+ * split-step method (SSM) of Chen & dos Reis, arXiv:2105.09688, for
+ * N-particle McKean-Vlasov systems.
+ *
+ * One time step of the scheme, Section 2.2, eqs. (2.3)-(2.4):
+ *   Y*_n^i    = X_n^i + h v(t_n, Y*_n^i, mu^X_n)                       (2.3)
+ *   X_{n+1}^i = Y*_n^i + b(t_n, Y*_n^i, mu^Y_n) h
+ *               + sigma(t_n, Y*_n^i, mu^Y_n) dW_n^i                    (2.4)
+ * with mu^X_n, mu^Y_n the empirical measures of all N particles (self
+ * included).  Everything runs in HIP kernels on the device; the host only
+ * validates, allocates and launches.
+ *
+ * Conventions for every entry point:
+ *  - Returns ssm_status: SSM_OK (0) or a negative error.  No C++ exception
+ *    crosses the ABI.  ssm_last_error() returns a thread-local message for the
+ *    last failure on the calling thread.
+ *  - "host" pointers are read or written during the call only; the caller
+ *    keeps ownership.  "device" pointers are HIP device memory owned by the
+ *    caller (for instance torch tensors); the library never frees them.
+ *  - Arrays of particle data are component-major (SoA): element (k, i) of a
+ *    [d][N] array is at k*N + i.
+ *  - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *    Entry points that take device pointers are asynchronous on that stream;
+ *    errors of the kernels themselves (sticky flags) are reported by
+ *    ssm_sync()/ssm_run()/ssm_moments()/ssm_get_state() of a context.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef SSM_H
+#define SSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSM_MAX_D 4
+
+typedef enum {
+    SSM_OK = 0,
+    SSM_ERR_INVALID = -1,   /* bad argument or configuration */
+    SSM_ERR_NEWTON = -2,    /* implicit solve did not converge within newton_max_iter */
+    SSM_ERR_NONFINITE = -3, /* a particle became NaN/Inf */
+    SSM_ERR_HIP = -4,       /* HIP runtime error */
+    SSM_ERR_OOM = -5,       /* device allocation failed */
+    SSM_ERR_STATE = -6      /* call not valid in the context's current state (e.g. past T) */
+} ssm_status;
+
+typedef enum {
+    SSM_FP64 = 0,       /* state and pairwise sums in double precision */
+    SSM_FP32 = 1,       /* state in float, pairwise sums accumulated plainly in float */
+    SSM_FP32_KAHAN = 2  /* state in float, pairwise sums in float within a tile of
+                           sources, compensated (Neumaier) across tiles */
+} ssm_precision;
+
+/*
+ * Coefficients (the split v + b of Section 2; Remark 2.7 moves a linear term
+ * between them through v_rho and b_c0):
+ *   v(y, mu_X) = (v_rho - v_kappa m2(mu_X)) y - v_a |y|^2 y + v_lam mean(mu_X)
+ *   b(y, mu_Y) = b_c0 y + b_lam mean(mu_Y)
+ *                + b_g (1/N) sum_j (Y^j - y) exp(-|y - Y^j|^2 / (2 b_ell^2))
+ *   sigma(y, mu_Y) = diag_k(s0[k] + s1[k] y_k + s2[k] mean_k(mu_Y))  (one Brownian
+ *                    motion per component)
+ * with m2(mu) = (1/N) sum_j |X^j|^2.  Requirements: v_a >= 0, v_kappa >= 0,
+ * b_ell > 0 if b_g != 0, and for every system 1 - h v_rho > 0 (Lemma 4.1:
+ * unique implicit root) and, unless allow_unstable_h, 1 - h (2 v_rho + 1) > 0
+ * (the step-size condition of Theorem 2.6, L_v = v_rho).
+ *
+ * Systems: n_sys independent particle clouds advanced together.  System s has
+ * N[s] particles, time step h[s] and ensemble id ens[s].  Brownian paths depend
+ * on (ens, particle index) only, so systems of one ensemble with different h
+ * see the same paths (Section 3 compares step sizes on the same paths).  The
+ * increment over a step is the sum of the fine-grid increments
+ *   dW_n^i = sqrt(h_fine) sum_{m < r} Z(0, i, n r + m, ens),  r = h / h_fine,
+ * where Z(tag, i, n, e) are four standard normals: Philox4x64-10 (Salmon et
+ * al., SC'11) of counter (i, n, e, tag << 32) under key (seed, 0), each word w
+ * mapped to u = ((w >> 11) + 0.5) 2^-53 and Box-Muller applied to (u0, u1) and
+ * (u2, u3); component k uses normal k.  X_0^i = x0_mean + x0_std * Z(1, i, 0, ens).
+ *
+ * Time: every h[s] must divide T and be an integer multiple of h_fine.  Let
+ * h_min = min h[s]; a "tick" advances time by h_min, and system s takes a step
+ * on every tick t with t % (h[s]/h_min) == 0 (h[s]/h_min must divide the
+ * largest such ratio).
+ */
+typedef struct {
+    int32_t d;              /* state dimension, 1..SSM_MAX_D */
+    int32_t n_sys;          /* number of systems, >= 1 */
+    const int64_t *N;       /* host [n_sys]: particles per system, 1 .. 2^31-1 */
+    const int32_t *ens;     /* host [n_sys]: ensemble id (Philox counter word 2) */
+    const double *h;        /* host [n_sys]: time step per system */
+    double T;               /* horizon */
+    double h_fine;          /* Brownian grid step */
+    uint64_t seed;          /* Philox key word 0 */
+    int32_t precision;      /* ssm_precision */
+    double v_rho, v_a, v_kappa, v_lam;
+    double b_c0, b_lam, b_g, b_ell;
+    double s0[SSM_MAX_D], s1[SSM_MAX_D], s2[SSM_MAX_D];
+    double x0_mean[SSM_MAX_D], x0_std[SSM_MAX_D];
+    int32_t newton_max_iter;   /* 0 -> 64 */
+    int32_t allow_unstable_h;  /* nonzero: skip the Theorem 2.6 check (stability studies) */
+    void *stream;              /* hipStream_t the context launches on; NULL -> a stream it owns */
+    /* Tiling of the pairwise kernel; 0 = library default.  Results do not
+     * depend on these beyond floating-point summation order. */
+    int32_t targets_per_lane;  /* 1, 2, 4 or 8 */
+    int32_t sources_per_item;  /* sources one wavefront sweeps per work item (>= 64) */
+} ssm_config;
+
+typedef struct {
+    int64_t tick;            /* ticks taken */
+    int64_t ticks_total;     /* T / h_min */
+    int32_t newton_max_seen; /* largest Newton iteration count seen so far */
+    int32_t newton_failures; /* particles whose implicit solve failed (sticky) */
+    int32_t nonfinite;       /* particles that became non-finite (sticky) */
+    int32_t n_pair_items;    /* wavefront work items of the pairwise kernel per tick (phase 0) */
+    int32_t targets_per_lane;
+    int32_t sources_per_item;
+    int64_t device_bytes;    /* device memory the context holds */
+    /* Kernel timing (ssm_profile enabled): HIP events recorded on the context's
+     * stream around each launch since the last ssm_profile(ctx, 1). */
+    int64_t pair_launches;   /* launches of the pairwise kernel */
+    double pair_ms;          /* their summed duration, milliseconds */
+    int64_t update_launches; /* launches of the per-particle update (+ implicit solve) kernels */
+    double update_ms;
+} ssm_info_t;
+
+typedef struct ssm_ctx ssm_ctx; /* opaque; owned by the library */
+
+/* Create a context: validate cfg, allocate the device state, draw X_0
+ * (Philox stream tag 1) and solve the implicit step (2.3) of the first step.
+ * *out receives the context, or NULL on error.  Asynchronous on the stream. */
+ssm_status ssm_init(const ssm_config *cfg, ssm_ctx **out);
+
+/* Advance n_ticks ticks (each system steps when its step boundary falls on
+ * the tick).  Asynchronous: enqueues kernels on the context's stream and
+ * returns.  SSM_ERR_STATE if this would pass T. */
+ssm_status ssm_step(ssm_ctx *ctx, int64_t n_ticks);
+
+/* Advance every system to T and synchronize; reports sticky kernel errors. */
+ssm_status ssm_run(ssm_ctx *ctx);
+
+/* Wait for the context's stream; return SSM_ERR_NEWTON / SSM_ERR_NONFINITE if
+ * a kernel flagged a particle since init. */
+ssm_status ssm_sync(ssm_ctx *ctx);
+
+/* Empirical moments of system sys (Section 3): mean[k] = (1/N) sum_i X_k^i and
+ * var[k] = (1/N) sum_i (X_k^i - mean[k])^2, two passes in double precision on
+ * the device.  mean, var: host [d].  Synchronizes. */
+ssm_status ssm_moments(ssm_ctx *ctx, int32_t sys, double *mean, double *var);
+
+/* Copy the state of system sys to host memory as double, [d][N].  which = 0:
+ * X (current positions); which = 1: Y* = F_h(X), the solution of (2.3) for the
+ * current X (valid once computed; the library keeps it one step ahead).
+ * *step (may be NULL) receives the number of steps the system has taken.
+ * Synchronizes. */
+ssm_status ssm_get_state(ssm_ctx *ctx, int32_t sys, int32_t which, double *host, int64_t *step);
+
+/* Overwrite X of system sys with host [d][N] (rounded to the storage
+ * precision) and recompute Y* for it.  Synchronizes. */
+ssm_status ssm_set_state(ssm_ctx *ctx, int32_t sys, const double *host);
+
+/* Strong error between two contexts with identical system layouts:
+ * per_sys[s] = sum_i |X_a^i - X_b^i|^2 over system s (host [n_sys], may be
+ * NULL), *rmse = sqrt(sum over all systems / total particles).  This is the
+ * epsilon_2 estimator of Section 3 when b holds the proxy solution.
+ * Synchronizes both contexts. */
+ssm_status ssm_rmse(ssm_ctx *a, ssm_ctx *b, double *per_sys, double *rmse);
+
+/* Enable (nonzero) or disable per-kernel timing with HIP events on the
+ * context's stream; enabling resets the accumulated times.  Timing adds one
+ * event record before and after each kernel launch. */
+ssm_status ssm_profile(ssm_ctx *ctx, int32_t enable);
+
+/* Counters, tiling and (if enabled) kernel times of a context.  Synchronizes. */
+ssm_status ssm_info(ssm_ctx *ctx, ssm_info_t *out);
+
+/* Destroy a context (waits for its stream first).  NULL is a no-op. */
+void ssm_destroy(ssm_ctx *ctx);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *ssm_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Kernel-level entry points on caller-owned device memory.  They run the
+ * same kernels the context uses, for one system, and exist so that a caller
+ * (or a test) can drive a single stage of the step.
+ * ------------------------------------------------------------------------- */
+
+/* Pairwise part of b (eq. (2.4) drift, the O(N^2) term):
+ *   K[k][i] = (1/N) sum_j (Y_k^j - Y_k^i) exp(-|Y^i - Y^j|^2 / (2 ell^2)),
+ * j over all N particles.  Y: device [d][N], double for SSM_FP64 and float for
+ * the FP32 modes.  K: device [d][N] double.  workspace: device buffer of at
+ * least ssm_pair_workspace_bytes(d, N, precision) bytes (scratch for partial
+ * sums; contents on entry ignored).  Asynchronous on stream. */
+ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, const void *Y, double ell,
+                        double *K, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Bytes of workspace ssm_pair_sum needs (deterministic function of its args). */
+size_t ssm_pair_workspace_bytes(int32_t d, int64_t N, int32_t precision);
+
+/* Implicit step (2.3) for N particles: Y^i = F_h(X^i), the unique c with
+ * c = X^i + h v(c, mu_X) for the coefficient family above (Lemma 4.1).  X, Y:
+ * device [d][N] double.  xbar: host [d] (mean of mu_X, used if v_lam != 0);
+ * m2: second moment of mu_X (used if v_kappa != 0).  iters: device [N] int32
+ * (Newton iterations, -1 on failure), may be NULL.  Asynchronous on stream. */
+ssm_status ssm_implicit_solve(int32_t d, int64_t N, const double *X, double h, double v_rho,
+                              double v_a, double v_kappa, double v_lam, const double *xbar,
+                              double m2, int32_t max_iter, double *Y, int32_t *iters, void *stream);
+
+/* Brownian increments of one step for particles 0..N-1 of ensemble ens:
+ * dW[k][i] = sqrt(h_fine) sum_{m < r} Z(0, i, n0 + m, ens)_k.  dW: device [d][N]
+ * double.  Asynchronous on stream. */
+ssm_status ssm_brownian(int32_t d, int64_t N, uint64_t seed, int32_t ens, int64_t n0, int32_t r,
+                        double h_fine, double *dW, void *stream);
+
+/* Raw Philox4x64-10 blocks: out[4 q + w] = word w of the block of counter
+ * (c0 + q, c1, c2, c3) under key (k0, k1), q = 0..count-1.  out: device
+ * uint64 [4 count].  Asynchronous on stream. */
+ssm_status ssm_philox_blocks(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                             uint64_t k1, int64_t count, uint64_t *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSM_H */

@@ -62,6 +62,8 @@ def _load():
     lib.ssmo_drift.argtypes = [C.c_int, C.c_int64, dp, C.c_double, C.c_double, C.c_double,
                                C.c_double, dp]
     lib.ssmo_pair_sum.argtypes = [C.c_int, C.c_int64, dp, C.c_double, dp]
+    lib.ssmo_pair_sum_at.argtypes = [C.c_int, C.c_int64, dp, C.c_double, C.c_int64,
+                                     C.POINTER(C.c_int64), dp]
     lib.ssmo_step.argtypes = [C.POINTER(_Cfg), C.c_int32, C.c_int64, C.c_double, C.c_int64, dp, dp]
     lib.ssmo_step.restype = C.c_int
     lib.ssmo_init_state.argtypes = [C.POINTER(_Cfg), C.c_int32, C.c_int64, dp]
@@ -131,6 +133,17 @@ def pair_sum(Y: np.ndarray, ell: float) -> np.ndarray:
     d, N = Y.shape
     K = np.zeros_like(Y)
     lib.ssmo_pair_sum(d, N, _dp(Y), ell, _dp(K))
+    return K
+
+
+def pair_sum_at(Y: np.ndarray, ell: float, idx) -> np.ndarray:
+    """The pairwise part at targets ``idx`` only: [d][len(idx)]."""
+    lib = _load()
+    Y = _f64(np.atleast_2d(Y))
+    d, N = Y.shape
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    K = np.zeros((d, idx.size))
+    lib.ssmo_pair_sum_at(d, N, _dp(Y), ell, idx.size, idx.ctypes.data_as(C.POINTER(C.c_int64)), _dp(K))
     return K
 
 

@@ -164,6 +164,28 @@ void ssmo_pair_sum(int d, int64_t N, const double *Y, double ell, double *K)
     }
 }
 
+void ssmo_pair_sum_at(int d, int64_t N, const double *Y, double ell, int64_t n_idx,
+                      const int64_t *idx, double *K)
+{
+    const double inv2l2 = 1.0 / (2.0 * ell * ell);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n_idx; ++q) {
+        const int64_t i = idx[q];
+        double acc[SSMO_MAX_D] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < N; ++j) {
+            double diff[SSMO_MAX_D];
+            double dist2 = 0.0;
+            for (int k = 0; k < d; ++k) {
+                diff[k] = Y[(int64_t)k * N + j] - Y[(int64_t)k * N + i];
+                dist2 += diff[k] * diff[k];
+            }
+            double kern = exp(-dist2 * inv2l2);
+            for (int k = 0; k < d; ++k) acc[k] += diff[k] * kern;
+        }
+        for (int k = 0; k < d; ++k) K[(int64_t)k * n_idx + q] = acc[k] / (double)N;
+    }
+}
+
 static void mean_of(int d, int64_t N, const double *X, double *mean)
 {
     for (int k = 0; k < d; ++k) {

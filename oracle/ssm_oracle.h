@@ -73,6 +73,10 @@ int ssmo_implicit(int d, const double *x, double h, double v_rho, double v_a,
                   double v_kappa, double v_lam, const double *xbar, double m2,
                   int max_iter, double *y);
 
+/* The pairwise part at selected targets only: K[k][q] for i = idx[q]. */
+void ssmo_pair_sum_at(int d, int64_t N, const double *Y, double ell, int64_t n_idx,
+                      const int64_t *idx, double *K);
+
 /* Interaction drift b at mu_Y for every particle (eq. (2.4) drift term).
  * Y, B are component-major [d][N]. */
 void ssmo_drift(int d, int64_t N, const double *Y, double b_c0, double b_lam,

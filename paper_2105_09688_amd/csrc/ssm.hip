@@ -1,0 +1,917 @@
+// ssm.hip -- libssm: host runtime and C ABI (include/ssm.h) of the SSM
+// particle step on MI355X (gfx950).  See ssm_kernels.hpp for the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ssm.h"
+#include "ssm_kernels.hpp"
+
+using namespace ssm;
+
+static constexpr double kLog2e = 1.4426950408889634073599246810018921;  // log2(e)
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static ssm_status fail(ssm_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(SSM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+extern "C" const char* ssm_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// kernels of the kernel-level entry points
+// ---------------------------------------------------------------------------
+namespace ssm {
+
+__global__ void k_combine(const double* __restrict__ Bp, int splits, int d, int64_t P, int64_t N,
+                          double scale, double* __restrict__ K)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int k = 0; k < d; ++k) {
+        double s = 0.0;
+        for (int q = 0; q < splits; ++q) s += Bp[((int64_t)q * d + k) * P + i];
+        K[(int64_t)k * N + i] = s * scale;
+    }
+}
+
+__global__ void k_brownian(int d, int64_t N, uint64_t seed, int32_t ens, int64_t n0, int32_t r,
+                           double sqrt_hf, double* __restrict__ dW)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double zs[kMaxD] = {0.0, 0.0, 0.0, 0.0};
+    for (int m = 0; m < r; ++m) {
+        double z[kMaxD];
+        normals(seed, 0u, (uint64_t)i, (uint64_t)(n0 + m), (uint64_t)ens, d, z);
+        for (int k = 0; k < d; ++k) zs[k] += z[k];
+    }
+    for (int k = 0; k < d; ++k) dW[(int64_t)k * N + i] = sqrt_hf * zs[k];
+}
+
+__global__ void k_philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                         uint64_t k1, int64_t count, uint64_t* __restrict__ out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const Block4 b = philox4x64_10(c0 + (uint64_t)q, c1, c2, c3, k0, k1);
+    for (int w = 0; w < 4; ++w) out[4 * q + w] = b.w[w];
+}
+
+template <int D>
+__global__ void k_implicit_plain(int64_t N, const double* __restrict__ X, double h, double rho,
+                                 double a, double kappa, double lam, double xb0, double xb1,
+                                 double xb2, double xb3, double m2, int max_iter,
+                                 double* __restrict__ Y, int32_t* __restrict__ iters)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double xbar[kMaxD] = {xb0, xb1, xb2, xb3};
+    double w[D], y[D];
+    for (int k = 0; k < D; ++k) w[k] = X[(int64_t)k * N + i] + h * lam * xbar[k];
+    const int it = implicit_radial<D>(w, 1.0 - h * (rho - kappa * m2), h * a, max_iter, y);
+    for (int k = 0; k < D; ++k) Y[(int64_t)k * N + i] = y[k];
+    if (iters) iters[i] = it;
+}
+
+}  // namespace ssm
+
+// ---------------------------------------------------------------------------
+// kernel dispatch tables (d, R, precision)
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+static void launch_pair_T(int R, bool kahan, dim3 grid, hipStream_t st, const PairItem* items,
+                          int n, const SysDev* sys, const T* Ys, int64_t P, double* Bp)
+{
+    dim3 block(64 * kWaves);
+#define SSM_PAIR_CASE(RR)                                                                      \
+    case RR:                                                                                   \
+        if (kahan)                                                                             \
+            hipLaunchKernelGGL((k_pair<T, D, RR, true>), grid, block, 0, st, items, n, sys, Ys, P, Bp); \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_pair<T, D, RR, false>), grid, block, 0, st, items, n, sys, Ys, P, Bp); \
+        break;
+    switch (R) {
+        SSM_PAIR_CASE(1)
+        SSM_PAIR_CASE(2)
+        SSM_PAIR_CASE(4)
+        SSM_PAIR_CASE(8)
+        default: break;
+    }
+#undef SSM_PAIR_CASE
+}
+
+template <typename T>
+static void launch_pair(int d, int R, bool kahan, dim3 grid, hipStream_t st, const PairItem* items,
+                        int n, const SysDev* sys, const T* Ys, int64_t P, double* Bp)
+{
+    switch (d) {
+        case 1: launch_pair_T<T, 1>(R, kahan, grid, st, items, n, sys, Ys, P, Bp); break;
+        case 2: launch_pair_T<T, 2>(R, kahan, grid, st, items, n, sys, Ys, P, Bp); break;
+        case 3: launch_pair_T<T, 3>(R, kahan, grid, st, items, n, sys, Ys, P, Bp); break;
+        case 4: launch_pair_T<T, 4>(R, kahan, grid, st, items, n, sys, Ys, P, Bp); break;
+        default: break;
+    }
+}
+
+#define SSM_DISPATCH_D(d, KERNEL_CALL)       \
+    switch (d) {                             \
+        case 1: { constexpr int D = 1; KERNEL_CALL; } break; \
+        case 2: { constexpr int D = 2; KERNEL_CALL; } break; \
+        case 3: { constexpr int D = 3; KERNEL_CALL; } break; \
+        case 4: { constexpr int D = 4; KERNEL_CALL; } break; \
+        default: break;                      \
+    }
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct SysHost {
+    int64_t N;
+    int32_t ens;
+    double h;
+    int64_t stride;  // ticks per step
+    int64_t r;       // fine increments per step
+    int64_t off;     // slot offset
+    int64_t blk0, nblk;
+    int64_t splits;
+    int64_t steps_done;
+};
+
+struct ssm_ctx {
+    int d = 1;
+    int prec = SSM_FP64;
+    bool fused = true;
+    bool has_pair = false;
+    Coef coef{};
+    std::vector<SysHost> sys;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int64_t P = 0;          // padded slots
+    int64_t nblk_tot = 0;
+    int64_t max_stride = 1;
+    int64_t tick = 0, ticks_total = 0;
+    int R = 4;
+    int64_t L = 0;          // sources per pair item
+    int64_t max_splits = 1;
+    // device buffers
+    void* X = nullptr;
+    void* Y = nullptr;
+    void* Ys = nullptr;
+    double* Bp = nullptr;
+    double* psumX = nullptr;
+    double* psumY = nullptr;
+    SysDev* dsys = nullptr;
+    PairItem* dpair = nullptr;
+    BlkItem* dblk = nullptr;
+    Flags* dflags = nullptr;
+    double* dstage = nullptr;  // staging for state copies / moments
+    int64_t bytes = 0;
+    // per phase (tick % max_stride) work lists: offsets into dpair / dblk
+    std::vector<int64_t> pair_off, pair_cnt, blk_off, blk_cnt;
+    std::vector<int64_t> all_blk_off;  // blocks of every system (init / set_state)
+    int64_t all_blk_cnt = 0;
+    // kernel timing: event pairs recorded around launches while profiling
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pair, ev_update;
+    std::vector<hipEvent_t> ev_pool;
+};
+
+static hipEvent_t take_event(ssm_ctx* c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static void recycle_events(ssm_ctx* c, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v)
+{
+    for (auto& p : v) {
+        if (p.first) c->ev_pool.push_back(p.first);
+        if (p.second) c->ev_pool.push_back(p.second);
+    }
+    v.clear();
+}
+
+// Sum of elapsed times of recorded event pairs (the stream must be synchronized).
+static double elapsed_ms(const std::vector<std::pair<hipEvent_t, hipEvent_t>>& v)
+{
+    double tot = 0.0;
+    for (auto& p : v) {
+        float ms = 0.0f;
+        if (p.first && p.second && hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) tot += ms;
+    }
+    return tot;
+}
+
+static size_t elt(int prec) { return prec == SSM_FP64 ? sizeof(double) : sizeof(float); }
+
+static ssm_status dev_alloc(ssm_ctx* c, void** p, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(SSM_ERR_OOM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    c->bytes += (int64_t)bytes;
+    return SSM_OK;
+}
+
+static void free_ctx(ssm_ctx* c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    void* bufs[] = {c->X, c->Y, c->Ys, c->Bp, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    recycle_events(c, c->ev_pair);
+    recycle_events(c, c->ev_update);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+static bool is_int_ratio(double a, double b, int64_t* out)
+{
+    const double q = a / b;
+    const double rq = std::nearbyint(q);
+    if (!(rq >= 1.0) || std::fabs(q - rq) > 1e-9 * rq || rq > 4e18) return false;
+    *out = (int64_t)rq;
+    return true;
+}
+
+// Work-list construction.  Pair items: for every system, tiles of 64 R targets
+// times source ranges of length L; ordered by decreasing cost (longest first),
+// and within a system source-range-major so that the wavefronts of one block
+// share their source stream.
+static void build_pair_items(const ssm_ctx* c, const std::vector<int>& systems,
+                             std::vector<PairItem>& out)
+{
+    std::vector<std::pair<int64_t, PairItem>> tmp;
+    const int64_t tile = 64 * (int64_t)c->R;
+    for (int s : systems) {
+        const SysHost& S = c->sys[s];
+        const int64_t tiles = (S.N + tile - 1) / tile;
+        for (int64_t q = 0; q < S.splits; ++q) {
+            const int64_t j0 = q * c->L;
+            const int64_t nj = std::min<int64_t>(c->L, S.N - j0);
+            for (int64_t t = 0; t < tiles; ++t) {
+                PairItem it{};
+                it.sys = s;
+                it.tgt0 = (int32_t)(t * tile);
+                it.src0 = (int32_t)j0;
+                it.nsrc = (int32_t)nj;
+                it.split = (int32_t)q;
+                tmp.push_back({nj * std::min<int64_t>(tile, S.N - t * tile), it});
+            }
+        }
+    }
+    std::stable_sort(tmp.begin(), tmp.end(),
+                     [](const std::pair<int64_t, PairItem>& a, const std::pair<int64_t, PairItem>& b) {
+                         return a.first > b.first;
+                     });
+    for (auto& p : tmp) out.push_back(p.second);
+}
+
+static void build_blk_items(const ssm_ctx* c, const std::vector<int>& systems, std::vector<BlkItem>& out)
+{
+    // largest systems first: their blocks also reduce the longest block-sum lists
+    std::vector<int> order(systems);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->sys[a].N > c->sys[b].N; });
+    for (int s : order)
+        for (int64_t b = 0; b < c->sys[s].nblk; ++b) out.push_back(BlkItem{s, (int32_t)b});
+}
+
+template <typename T>
+static ssm_status launch_tick(ssm_ctx* c)
+{
+    const int64_t ph = c->tick % c->max_stride;
+    const int64_t np = c->pair_cnt[ph], nb = c->blk_cnt[ph];
+    T* X = (T*)c->X;
+    T* Y = (T*)c->Y;
+    T* Ys = (T*)c->Ys;
+    const int d = c->d;
+    if (c->has_pair && np > 0) {
+        dim3 grid((unsigned)((np + kWaves - 1) / kWaves));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->profiling) {
+            e0 = take_event(c);
+            e1 = take_event(c);
+            if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
+        }
+        launch_pair<T>(d, c->R, c->prec == SSM_FP32_KAHAN, grid, c->stream, c->dpair + c->pair_off[ph],
+                       (int)np, c->dsys, Ys, c->P, c->Bp);
+        HIP_TRY(hipGetLastError());
+        if (c->profiling) {
+            if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
+            c->ev_pair.push_back({e0, e1});
+        }
+    }
+    if (nb > 0) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->profiling) {
+            e0 = take_event(c);
+            e1 = take_event(c);
+            if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
+        }
+        const BlkItem* items = c->dblk + c->blk_off[ph];
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_update<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream,
+                                             items, c->dsys, c->coef, c->P, c->tick, X, Y, Ys, c->Bp,
+                                             c->psumX, c->psumY, c->nblk_tot, c->dflags));
+        HIP_TRY(hipGetLastError());
+        if (!c->fused) {
+            SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_newton<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream,
+                                                 items, c->dsys, c->coef, c->P, c->tick, X, Y, Ys,
+                                                 c->psumX, c->psumY, c->nblk_tot, c->dflags));
+            HIP_TRY(hipGetLastError());
+        }
+        if (c->profiling) {
+            if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
+            c->ev_update.push_back({e0, e1});
+        }
+    }
+    for (auto& S : c->sys)
+        if (c->tick % S.stride == 0) S.steps_done++;
+    c->tick++;
+    return SSM_OK;
+}
+
+template <typename T>
+static ssm_status launch_init(ssm_ctx* c)
+{
+    const BlkItem* items = c->dblk + c->all_blk_off[0];
+    const unsigned nb = (unsigned)c->all_blk_cnt;
+    SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_init<T, D>), dim3(nb), dim3(kBlk), 0, c->stream, items, c->dsys,
+                                            c->coef, c->P, (T*)c->X, (T*)c->Y, (T*)c->Ys, c->psumX,
+                                            c->nblk_tot));
+    HIP_TRY(hipGetLastError());
+    SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<T, D>), dim3(nb), dim3(kBlk), 0, c->stream, items, c->dsys,
+                                            c->coef, c->P, (int64_t)-1, (const T*)c->X, (T*)c->Y, (T*)c->Ys,
+                                            c->psumX, c->psumY, c->nblk_tot, c->dflags));
+    HIP_TRY(hipGetLastError());
+    return SSM_OK;
+}
+
+static ssm_status validate(const ssm_config* cfg)
+{
+    if (!cfg) return fail(SSM_ERR_INVALID, "cfg is NULL");
+    if (cfg->d < 1 || cfg->d > SSM_MAX_D) return fail(SSM_ERR_INVALID, "d must be in 1..4");
+    if (cfg->n_sys < 1 || !cfg->N || !cfg->ens || !cfg->h) return fail(SSM_ERR_INVALID, "need n_sys >= 1 and N, ens, h arrays");
+    if (cfg->precision < SSM_FP64 || cfg->precision > SSM_FP32_KAHAN) return fail(SSM_ERR_INVALID, "unknown precision");
+    if (!(cfg->T > 0.0) || !std::isfinite(cfg->T)) return fail(SSM_ERR_INVALID, "T must be > 0");
+    if (!(cfg->h_fine > 0.0)) return fail(SSM_ERR_INVALID, "h_fine must be > 0");
+    if (!(cfg->v_a >= 0.0)) return fail(SSM_ERR_INVALID, "v_a must be >= 0 (one-sided Lipschitz v)");
+    if (!(cfg->v_kappa >= 0.0)) return fail(SSM_ERR_INVALID, "v_kappa must be >= 0");
+    if (cfg->b_g != 0.0 && !(cfg->b_ell > 0.0)) return fail(SSM_ERR_INVALID, "b_ell must be > 0");
+    if (cfg->targets_per_lane != 0 && cfg->targets_per_lane != 1 && cfg->targets_per_lane != 2 &&
+        cfg->targets_per_lane != 4 && cfg->targets_per_lane != 8)
+        return fail(SSM_ERR_INVALID, "targets_per_lane must be 0, 1, 2, 4 or 8");
+    if (cfg->sources_per_item != 0 && cfg->sources_per_item < 64)
+        return fail(SSM_ERR_INVALID, "sources_per_item must be 0 or >= 64");
+    for (int s = 0; s < cfg->n_sys; ++s) {
+        const double h = cfg->h[s];
+        if (cfg->N[s] < 1 || cfg->N[s] > 0x7fffffff - 1024) return fail(SSM_ERR_INVALID, "N out of range");
+        if (!(h > 0.0)) return fail(SSM_ERR_INVALID, "h must be > 0");
+        int64_t m, r;
+        if (!is_int_ratio(cfg->T, h, &m)) return fail(SSM_ERR_INVALID, "T / h must be an integer");
+        if (!is_int_ratio(h, cfg->h_fine, &r)) return fail(SSM_ERR_INVALID, "h / h_fine must be an integer >= 1");
+        if (r > 0x7fffffff) return fail(SSM_ERR_INVALID, "h / h_fine too large");
+        if (!(1.0 - h * cfg->v_rho > 0.0)) return fail(SSM_ERR_INVALID, "1 - h v_rho <= 0: the implicit step has no unique root (Lemma 4.1)");
+        if (!cfg->allow_unstable_h && !(1.0 - h * (2.0 * cfg->v_rho + 1.0) > 0.0))
+            return fail(SSM_ERR_INVALID, "h violates 1 - h (2 L_v + 1) > 0 (Theorem 2.6); set allow_unstable_h to override");
+    }
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
+{
+    if (!out) return fail(SSM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    ssm_status st = validate(cfg);
+    if (st != SSM_OK) return st;
+
+    ssm_ctx* c = new (std::nothrow) ssm_ctx();
+    if (!c) return fail(SSM_ERR_OOM, "host allocation failed");
+    c->d = cfg->d;
+    c->prec = cfg->precision;
+    c->fused = (cfg->v_kappa == 0.0 && cfg->v_lam == 0.0);
+    c->has_pair = cfg->b_g != 0.0;
+    Coef& cf = c->coef;
+    cf.v_rho = cfg->v_rho; cf.v_a = cfg->v_a; cf.v_kappa = cfg->v_kappa; cf.v_lam = cfg->v_lam;
+    cf.b_c0 = cfg->b_c0; cf.b_lam = cfg->b_lam;
+    for (int k = 0; k < kMaxD; ++k) {
+        const bool in = k < cfg->d;
+        cf.s0[k] = in ? cfg->s0[k] : 0.0; cf.s1[k] = in ? cfg->s1[k] : 0.0; cf.s2[k] = in ? cfg->s2[k] : 0.0;
+        cf.x0_mean[k] = in ? cfg->x0_mean[k] : 0.0; cf.x0_std[k] = in ? cfg->x0_std[k] : 0.0;
+    }
+    const double ell = c->has_pair ? cfg->b_ell : 1.0;
+    cf.coord_scale = std::sqrt(kLog2e / (2.0 * ell * ell));
+    cf.sqrt_hf = std::sqrt(cfg->h_fine);
+    cf.seed = cfg->seed;
+    cf.newton_max_iter = cfg->newton_max_iter > 0 ? cfg->newton_max_iter : 64;
+    cf.has_pair = c->has_pair ? 1 : 0;
+    cf.fused = c->fused ? 1 : 0;
+
+    // systems, strides, padding
+    double h_min = cfg->h[0];
+    for (int s = 1; s < cfg->n_sys; ++s) h_min = std::min(h_min, cfg->h[s]);
+    int64_t off = 0, blk = 0;
+    for (int s = 0; s < cfg->n_sys; ++s) {
+        SysHost S{};
+        S.N = cfg->N[s];
+        S.ens = cfg->ens[s];
+        S.h = cfg->h[s];
+        if (!is_int_ratio(S.h, h_min, &S.stride)) { free_ctx(c); return fail(SSM_ERR_INVALID, "every h must be an integer multiple of the smallest h"); }
+        is_int_ratio(S.h, cfg->h_fine, &S.r);
+        S.off = off;
+        S.nblk = (S.N + kBlk - 1) / kBlk;
+        S.blk0 = blk;
+        off += S.nblk * kBlk;
+        blk += S.nblk;
+        c->max_stride = std::max(c->max_stride, S.stride);
+        c->sys.push_back(S);
+    }
+    for (auto& S : c->sys)
+        if (c->max_stride % S.stride != 0) { free_ctx(c); return fail(SSM_ERR_INVALID, "every h / h_min must divide the largest such ratio"); }
+    if (c->max_stride > 4096) { free_ctx(c); return fail(SSM_ERR_INVALID, "h_max / h_min larger than 4096"); }
+    c->P = off;
+    c->nblk_tot = blk;
+    is_int_ratio(cfg->T, h_min, &c->ticks_total);
+
+    // pair tiling: R targets per lane, L sources per item
+    c->R = cfg->targets_per_lane > 0 ? cfg->targets_per_lane : 4;
+    if (cfg->sources_per_item > 0) {
+        c->L = cfg->sources_per_item;
+    } else {
+        // aim at ~8192 wavefronts per tick over all systems (8 per SIMD)
+        const int64_t tile = 64 * (int64_t)c->R;
+        double lane_pairs = 0.0;
+        for (auto& S : c->sys) lane_pairs += (double)((S.N + tile - 1) / tile) * tile * (double)S.N;
+        const double per_wave = lane_pairs / 8192.0 / (double)tile;
+        int64_t L = (int64_t)std::ceil(per_wave / 64.0) * 64;
+        c->L = std::max<int64_t>(L, 512);
+    }
+    c->max_splits = 1;
+    for (auto& S : c->sys) {
+        S.splits = (S.N + c->L - 1) / c->L;
+        c->max_splits = std::max(c->max_splits, S.splits);
+    }
+
+    // stream
+    if (cfg->stream) {
+        c->stream = (hipStream_t)cfg->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { free_ctx(c); return fail(SSM_ERR_HIP, "hipStreamCreate failed"); }
+        c->own_stream = true;
+    }
+
+    // work lists per phase
+    std::vector<PairItem> pairs;
+    std::vector<BlkItem> blks;
+    c->pair_off.resize(c->max_stride);
+    c->pair_cnt.resize(c->max_stride);
+    c->blk_off.resize(c->max_stride);
+    c->blk_cnt.resize(c->max_stride);
+    for (int64_t ph = 0; ph < c->max_stride; ++ph) {
+        std::vector<int> act;
+        for (int s = 0; s < (int)c->sys.size(); ++s)
+            if (ph % c->sys[s].stride == 0) act.push_back(s);
+        c->pair_off[ph] = (int64_t)pairs.size();
+        if (c->has_pair) build_pair_items(c, act, pairs);
+        c->pair_cnt[ph] = (int64_t)pairs.size() - c->pair_off[ph];
+        c->blk_off[ph] = (int64_t)blks.size();
+        build_blk_items(c, act, blks);
+        c->blk_cnt[ph] = (int64_t)blks.size() - c->blk_off[ph];
+    }
+    {
+        std::vector<int> all;
+        for (int s = 0; s < (int)c->sys.size(); ++s) all.push_back(s);
+        c->all_blk_off.push_back((int64_t)blks.size());
+        build_blk_items(c, all, blks);
+        c->all_blk_cnt = (int64_t)blks.size() - c->all_blk_off[0];
+    }
+
+    // device state
+    const size_t e = elt(c->prec);
+    const size_t field = (size_t)c->d * (size_t)c->P * e;
+    std::vector<SysDev> sd;
+    for (auto& S : c->sys) {
+        SysDev x{};
+        x.off = S.off;
+        x.N = (int32_t)S.N;
+        x.ens = S.ens;
+        x.stride = (int32_t)S.stride;
+        x.r = (int32_t)S.r;
+        x.blk0 = (int32_t)S.blk0;
+        x.nblk = (int32_t)S.nblk;
+        x.splits = (int32_t)S.splits;
+        x.h = S.h;
+        x.pair_scale = c->has_pair ? cfg->b_g / ((double)S.N * cf.coord_scale) : 0.0;
+        sd.push_back(x);
+    }
+#define ALLOC(ptr, bytes) do { st = dev_alloc(c, (void**)&(ptr), (bytes)); if (st != SSM_OK) { free_ctx(c); return st; } } while (0)
+    ALLOC(c->X, field);
+    ALLOC(c->Y, field);
+    ALLOC(c->Ys, field);
+    ALLOC(c->Bp, c->has_pair ? (size_t)c->max_splits * c->d * c->P * sizeof(double) : 0);
+    ALLOC(c->psumX, 2 * (size_t)(c->d + 1) * c->nblk_tot * sizeof(double));
+    ALLOC(c->psumY, 2 * (size_t)c->d * c->nblk_tot * sizeof(double));
+    ALLOC(c->dsys, sd.size() * sizeof(SysDev));
+    ALLOC(c->dpair, std::max<size_t>(pairs.size(), 1) * sizeof(PairItem));
+    ALLOC(c->dblk, blks.size() * sizeof(BlkItem));
+    ALLOC(c->dflags, sizeof(Flags));
+    int64_t maxN = 0;
+    for (auto& S : c->sys) maxN = std::max(maxN, S.N);
+    ALLOC(c->dstage, std::max<size_t>((size_t)c->d * maxN * sizeof(double), 2 * kMaxD * sizeof(double)));
+#undef ALLOC
+    hipError_t he = hipMemcpyAsync(c->dsys, sd.data(), sd.size() * sizeof(SysDev), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess && !pairs.empty()) he = hipMemcpyAsync(c->dpair, pairs.data(), pairs.size() * sizeof(PairItem), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(c->dblk, blks.data(), blks.size() * sizeof(BlkItem), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(c->dflags, 0, sizeof(Flags), c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);  // host vectors go out of scope
+    if (he != hipSuccess) { std::string m = hipGetErrorString(he); free_ctx(c); return fail(SSM_ERR_HIP, "upload: " + m); }
+
+    st = (c->prec == SSM_FP64) ? launch_init<double>(c) : launch_init<float>(c);
+    if (st != SSM_OK) { free_ctx(c); return st; }
+    *out = c;
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_step(ssm_ctx* c, int64_t n_ticks)
+{
+    if (!c) return fail(SSM_ERR_INVALID, "ctx is NULL");
+    if (n_ticks < 0) return fail(SSM_ERR_INVALID, "n_ticks < 0");
+    if (c->tick + n_ticks > c->ticks_total) return fail(SSM_ERR_STATE, "stepping past T");
+    for (int64_t t = 0; t < n_ticks; ++t) {
+        ssm_status st = (c->prec == SSM_FP64) ? launch_tick<double>(c) : launch_tick<float>(c);
+        if (st != SSM_OK) return st;
+    }
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_sync(ssm_ctx* c)
+{
+    if (!c) return fail(SSM_ERR_INVALID, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    Flags f{};
+    HIP_TRY(hipMemcpy(&f, c->dflags, sizeof(Flags), hipMemcpyDeviceToHost));
+    if (f.newton_fail) return fail(SSM_ERR_NEWTON, std::to_string(f.newton_fail) + " implicit solves did not converge");
+    if (f.nonfinite) return fail(SSM_ERR_NONFINITE, std::to_string(f.nonfinite) + " particles became non-finite");
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_run(ssm_ctx* c)
+{
+    if (!c) return fail(SSM_ERR_INVALID, "ctx is NULL");
+    ssm_status st = ssm_step(c, c->ticks_total - c->tick);
+    if (st != SSM_OK) return st;
+    return ssm_sync(c);
+}
+
+// ---------------------------------------------------------------------------
+// moments, state access, rMSE
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_moments(const T* __restrict__ X, int64_t P, int64_t off, int64_t N, int d, double* __restrict__ out)
+{
+    // one block of kBlk threads; fixed-order strided sums + tree
+    __shared__ double red[kBlk];
+    for (int k = 0; k < d; ++k) {
+        double s = 0.0;
+        for (int64_t i = threadIdx.x; i < N; i += kBlk) s += (double)X[k * P + off + i];
+        const double mean = block_sum(s, red) / (double)N;
+        double v = 0.0;
+        for (int64_t i = threadIdx.x; i < N; i += kBlk) {
+            const double c = (double)X[k * P + off + i] - mean;
+            v += c * c;
+        }
+        const double var = block_sum(v, red) / (double)N;
+        if (threadIdx.x == 0) {
+            out[k] = mean;
+            out[kMaxD + k] = var;
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_gather(const T* __restrict__ X, int64_t P, int64_t off, int64_t N, int d, double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int k = 0; k < d; ++k) out[(int64_t)k * N + i] = (double)X[k * P + off + i];
+}
+
+template <typename T>
+__global__ void k_scatter(const double* __restrict__ in, int64_t P, int64_t off, int64_t N, int d, T* __restrict__ X)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int k = 0; k < d; ++k) X[k * P + off + i] = (T)in[(int64_t)k * N + i];
+}
+
+template <typename TA, typename TB>
+__global__ void k_sqdiff(const TA* __restrict__ A, const TB* __restrict__ B, int64_t P, int64_t off, int64_t N,
+                         int d, double* __restrict__ out)
+{
+    __shared__ double red[kBlk];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += kBlk)
+        for (int k = 0; k < d; ++k) {
+            const double c = (double)A[k * P + off + i] - (double)B[k * P + off + i];
+            s += c * c;
+        }
+    const double tot = block_sum(s, red);
+    if (threadIdx.x == 0) out[0] = tot;
+}
+
+extern "C" ssm_status ssm_moments(ssm_ctx* c, int32_t sys, double* mean, double* var)
+{
+    if (!c || !mean || !var) return fail(SSM_ERR_INVALID, "NULL argument");
+    if (sys < 0 || sys >= (int32_t)c->sys.size()) return fail(SSM_ERR_INVALID, "sys out of range");
+    const SysHost& S = c->sys[sys];
+    if (c->prec == SSM_FP64)
+        hipLaunchKernelGGL(k_moments<double>, dim3(1), dim3(kBlk), 0, c->stream, (const double*)c->X, c->P, S.off, S.N, c->d, c->dstage);
+    else
+        hipLaunchKernelGGL(k_moments<float>, dim3(1), dim3(kBlk), 0, c->stream, (const float*)c->X, c->P, S.off, S.N, c->d, c->dstage);
+    HIP_TRY(hipGetLastError());
+    double buf[2 * kMaxD];
+    HIP_TRY(hipMemcpyAsync(buf, c->dstage, sizeof(buf), hipMemcpyDeviceToHost, c->stream));
+    ssm_status st = ssm_sync(c);
+    for (int k = 0; k < c->d; ++k) {
+        mean[k] = buf[k];
+        var[k] = buf[kMaxD + k];
+    }
+    return st;
+}
+
+extern "C" ssm_status ssm_get_state(ssm_ctx* c, int32_t sys, int32_t which, double* host, int64_t* step)
+{
+    if (!c || !host) return fail(SSM_ERR_INVALID, "NULL argument");
+    if (sys < 0 || sys >= (int32_t)c->sys.size()) return fail(SSM_ERR_INVALID, "sys out of range");
+    if (which != 0 && which != 1) return fail(SSM_ERR_INVALID, "which must be 0 (X) or 1 (Y*)");
+    const SysHost& S = c->sys[sys];
+    const void* src = which == 0 ? c->X : c->Y;
+    const unsigned g = (unsigned)((S.N + kBlk - 1) / kBlk);
+    if (c->prec == SSM_FP64)
+        hipLaunchKernelGGL(k_gather<double>, dim3(g), dim3(kBlk), 0, c->stream, (const double*)src, c->P, S.off, S.N, c->d, c->dstage);
+    else
+        hipLaunchKernelGGL(k_gather<float>, dim3(g), dim3(kBlk), 0, c->stream, (const float*)src, c->P, S.off, S.N, c->d, c->dstage);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(host, c->dstage, (size_t)c->d * S.N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    ssm_status st = ssm_sync(c);
+    if (step) *step = S.steps_done;
+    return st;
+}
+
+extern "C" ssm_status ssm_set_state(ssm_ctx* c, int32_t sys, const double* host)
+{
+    if (!c || !host) return fail(SSM_ERR_INVALID, "NULL argument");
+    if (sys < 0 || sys >= (int32_t)c->sys.size()) return fail(SSM_ERR_INVALID, "sys out of range");
+    if (!c->fused) return fail(SSM_ERR_STATE, "set_state needs v independent of mu^X");
+    const SysHost& S = c->sys[sys];
+    HIP_TRY(hipMemcpyAsync(c->dstage, host, (size_t)c->d * S.N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    const unsigned g = (unsigned)((S.N + kBlk - 1) / kBlk);
+    if (c->prec == SSM_FP64)
+        hipLaunchKernelGGL(k_scatter<double>, dim3(g), dim3(kBlk), 0, c->stream, c->dstage, c->P, S.off, S.N, c->d, (double*)c->X);
+    else
+        hipLaunchKernelGGL(k_scatter<float>, dim3(g), dim3(kBlk), 0, c->stream, c->dstage, c->P, S.off, S.N, c->d, (float*)c->X);
+    HIP_TRY(hipGetLastError());
+    // recompute Y* and its block sums for this system (parity of its step count)
+    std::vector<BlkItem> items;
+    for (int64_t b = 0; b < S.nblk; ++b) items.push_back(BlkItem{sys, (int32_t)b});
+    BlkItem* ditems = nullptr;
+    HIP_TRY(hipMalloc((void**)&ditems, items.size() * sizeof(BlkItem)));
+    hipError_t he = hipMemcpyAsync(ditems, items.data(), items.size() * sizeof(BlkItem), hipMemcpyHostToDevice, c->stream);
+    // k_newton derives the step count from the tick: tick = (steps_done - 1) * stride
+    const int64_t tick_arg = S.steps_done == 0 ? -1 : (S.steps_done - 1) * S.stride;
+    if (he == hipSuccess) {
+        if (c->prec == SSM_FP64) {
+            SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<double, D>), dim3((unsigned)items.size()), dim3(kBlk), 0, c->stream,
+                                                    ditems, c->dsys, c->coef, c->P, tick_arg, (const double*)c->X, (double*)c->Y,
+                                                    (double*)c->Ys, c->psumX, c->psumY, c->nblk_tot, c->dflags));
+        } else {
+            SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<float, D>), dim3((unsigned)items.size()), dim3(kBlk), 0, c->stream,
+                                                    ditems, c->dsys, c->coef, c->P, tick_arg, (const float*)c->X, (float*)c->Y,
+                                                    (float*)c->Ys, c->psumX, c->psumY, c->nblk_tot, c->dflags));
+        }
+        he = hipGetLastError();
+    }
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    (void)hipFree(ditems);
+    if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("set_state: ") + hipGetErrorString(he));
+    return ssm_sync(c);
+}
+
+extern "C" ssm_status ssm_rmse(ssm_ctx* a, ssm_ctx* b, double* per_sys, double* rmse)
+{
+    if (!a || !b || !rmse) return fail(SSM_ERR_INVALID, "NULL argument");
+    if (a->d != b->d || a->sys.size() != b->sys.size()) return fail(SSM_ERR_INVALID, "contexts differ in layout");
+    for (size_t s = 0; s < a->sys.size(); ++s)
+        if (a->sys[s].N != b->sys[s].N || a->sys[s].off != b->sys[s].off) return fail(SSM_ERR_INVALID, "contexts differ in layout");
+    ssm_status st = ssm_sync(b);
+    if (st != SSM_OK) return st;
+    const int n = (int)a->sys.size();
+    double* dout = nullptr;
+    HIP_TRY(hipMalloc((void**)&dout, n * sizeof(double)));
+    for (int s = 0; s < n; ++s) {
+        const SysHost& S = a->sys[s];
+        const bool fa = a->prec == SSM_FP64, fb = b->prec == SSM_FP64;
+        if (fa && fb) hipLaunchKernelGGL((k_sqdiff<double, double>), dim3(1), dim3(kBlk), 0, a->stream, (const double*)a->X, (const double*)b->X, a->P, S.off, S.N, a->d, dout + s);
+        else if (fa) hipLaunchKernelGGL((k_sqdiff<double, float>), dim3(1), dim3(kBlk), 0, a->stream, (const double*)a->X, (const float*)b->X, a->P, S.off, S.N, a->d, dout + s);
+        else if (fb) hipLaunchKernelGGL((k_sqdiff<float, double>), dim3(1), dim3(kBlk), 0, a->stream, (const float*)a->X, (const double*)b->X, a->P, S.off, S.N, a->d, dout + s);
+        else hipLaunchKernelGGL((k_sqdiff<float, float>), dim3(1), dim3(kBlk), 0, a->stream, (const float*)a->X, (const float*)b->X, a->P, S.off, S.N, a->d, dout + s);
+    }
+    std::vector<double> h(n);
+    hipError_t he = hipGetLastError();
+    if (he == hipSuccess) he = hipMemcpyAsync(h.data(), dout, n * sizeof(double), hipMemcpyDeviceToHost, a->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(a->stream);
+    (void)hipFree(dout);
+    if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("rmse: ") + hipGetErrorString(he));
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (int s = 0; s < n; ++s) {
+        if (per_sys) per_sys[s] = h[s];
+        tot += h[s];
+        cnt += a->sys[s].N;
+    }
+    *rmse = std::sqrt(tot / (double)cnt);
+    return ssm_sync(a);
+}
+
+extern "C" ssm_status ssm_info(ssm_ctx* c, ssm_info_t* out)
+{
+    if (!c || !out) return fail(SSM_ERR_INVALID, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    Flags f{};
+    HIP_TRY(hipMemcpy(&f, c->dflags, sizeof(Flags), hipMemcpyDeviceToHost));
+    out->tick = c->tick;
+    out->ticks_total = c->ticks_total;
+    out->newton_max_seen = f.newton_max;
+    out->newton_failures = f.newton_fail;
+    out->nonfinite = f.nonfinite;
+    out->n_pair_items = (int32_t)c->pair_cnt[0];
+    out->targets_per_lane = c->R;
+    out->sources_per_item = (int32_t)c->L;
+    out->device_bytes = c->bytes;
+    out->pair_launches = (int64_t)c->ev_pair.size();
+    out->pair_ms = elapsed_ms(c->ev_pair);
+    out->update_launches = (int64_t)c->ev_update.size();
+    out->update_ms = elapsed_ms(c->ev_update);
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_profile(ssm_ctx* c, int32_t enable)
+{
+    if (!c) return fail(SSM_ERR_INVALID, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    recycle_events(c, c->ev_pair);
+    recycle_events(c, c->ev_update);
+    c->profiling = enable != 0;
+    return SSM_OK;
+}
+
+extern "C" void ssm_destroy(ssm_ctx* c) { free_ctx(c); }
+
+// ---------------------------------------------------------------------------
+// kernel-level entry points
+// ---------------------------------------------------------------------------
+static const int kPairR = 4;
+
+static void pair_plan(int64_t N, int64_t* L, int64_t* splits)
+{
+    const int64_t tile = 64 * kPairR;
+    const double lane_pairs = (double)((N + tile - 1) / tile) * tile * (double)N;
+    int64_t l = (int64_t)std::ceil(lane_pairs / 8192.0 / (double)tile / 64.0) * 64;
+    *L = std::max<int64_t>(l, 512);
+    *splits = (N + *L - 1) / *L;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" size_t ssm_pair_workspace_bytes(int32_t d, int64_t N, int32_t precision)
+{
+    if (d < 1 || d > SSM_MAX_D || N < 1) return 0;
+    int64_t L, splits;
+    pair_plan(N, &L, &splits);
+    const int64_t tile = 64 * kPairR;
+    const int64_t items = splits * ((N + tile - 1) / tile);
+    return align256(sizeof(SysDev)) + align256(items * sizeof(PairItem)) +
+           align256((size_t)d * N * elt(precision)) + align256((size_t)splits * d * N * sizeof(double));
+}
+
+extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, const void* Y, double ell,
+                                   double* K, void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (d < 1 || d > SSM_MAX_D) return fail(SSM_ERR_INVALID, "d must be in 1..4");
+    if (N < 1 || N > 0x7fffffff - 1024) return fail(SSM_ERR_INVALID, "N out of range");
+    if (precision < SSM_FP64 || precision > SSM_FP32_KAHAN) return fail(SSM_ERR_INVALID, "unknown precision");
+    if (!Y || !K || !workspace) return fail(SSM_ERR_INVALID, "NULL pointer");
+    if (!(ell > 0.0)) return fail(SSM_ERR_INVALID, "ell must be > 0");
+    const size_t need = ssm_pair_workspace_bytes(d, N, precision);
+    if (workspace_bytes < need) return fail(SSM_ERR_INVALID, "workspace too small: need " + std::to_string(need));
+    hipStream_t st = (hipStream_t)stream;
+    int64_t L, splits;
+    pair_plan(N, &L, &splits);
+    const int64_t tile = 64 * kPairR;
+    // plan on the host
+    SysDev S{};
+    S.off = 0; S.N = (int32_t)N; S.stride = 1; S.r = 1; S.nblk = (int32_t)((N + kBlk - 1) / kBlk); S.splits = (int32_t)splits;
+    std::vector<PairItem> items;
+    for (int64_t q = 0; q < splits; ++q)
+        for (int64_t t = 0; t < (N + tile - 1) / tile; ++t) {
+            PairItem it{};
+            it.sys = 0; it.tgt0 = (int32_t)(t * tile); it.src0 = (int32_t)(q * L);
+            it.nsrc = (int32_t)std::min<int64_t>(L, N - q * L); it.split = (int32_t)q;
+            items.push_back(it);
+        }
+    char* w = (char*)workspace;
+    SysDev* dS = (SysDev*)w; w += align256(sizeof(SysDev));
+    PairItem* dI = (PairItem*)w; w += align256(items.size() * sizeof(PairItem));
+    void* dYs = (void*)w; w += align256((size_t)d * N * elt(precision));
+    double* dBp = (double*)w;
+    HIP_TRY(hipMemcpyAsync(dS, &S, sizeof(S), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dI, items.data(), items.size() * sizeof(PairItem), hipMemcpyHostToDevice, st));
+    const double c = std::sqrt(kLog2e / (2.0 * ell * ell));
+    const int64_t n = (int64_t)d * N;
+    const dim3 g1((unsigned)((n + 255) / 256));
+    const dim3 gp((unsigned)((items.size() + kWaves - 1) / kWaves));
+    if (precision == SSM_FP64) {
+        hipLaunchKernelGGL(k_scale_copy<double>, g1, dim3(256), 0, st, (const double*)Y, (double*)dYs, n, c);
+        launch_pair<double>(d, kPairR, false, gp, st, dI, (int)items.size(), dS, (const double*)dYs, N, dBp);
+    } else {
+        hipLaunchKernelGGL(k_scale_copy<float>, g1, dim3(256), 0, st, (const float*)Y, (float*)dYs, n, c);
+        launch_pair<float>(d, kPairR, precision == SSM_FP32_KAHAN, gp, st, dI, (int)items.size(), dS, (const float*)dYs, N, dBp);
+    }
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, dBp, (int)splits, d, N, N,
+                       1.0 / ((double)N * c), K);
+    HIP_TRY(hipGetLastError());
+    // the host-side item list must outlive the asynchronous copy
+    HIP_TRY(hipStreamSynchronize(st));
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_implicit_solve(int32_t d, int64_t N, const double* X, double h, double v_rho,
+                                         double v_a, double v_kappa, double v_lam, const double* xbar,
+                                         double m2, int32_t max_iter, double* Y, int32_t* iters, void* stream)
+{
+    if (d < 1 || d > SSM_MAX_D || N < 1) return fail(SSM_ERR_INVALID, "bad d or N");
+    if (!X || !Y) return fail(SSM_ERR_INVALID, "NULL pointer");
+    if (!(v_a >= 0.0) || !(v_kappa >= 0.0)) return fail(SSM_ERR_INVALID, "v_a, v_kappa must be >= 0");
+    if (!(1.0 - h * (v_rho - v_kappa * m2) > 0.0)) return fail(SSM_ERR_INVALID, "no unique implicit root (1 - h L_v <= 0)");
+    double xb[kMaxD] = {0.0, 0.0, 0.0, 0.0};
+    if (xbar)
+        for (int k = 0; k < d; ++k) xb[k] = xbar[k];
+    const dim3 g((unsigned)((N + 255) / 256));
+    hipStream_t st = (hipStream_t)stream;
+    const int mi = max_iter > 0 ? max_iter : 64;
+    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_implicit_plain<D>), g, dim3(256), 0, st, N, X, h, v_rho, v_a, v_kappa, v_lam,
+                                         xb[0], xb[1], xb[2], xb[3], m2, mi, Y, iters));
+    HIP_TRY(hipGetLastError());
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_brownian(int32_t d, int64_t N, uint64_t seed, int32_t ens, int64_t n0, int32_t r,
+                                   double h_fine, double* dW, void* stream)
+{
+    if (d < 1 || d > SSM_MAX_D || N < 1 || r < 1 || n0 < 0 || !dW || !(h_fine > 0.0))
+        return fail(SSM_ERR_INVALID, "bad argument");
+    hipLaunchKernelGGL(k_brownian, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, (hipStream_t)stream, d, N, seed, ens,
+                       n0, r, std::sqrt(h_fine), dW);
+    HIP_TRY(hipGetLastError());
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_philox_blocks(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1,
+                                        int64_t count, uint64_t* out, void* stream)
+{
+    if (count < 1 || !out) return fail(SSM_ERR_INVALID, "bad argument");
+    hipLaunchKernelGGL(k_philox, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, (hipStream_t)stream, c0, c1, c2, c3,
+                       k0, k1, count, out);
+    HIP_TRY(hipGetLastError());
+    return SSM_OK;
+}

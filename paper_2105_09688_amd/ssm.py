@@ -1,0 +1,190 @@
+"""Python front end of libssm: the split-step method (SSM) of arXiv:2105.09688
+(Section 2.2, eqs. (2.3)-(2.4)) for N-particle McKean-Vlasov systems on one
+MI355X.  Thin ctypes marshalling; PyTorch provides device memory and streams."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import SSM_FP32, SSM_FP32_KAHAN, SSM_FP64, check
+
+PRECISIONS = {"fp64": SSM_FP64, "fp32": SSM_FP32, "fp32_kahan": SSM_FP32_KAHAN}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class SSM:
+    """One context: n systems advanced together (see include/ssm.h).
+
+    ``workload`` is the dict of ``paper_2105_09688_amd.workloads``."""
+
+    def __init__(self, workload: dict, precision: str = "fp64", stream=None,
+                 targets_per_lane: int = 0, sources_per_item: int = 0):
+        lib = _lib.load()
+        w = workload
+        d = int(w["d"])
+        systems = w["systems"]
+        self.d = d
+        self.N = [int(s[0]) for s in systems]
+        self._Ns = (C.c_int64 * len(systems))(*self.N)
+        self._ens = (C.c_int32 * len(systems))(*[int(s[1]) for s in systems])
+        self._hs = (C.c_double * len(systems))(*[float(s[2]) for s in systems])
+        c = _lib.Config()
+        c.d, c.n_sys = d, len(systems)
+        c.N, c.ens, c.h = self._Ns, self._ens, self._hs
+        c.T, c.h_fine, c.seed = float(w["T"]), float(w["h_fine"]), int(w["seed"])
+        c.precision = PRECISIONS[precision]
+        v, b, s = w["v"], w["b"], w["sigma"]
+        c.v_rho, c.v_a = float(v.get("rho", 0.0)), float(v.get("a", 0.0))
+        c.v_kappa, c.v_lam = float(v.get("kappa", 0.0)), float(v.get("lam", 0.0))
+        c.b_c0, c.b_lam = float(b.get("c0", 0.0)), float(b.get("lam", 0.0))
+        c.b_g, c.b_ell = float(b.get("g", 0.0)), float(b.get("ell", 1.0))
+        for k in range(d):
+            c.s0[k], c.s1[k], c.s2[k] = float(s["s0"][k]), float(s["s1"][k]), float(s["s2"][k])
+            c.x0_mean[k], c.x0_std[k] = float(w["x0_mean"][k]), float(w["x0_std"][k])
+        c.newton_max_iter = int(w.get("newton_max_iter", 0))
+        c.allow_unstable_h = int(bool(w.get("allow_unstable_h", False)))
+        c.stream = _stream_ptr(stream)
+        c.targets_per_lane = int(targets_per_lane)
+        c.sources_per_item = int(sources_per_item)
+        self._cfg = c
+        h = C.c_void_p()
+        check(lib.ssm_init(C.byref(c), C.byref(h)))
+        self._h = h
+        self.precision = precision
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().ssm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- stepping ----------------------------------------------------------
+    def step(self, n_ticks: int = 1):
+        check(_lib.load().ssm_step(self._h, int(n_ticks)))
+
+    def run(self):
+        check(_lib.load().ssm_run(self._h))
+
+    def sync(self):
+        check(_lib.load().ssm_sync(self._h))
+
+    # -- outputs -----------------------------------------------------------
+    def moments(self, sys: int = 0):
+        m = np.zeros(self.d)
+        v = np.zeros(self.d)
+        check(_lib.load().ssm_moments(self._h, sys, m.ctypes.data_as(C.POINTER(C.c_double)),
+                                      v.ctypes.data_as(C.POINTER(C.c_double))))
+        return m, v
+
+    def state(self, sys: int = 0, which: str = "x"):
+        out = np.zeros((self.d, self.N[sys]))
+        step = C.c_int64()
+        check(_lib.load().ssm_get_state(self._h, sys, 0 if which == "x" else 1,
+                                        out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(step)))
+        return out
+
+    def states(self, which: str = "x"):
+        return [self.state(s, which) for s in range(len(self.N))]
+
+    def set_state(self, sys: int, X) -> None:
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(self.d, self.N[sys])
+        check(_lib.load().ssm_set_state(self._h, sys, X.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def rmse(self, other: "SSM"):
+        per = np.zeros(len(self.N))
+        r = C.c_double()
+        check(_lib.load().ssm_rmse(self._h, other._h, per.ctypes.data_as(C.POINTER(C.c_double)), C.byref(r)))
+        return r.value, per
+
+    def profile(self, enable: bool = True) -> None:
+        check(_lib.load().ssm_profile(self._h, 1 if enable else 0))
+
+    def info(self) -> dict:
+        i = _lib.Info()
+        check(_lib.load().ssm_info(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in i._fields_}
+
+
+# -------------------------------------------------------------------------- kernel-level calls
+def _cur_stream():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def pair_sum(Y, ell: float, precision: str = "fp64"):
+    """K[k][i] = (1/N) sum_j (Y_k^j - Y_k^i) exp(-|Y^i - Y^j|^2/(2 ell^2)) for a device tensor Y [d][N]
+    (float64 for 'fp64', float32 otherwise).  Returns a float64 device tensor [d][N]."""
+    torch = _torch()
+    lib = _lib.load()
+    prec = PRECISIONS[precision]
+    want = torch.float64 if prec == SSM_FP64 else torch.float32
+    if Y.dtype != want or not Y.is_cuda or Y.dim() != 2:
+        raise ValueError(f"Y must be a 2-D CUDA tensor of {want}")
+    Y = Y.contiguous()
+    d, N = Y.shape
+    K = torch.empty((d, N), dtype=torch.float64, device=Y.device)
+    nbytes = lib.ssm_pair_workspace_bytes(d, N, prec)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=Y.device)
+    check(lib.ssm_pair_sum(d, N, prec, Y.data_ptr(), float(ell), K.data_ptr(), ws.data_ptr(),
+                           nbytes, _cur_stream()))
+    return K
+
+
+def implicit_solve(X, h: float, rho=0.0, a=1.0, kappa=0.0, lam=0.0, xbar=None, m2=0.0, max_iter=64):
+    """Y = F_h(X) of (2.3) for a float64 device tensor X [d][N]; returns (Y, iterations)."""
+    torch = _torch()
+    lib = _lib.load()
+    if X.dtype != torch.float64 or not X.is_cuda or X.dim() != 2:
+        raise ValueError("X must be a 2-D float64 CUDA tensor")
+    X = X.contiguous()
+    d, N = X.shape
+    Y = torch.empty_like(X)
+    it = torch.empty(N, dtype=torch.int32, device=X.device)
+    xb = np.zeros(d) if xbar is None else np.ascontiguousarray(xbar, dtype=np.float64)
+    check(lib.ssm_implicit_solve(d, N, X.data_ptr(), h, rho, a, kappa, lam,
+                                 xb.ctypes.data_as(C.POINTER(C.c_double)), m2, max_iter,
+                                 Y.data_ptr(), it.data_ptr(), _cur_stream()))
+    return Y, it
+
+
+def brownian(d: int, N: int, seed: int, ens: int, n0: int, r: int, h_fine: float, device="cuda"):
+    """dW[k][i] = sqrt(h_fine) sum_{m<r} Z(0, i, n0+m, ens)_k as a float64 device tensor."""
+    torch = _torch()
+    dW = torch.empty((d, N), dtype=torch.float64, device=device)
+    check(_lib.load().ssm_brownian(d, N, seed, ens, n0, r, h_fine, dW.data_ptr(), _cur_stream()))
+    return dW
+
+
+def philox_blocks(ctr, key, count: int, device="cuda"):
+    """Philox4x64-10 blocks of counters (ctr[0]+q, ctr[1], ctr[2], ctr[3]), q < count; int64 view [count, 4]."""
+    torch = _torch()
+    out = torch.empty((count, 4), dtype=torch.int64, device=device)
+    c = [int(v) & (2 ** 64 - 1) for v in ctr]
+    k = [int(v) & (2 ** 64 - 1) for v in key]
+    check(_lib.load().ssm_philox_blocks(c[0], c[1], c[2], c[3], k[0], k[1], count, out.data_ptr(), _cur_stream()))
+    return out

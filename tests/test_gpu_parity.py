@@ -1,0 +1,319 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (pathwise, on the same Philox stream): max_i |x_gpu - x_ref| /
+max(1, |x_ref|) <= 1e-10 for FP64 and <= 1e-4 for the FP32 modes.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_09688_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 1e-4
+
+
+def _say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return torch
+
+
+def _err(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.max(np.abs(got - ref) / np.maximum(1.0, np.abs(ref)))) if ref.size else 0.0
+
+
+def _ssm(w, precision="fp64", **kw):
+    from paper_2105_09688_amd.ssm import SSM
+    return SSM(w, precision=precision, **kw)
+
+
+# --------------------------------------------------------------------------- random numbers
+def test_philox_blocks_bitwise(torch_cuda):
+    from paper_2105_09688_amd.ssm import philox_blocks
+    rng = np.random.default_rng(1)
+    for _ in range(4):
+        ctr = [int(v) for v in rng.integers(0, 2 ** 63, 4)]
+        key = [int(v) for v in rng.integers(0, 2 ** 63, 2)]
+        _say(f"philox ctr={ctr} key={key}")
+        got = philox_blocks(ctr, key, 257).cpu().numpy().view(np.uint64)
+        for q in range(0, 257, 16):
+            ref = oracle.philox4x64_10([ctr[0] + q, ctr[1], ctr[2], ctr[3]], key)
+            assert np.array_equal(got[q], ref), q
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_brownian_increments_match_oracle(torch_cuda, d):
+    from paper_2105_09688_amd.ssm import brownian
+    N, seed, ens, n0, r, hf = 300, 7, 5, 17, 3, 2.0 ** -10
+    _say(f"brownian d={d}")
+    got = brownian(d, N, seed, ens, n0, r, hf).cpu().numpy()
+    ref = np.zeros((d, N))
+    for i in range(N):
+        zs = sum(oracle.normals4(seed, 0, i, n0 + m, ens) for m in range(r))
+        ref[:, i] = math.sqrt(hf) * zs[:d]
+    assert np.max(np.abs(got - ref)) <= 1e-13
+
+
+# --------------------------------------------------------------------------- implicit step (2.3)
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_implicit_solve_matches_oracle(torch_cuda, d):
+    from paper_2105_09688_amd.ssm import implicit_solve
+    torch = torch_cuda
+    rng = np.random.default_rng(d)
+    N = 2000
+    X = rng.normal(size=(d, N)) * 4.0
+    X[:, 0] = 0.0
+    X[:, 1] = 1e-300
+    for (h, rho, a, kappa, lam) in [(2.0 ** -4, 0.0, 1.0, 0.0, 0.0), (2.0 ** -10, 0.0, 1.0, 0.0, 0.0),
+                                    (0.05, 2.0, 0.25, 0.0, 0.0), (0.1, -1.0, 0.0, 0.0, 0.0),
+                                    (0.01, 0.5, 1.0, 0.3, 0.7)]:
+        xbar = rng.normal(size=d)
+        m2 = 1.7
+        _say(f"implicit d={d} h={h} rho={rho} a={a} kappa={kappa} lam={lam}")
+        Y, it = implicit_solve(torch.tensor(X, device="cuda"), h, rho, a, kappa, lam, xbar, m2)
+        Y = Y.cpu().numpy()
+        it = it.cpu().numpy()
+        assert np.all(it >= 0)
+        ref = np.stack([oracle.implicit(X[:, i], h, rho, a, kappa, lam, xbar, m2)[0] for i in range(N)], axis=1)
+        assert np.max(np.abs(Y - ref) / np.maximum(1e-300, np.abs(ref)).clip(min=1.0)) <= 1e-14
+
+
+# --------------------------------------------------------------------------- pairwise sums (2.4)
+@pytest.mark.parametrize("d,ell", [(1, 1.0), (2, 1.0), (3, 0.5)])
+@pytest.mark.parametrize("N", [1, 2, 63, 64, 65, 257, 1000, 4099])
+def test_pair_sum_matches_oracle(torch_cuda, d, ell, N):
+    from paper_2105_09688_amd.ssm import pair_sum
+    torch = torch_cuda
+    Y = W.random_cloud(d, N, seed=N + 10 * d, loc=0.3, scale=1.5)
+    ref = oracle.pair_sum(Y, ell)
+    _say(f"pair_sum fp64 d={d} N={N}")
+    got = pair_sum(torch.tensor(Y, device="cuda"), ell, "fp64").cpu().numpy()
+    assert _err(got, ref) <= 1e-12
+    for prec in ("fp32", "fp32_kahan"):
+        _say(f"pair_sum {prec} d={d} N={N}")
+        Yf = torch.tensor(Y, device="cuda", dtype=torch.float32)
+        got = pair_sum(Yf, ell, prec).cpu().numpy()
+        ref32 = oracle.pair_sum(Yf.cpu().numpy().astype(np.float64), ell)  # same rounded inputs
+        assert _err(got, ref32) <= 2e-6, prec
+
+
+def test_pair_sum_full_size_sampled_and_zero_net_force(torch_cuda):
+    """N = 2^16 (the single-GPU d=1 size) and N = 2^18 at d=3: sampled targets
+    against the oracle, plus sum_i K^i = 0 (odd kernel) over all targets."""
+    from paper_2105_09688_amd.ssm import pair_sum
+    torch = torch_cuda
+    rng = np.random.default_rng(3)
+    for d, N, ell in [(1, 2 ** 16, 1.0), (3, 2 ** 18, 0.5)]:
+        Y = W.random_cloud(d, N, seed=77 + d)
+        idx = np.sort(rng.choice(N, 96, replace=False))
+        idx[-1] = N - 1
+        ref = oracle.pair_sum_at(Y, ell, idx)
+        for prec, tol in (("fp64", 1e-12), ("fp32_kahan", 2e-6), ("fp32", 2e-6)):
+            _say(f"pair_sum full size d={d} N={N} {prec}")
+            dt = torch.float64 if prec == "fp64" else torch.float32
+            Yd = torch.tensor(Y, device="cuda", dtype=dt)
+            K = pair_sum(Yd, ell, prec).cpu().numpy()
+            r = ref if prec == "fp64" else oracle.pair_sum_at(Yd.cpu().numpy().astype(np.float64), ell, idx)
+            assert _err(K[:, idx], r) <= tol, prec
+            net = np.abs(K.sum(axis=1))
+            assert np.all(net <= (1e-9 if prec == "fp64" else 1e-3) * np.abs(K).sum(axis=1)), (prec, net)
+
+
+# --------------------------------------------------------------------------- whole runs
+@pytest.fixture(scope="module")
+def c0_oracle():
+    w = W.small_parity()
+    _say("oracle run: 10 x 1000 particles, 256 steps")
+    return w, oracle.run(w)
+
+
+def test_run_small_parity_fp64(torch_cuda, c0_oracle):
+    w, ref = c0_oracle
+    _say("gpu fp64 run 10 x 1000 x 256 steps")
+    with _ssm(w, "fp64") as s:
+        s.run()
+        got = s.states()
+        for e in range(len(ref)):
+            assert _err(got[e], ref[e]) <= FP64_TOL, e
+            m, v = s.moments(e)
+            mr, vr = oracle.moments(ref[e])
+            assert np.allclose(m, mr, rtol=0, atol=1e-10) and np.allclose(v, vr, rtol=0, atol=1e-10)
+        info = s.info()
+        assert info["newton_failures"] == 0 and info["nonfinite"] == 0 and info["tick"] == 256
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_kahan"])
+def test_run_small_parity_fp32(torch_cuda, c0_oracle, precision):
+    w, ref = c0_oracle
+    _say(f"gpu {precision} run 10 x 1000 x 256 steps")
+    with _ssm(w, precision) as s:
+        s.run()
+        got = s.states()
+    errs = [_err(g, r) for g, r in zip(got, ref)]
+    _say(f"{precision} max pathwise error {max(errs):.3e}")
+    assert max(errs) <= FP32_TOL
+
+
+def test_stepwise_parity_and_implicit_state(torch_cuda):
+    """Step by step on one system: X_n and Y*_n = F_h(X_n) against oracle steps
+    from the GPU's own X_n (isolates one step's error)."""
+    w = W.small_parity(n_ens=1, N=777, h=2.0 ** -6, h_fine=2.0 ** -8)
+    h = 2.0 ** -6
+    with _ssm(w, "fp64") as s:
+        X = oracle.init_state(w, 0, 777)
+        assert _err(s.state(0, "x"), X) <= 1e-15
+        for n in range(8):
+            _say(f"stepwise n={n}")
+            Xg = s.state(0, "x")
+            Yg = s.state(0, "y")
+            Xn_ref, Y_ref = oracle.step(w, 0, h, n, Xg)
+            assert _err(Yg, Y_ref) <= 1e-14
+            s.step(1)
+            assert _err(s.state(0, "x"), Xn_ref) <= 1e-13
+
+
+def test_multilevel_batched_equals_separate_runs(torch_cuda):
+    """Uneven ensembles at several step sizes in one context == each system run
+    alone by the oracle (same Brownian paths per ensemble)."""
+    sizes = [300, 1000, 65, 1]
+    w = W.batched(n_ens=4, levels=(4, 5, 6), h_fine=2.0 ** -8, sizes=sizes)
+    w["T"] = 0.25
+    _say("oracle: 12 systems")
+    ref = oracle.run(w)
+    for prec, tol in (("fp64", FP64_TOL), ("fp32_kahan", FP32_TOL)):
+        _say(f"gpu batched {prec}")
+        with _ssm(w, prec) as s:
+            s.run()
+            got = s.states()
+        for k, (g, r) in enumerate(zip(got, ref)):
+            assert _err(g, r) <= tol, (prec, k, w["systems"][k])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32_kahan", FP32_TOL), ("fp32", FP32_TOL)])
+def test_run_d3_and_d2(torch_cuda, precision, tol):
+    for w in (W.precision_d3(N=700), W.surrogate_d2(N=900, h=2.0 ** -9, h_fine=2.0 ** -10)):
+        w["T"] = 2.0 ** -4
+        _say(f"d={w['d']} {precision}")
+        ref = oracle.run(w)[0]
+        with _ssm(w, precision) as s:
+            s.run()
+            got = s.state(0)
+        assert _err(got, ref) <= tol
+
+
+def test_measure_dependent_v_unfused_path(torch_cuda):
+    """v depends on mu^X (mean and second moment): the implicit solve runs in
+    its own kernel after the moments of the new cloud are reduced."""
+    w = W.small_parity(n_ens=2, N=513, h=2.0 ** -6, h_fine=2.0 ** -6)
+    w["T"] = 0.25
+    w["v"] = dict(rho=-1.0, a=0.5, kappa=0.3, lam=0.5)
+    w["b"] = dict(c0=0.2, lam=0.4, g=0.7, ell=0.8)
+    w["sigma"] = dict(s0=[0.1], s1=[0.3], s2=[0.2])
+    ref = oracle.run(w)
+    _say("gpu unfused fp64")
+    with _ssm(w, "fp64") as s:
+        s.run()
+        got = s.states()
+    for g, r in zip(got, ref):
+        assert _err(g, r) <= FP64_TOL
+
+
+def test_linear_ou_without_pair_term(torch_cuda):
+    w = W.ou(rho=-0.7, lam=0.4, eta=0.5, x0=1.0, x0_std=0.2, N=4097, h=2.0 ** -7, n_ens=2, T=0.5)
+    ref = oracle.run(w)
+    with _ssm(w, "fp64") as s:
+        s.run()
+        for e in range(2):
+            assert _err(s.state(e), ref[e]) <= FP64_TOL
+
+
+def test_single_particle_and_ragged_sizes(torch_cuda):
+    for N in (1, 2, 255, 257):
+        w = W.small_parity(n_ens=1, N=N, h=2.0 ** -5, h_fine=2.0 ** -5)
+        w["T"] = 2.0 ** -3
+        ref = oracle.run(w)[0]
+        with _ssm(w, "fp64") as s:
+            s.run()
+            assert _err(s.state(0), ref) <= FP64_TOL, N
+
+
+def test_determinism_bitwise(torch_cuda):
+    w = W.small_parity(n_ens=3, N=1500)
+    w["T"] = 2.0 ** -4
+    outs = []
+    for _ in range(2):
+        with _ssm(w, "fp32_kahan") as s:
+            s.run()
+            outs.append(s.states())
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_tiling_does_not_change_results_beyond_rounding(torch_cuda):
+    w = W.small_parity(n_ens=2, N=3000)
+    w["T"] = 2.0 ** -5
+    base = None
+    for R, L in ((1, 64), (2, 512), (4, 0), (8, 1000)):
+        _say(f"tiling R={R} L={L}")
+        with _ssm(w, "fp64", targets_per_lane=R, sources_per_item=L) as s:
+            s.run()
+            got = s.states()
+        if base is None:
+            base = got
+        for g, b in zip(got, base):
+            assert _err(g, b) <= 1e-12
+
+
+def test_rmse_matches_oracle_within_5_percent(torch_cuda):
+    """The strong error of a run at h against its proxy at h_ref (Section 3),
+    GPU vs oracle: the 'fixed rMSE' criterion (within 5 %)."""
+    base = W.small_parity(n_ens=4, N=500, h_fine=2.0 ** -12)
+    ref_w = W.with_h(base, 2.0 ** -12)
+    _say("oracle reference run at 2^-12")
+    ref = oracle.run(ref_w)
+    for h in (2.0 ** -6, 2.0 ** -8):
+        oh = oracle.run(W.with_h(base, h))
+        r_or = oracle.strong_error(oh, ref)
+        for prec in ("fp64", "fp32_kahan"):
+            _say(f"rmse h={h} {prec}")
+            with _ssm(W.with_h(base, h), prec) as a, _ssm(ref_w, prec) as b:
+                a.run()
+                b.run()
+                r_gpu, per = a.rmse(b)
+                sa, sb = a.states(), b.states()
+            # the device reduction equals the host formula on the same states
+            assert r_gpu == pytest.approx(oracle.strong_error(sa, sb), rel=1e-12)
+            assert abs(r_gpu - r_or) <= 0.05 * r_or, (prec, h, r_gpu, r_or)
+            if prec == "fp64":
+                assert abs(r_gpu - r_or) <= 1e-8 * r_or
+
+
+def test_errors_are_reported(torch_cuda):
+    from paper_2105_09688_amd import SSMError
+    w = W.small_parity(n_ens=1, N=100)
+    w["T"] = 2.0 ** -6
+    with _ssm(w, "fp64") as s:
+        s.run()
+        with pytest.raises(SSMError) as e:
+            s.step(1)
+        assert e.value.status == -6
+    w["newton_max_iter"] = 1
+    w["x0_std"] = [20.0]
+    with pytest.raises(SSMError) as e:
+        with _ssm(w, "fp64") as s:
+            s.run()
+    assert e.value.status == -2
