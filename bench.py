@@ -29,6 +29,28 @@ def flops_per_pair(d: int) -> int:
     return 5 * d + 1
 
 
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ssm_kernels.hpp", "ssm_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2105_09688_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(key: str):
+    """HBM bytes per launch of the pair kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE runs, if the kernel sources are unchanged since."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+            rec = json.load(fh).get(key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(w, budget_s: float):
     """The FP64 oracle on this host's cores, on a bounded sample of the same
     workload: whole time steps of the same system, as many as fit in the budget."""
@@ -60,6 +82,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, one plain device copy of this many MiB (calibrates byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -131,7 +155,8 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": recorded_traffic(f"k_pair {args.precision} d={d} N={N} R={info['targets_per_lane']} "
+                                        f"L={info['sources_per_item']}"),
             "flop_per_pair": flops_per_pair(d),
             "pairs_per_launch": pairs,
             "avg_launch_ms": pair_avg_s * 1e3,
@@ -150,6 +175,14 @@ def main():
         out["check"] = {"max_pathwise_err_vs_fp64": float(np.max(np.abs(a - b) / np.maximum(1.0, np.abs(b)))),
                         "steps": args.steps}
     s.close()
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = {"read": 4 * n, "write": 4 * n}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)
