@@ -72,13 +72,118 @@ def cpu_baseline(w, budget_s: float):
             "sample": f"{steps} full time steps of the same system (N={N}, d={w['d']}), FP64, from X_0"}
 
 
+def timed_run(SSM, w, precision, stream, steps=None, profile=True, **kw):
+    """Fresh context, then `steps` ticks (default: to T) between HIP events on its stream."""
+    import torch
+    s = SSM(w, precision=precision, stream=stream, **kw)
+    s.sync()
+    if profile:
+        s.profile(True)
+    info0 = s.info()
+    n = info0["ticks_total"] if steps is None else steps
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(n)
+    e1.record(stream)
+    s.sync()
+    torch.cuda.synchronize()
+    return s, e0.elapsed_time(e1) / 1e3, n
+
+
+def particle_steps(w, ticks):
+    """sum over systems of N_s x (steps system s takes in `ticks` ticks)."""
+    h_min = min(sy[2] for sy in w["systems"])
+    tot = 0
+    for N, _e, h in w["systems"]:
+        stride = int(round(h / h_min))
+        tot += N * ((ticks + stride - 1) // stride)
+    return tot
+
+
+def study_precision(args, stream):
+    """d=3 precision study: FP64, FP32 and FP32-compensated runs of the same
+    paths; errors of FP32 modes against the FP64 path (mean, variance, rMSE)."""
+    import numpy as np
+    from paper_2105_09688_amd import workloads as W
+    from paper_2105_09688_amd.ssm import SSM
+    w = W.precision_d3(N=args.N or 2 ** 18)
+    N = w["systems"][0][0]
+    res = {}
+    states = {}
+    for prec in ("fp64", "fp32_kahan", "fp32"):
+        s, dt, n = timed_run(SSM, w, prec, stream)
+        info = s.info()
+        states[prec] = (s.state(0), s.moments(0))
+        pair_avg = info["pair_ms"] / 1e3 / max(1, info["pair_launches"])
+        res[prec] = {"seconds": dt, "steps": n, "particle_steps_per_s": N * n / dt,
+                     "pair_kernel_avg_ms": pair_avg * 1e3,
+                     "pair_tflops": float(N) * N * flops_per_pair(3) / pair_avg / 1e12}
+        s.close()
+        print(f"[precision] {prec}: {dt:.2f} s", file=sys.stderr, flush=True)
+    X64, (m64, v64) = states["fp64"]
+    for prec in ("fp32_kahan", "fp32"):
+        X, (m, v) = states[prec]
+        D = X - X64
+        res[prec]["err_vs_fp64"] = {
+            "mean_abs": [float(x) for x in np.abs(m - m64)],
+            "var_abs": [float(x) for x in np.abs(v - v64)],
+            "pathwise_rms": float(np.sqrt(np.sum(D * D) / N)),
+            "pathwise_max_rel": float(np.max(np.abs(D) / np.maximum(1.0, np.abs(X64)))),
+        }
+    res["fp64"]["mean"] = [float(x) for x in m64]
+    res["fp64"]["var"] = [float(x) for x in v64]
+    return {"study": "precision", "workload": f"d=3 N={N} T=1 h=2^-10 l=0.5", "results": res}
+
+
+def study_batched(args, stream):
+    """Batched case: 64 ensembles of uneven N x 5 step sizes in one context;
+    throughput, and rMSE per step size against a 2^-12 proxy solution on the
+    same Brownian paths, with the OLS slope."""
+    import math
+    from paper_2105_09688_amd import workloads as W
+    from paper_2105_09688_amd.ssm import SSM
+    levels = (4, 5, 6, 7, 8)
+    w = W.batched(levels=levels)
+    prec = args.precision
+    s, dt, n = timed_run(SSM, w, prec, stream)
+    info = s.info()
+    ps = particle_steps(w, n)
+    ref_w = W.with_systems(w, [(N, e, 2.0 ** -12) for (N, e) in {(sy[0], sy[1]) for sy in w["systems"]}])
+    ref_w["systems"] = sorted(ref_w["systems"], key=lambda t: t[1])
+    r, dt_ref, _ = timed_run(SSM, ref_w, prec, stream, profile=False)
+    by_ens = {sy[1]: k for k, sy in enumerate(ref_w["systems"])}
+    sq = {l: 0.0 for l in levels}
+    cnt = {l: 0 for l in levels}
+    for k, (N, e, h) in enumerate(w["systems"]):
+        l = int(round(-math.log2(h)))
+        sq[l] += s.sqdiff(k, r, by_ens[e])
+        cnt[l] += N
+    rmse = {l: math.sqrt(sq[l] / cnt[l]) for l in levels}
+    xs = [math.log2(2.0 ** -l) for l in levels]
+    ys = [math.log2(rmse[l]) for l in levels]
+    xm, ym = sum(xs) / len(xs), sum(ys) / len(ys)
+    slope = sum((x - xm) * (y - ym) for x, y in zip(xs, ys)) / sum((x - xm) ** 2 for x in xs)
+    out = {"study": "batched", "workload": f"64 ensembles, N in [2^10, 2^16] (sum {sum(sy[0] for sy in w['systems']) // len(levels)}), "
+                                            f"h = 2^-4..2^-8 on a 2^-12 grid, T=1, {prec}",
+           "ticks": n, "seconds": dt, "particle_steps": ps, "particle_steps_per_s": ps / dt,
+           "pair_kernel_ms_total": info["pair_ms"], "update_kernel_ms_total": info["update_ms"],
+           "rmse_vs_2^-12": {f"2^-{l}": rmse[l] for l in levels}, "slope": slope,
+           "reference_seconds": dt_ref}
+    s.close()
+    r.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1024)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--precision", default="fp32_kahan", choices=["fp64", "fp32", "fp32_kahan"])
-    ap.add_argument("--N", type=int, default=2 ** 16)
+    ap.add_argument("--N", type=int, default=0)
+    ap.add_argument("--study", choices=["none", "precision", "batched"], default="none",
+                    help="run a study of another workload instead of the throughput line")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -97,7 +202,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    w = W.single_gpu_d1(N=args.N)
+    if args.study != "none":
+        stream = torch.cuda.Stream()
+        fn = {"precision": study_precision, "batched": study_batched}[args.study]
+        print(json.dumps(fn(args, stream)), flush=True)
+        return
+    w = W.single_gpu_d1(N=args.N or 2 ** 16)
     N, _, h = w["systems"][0]
     d = w["d"]
     total_steps = int(round(w["T"] / h))

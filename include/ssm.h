@@ -167,6 +167,13 @@ ssm_status ssm_set_state(ssm_ctx *ctx, int32_t sys, const double *host);
  * Synchronizes both contexts. */
 ssm_status ssm_rmse(ssm_ctx *a, ssm_ctx *b, double *per_sys, double *rmse);
 
+/* Sum of squared differences between system sys_a of context a and system
+ * sys_b of context b (same d and N): *out = sum_i |X_a^i - X_b^i|^2, double
+ * precision on the device.  Lets a batch at several step sizes be compared
+ * with a proxy-solution context of another layout (Section 3).  Synchronizes
+ * both contexts. */
+ssm_status ssm_sqdiff(ssm_ctx *a, int32_t sys_a, ssm_ctx *b, int32_t sys_b, double *out);
+
 /* Enable (nonzero) or disable per-kernel timing with HIP events on the
  * context's stream; enabling resets the accumulated times.  Timing adds one
  * event record before and after each kernel launch. */

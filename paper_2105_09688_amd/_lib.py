@@ -16,7 +16,7 @@ SSM_FP64, SSM_FP32, SSM_FP32_KAHAN = 0, 1, 2
 # every function the header declares (checked by the CPU test suite)
 EXPORTS = (
     "ssm_init", "ssm_step", "ssm_run", "ssm_sync", "ssm_moments", "ssm_get_state",
-    "ssm_set_state", "ssm_rmse", "ssm_info", "ssm_profile", "ssm_destroy", "ssm_last_error",
+    "ssm_set_state", "ssm_rmse", "ssm_sqdiff", "ssm_info", "ssm_profile", "ssm_destroy", "ssm_last_error",
     "ssm_pair_sum", "ssm_pair_workspace_bytes", "ssm_implicit_solve", "ssm_brownian",
     "ssm_philox_blocks",
 )
@@ -70,6 +70,7 @@ def load():
         "ssm_get_state": (st, [vp, i32, i32, dp, C.POINTER(C.c_int64)]),
         "ssm_set_state": (st, [vp, i32, dp]),
         "ssm_rmse": (st, [vp, vp, dp, dp]),
+        "ssm_sqdiff": (st, [vp, i32, vp, i32, dp]),
         "ssm_info": (st, [vp, C.POINTER(Info)]),
         "ssm_profile": (st, [vp, i32]),
         "ssm_destroy": (None, [vp]),

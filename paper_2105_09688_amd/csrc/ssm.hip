@@ -635,18 +635,35 @@ __global__ void k_scatter(const double* __restrict__ in, int64_t P, int64_t off,
 }
 
 template <typename TA, typename TB>
-__global__ void k_sqdiff(const TA* __restrict__ A, const TB* __restrict__ B, int64_t P, int64_t off, int64_t N,
-                         int d, double* __restrict__ out)
+__global__ void k_sqdiff(const TA* __restrict__ A, int64_t PA, int64_t offA, const TB* __restrict__ B, int64_t PB,
+                         int64_t offB, int64_t N, int d, double* __restrict__ out)
 {
     __shared__ double red[kBlk];
     double s = 0.0;
     for (int64_t i = threadIdx.x; i < N; i += kBlk)
         for (int k = 0; k < d; ++k) {
-            const double c = (double)A[k * P + off + i] - (double)B[k * P + off + i];
+            const double c = (double)A[k * PA + offA + i] - (double)B[k * PB + offB + i];
             s += c * c;
         }
     const double tot = block_sum(s, red);
     if (threadIdx.x == 0) out[0] = tot;
+}
+
+// one system of a against one system of b; result in dout (device), async on a's stream
+static ssm_status launch_sqdiff(ssm_ctx* a, int sa, ssm_ctx* b, int sb, double* dout)
+{
+    const SysHost& A = a->sys[sa];
+    const SysHost& B = b->sys[sb];
+    const bool fa = a->prec == SSM_FP64, fb = b->prec == SSM_FP64;
+#define SQD(TA, TB) hipLaunchKernelGGL((k_sqdiff<TA, TB>), dim3(1), dim3(kBlk), 0, a->stream, (const TA*)a->X, a->P, A.off, \
+                                       (const TB*)b->X, b->P, B.off, A.N, a->d, dout)
+    if (fa && fb) SQD(double, double);
+    else if (fa) SQD(double, float);
+    else if (fb) SQD(float, double);
+    else SQD(float, float);
+#undef SQD
+    HIP_TRY(hipGetLastError());
+    return SSM_OK;
 }
 
 extern "C" ssm_status ssm_moments(ssm_ctx* c, int32_t sys, double* mean, double* var)
@@ -732,25 +749,19 @@ extern "C" ssm_status ssm_rmse(ssm_ctx* a, ssm_ctx* b, double* per_sys, double* 
     if (!a || !b || !rmse) return fail(SSM_ERR_INVALID, "NULL argument");
     if (a->d != b->d || a->sys.size() != b->sys.size()) return fail(SSM_ERR_INVALID, "contexts differ in layout");
     for (size_t s = 0; s < a->sys.size(); ++s)
-        if (a->sys[s].N != b->sys[s].N || a->sys[s].off != b->sys[s].off) return fail(SSM_ERR_INVALID, "contexts differ in layout");
+        if (a->sys[s].N != b->sys[s].N) return fail(SSM_ERR_INVALID, "contexts differ in layout");
     ssm_status st = ssm_sync(b);
     if (st != SSM_OK) return st;
     const int n = (int)a->sys.size();
     double* dout = nullptr;
     HIP_TRY(hipMalloc((void**)&dout, n * sizeof(double)));
-    for (int s = 0; s < n; ++s) {
-        const SysHost& S = a->sys[s];
-        const bool fa = a->prec == SSM_FP64, fb = b->prec == SSM_FP64;
-        if (fa && fb) hipLaunchKernelGGL((k_sqdiff<double, double>), dim3(1), dim3(kBlk), 0, a->stream, (const double*)a->X, (const double*)b->X, a->P, S.off, S.N, a->d, dout + s);
-        else if (fa) hipLaunchKernelGGL((k_sqdiff<double, float>), dim3(1), dim3(kBlk), 0, a->stream, (const double*)a->X, (const float*)b->X, a->P, S.off, S.N, a->d, dout + s);
-        else if (fb) hipLaunchKernelGGL((k_sqdiff<float, double>), dim3(1), dim3(kBlk), 0, a->stream, (const float*)a->X, (const double*)b->X, a->P, S.off, S.N, a->d, dout + s);
-        else hipLaunchKernelGGL((k_sqdiff<float, float>), dim3(1), dim3(kBlk), 0, a->stream, (const float*)a->X, (const float*)b->X, a->P, S.off, S.N, a->d, dout + s);
-    }
+    for (int s = 0; s < n && st == SSM_OK; ++s) st = launch_sqdiff(a, s, b, s, dout + s);
     std::vector<double> h(n);
-    hipError_t he = hipGetLastError();
-    if (he == hipSuccess) he = hipMemcpyAsync(h.data(), dout, n * sizeof(double), hipMemcpyDeviceToHost, a->stream);
+    hipError_t he = hipSuccess;
+    if (st == SSM_OK) he = hipMemcpyAsync(h.data(), dout, n * sizeof(double), hipMemcpyDeviceToHost, a->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(a->stream);
     (void)hipFree(dout);
+    if (st != SSM_OK) return st;
     if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("rmse: ") + hipGetErrorString(he));
     double tot = 0.0;
     int64_t cnt = 0;
@@ -760,6 +771,20 @@ extern "C" ssm_status ssm_rmse(ssm_ctx* a, ssm_ctx* b, double* per_sys, double* 
         cnt += a->sys[s].N;
     }
     *rmse = std::sqrt(tot / (double)cnt);
+    return ssm_sync(a);
+}
+
+extern "C" ssm_status ssm_sqdiff(ssm_ctx* a, int32_t sys_a, ssm_ctx* b, int32_t sys_b, double* out)
+{
+    if (!a || !b || !out) return fail(SSM_ERR_INVALID, "NULL argument");
+    if (sys_a < 0 || sys_a >= (int32_t)a->sys.size() || sys_b < 0 || sys_b >= (int32_t)b->sys.size())
+        return fail(SSM_ERR_INVALID, "sys out of range");
+    if (a->d != b->d || a->sys[sys_a].N != b->sys[sys_b].N) return fail(SSM_ERR_INVALID, "systems differ in d or N");
+    ssm_status st = ssm_sync(b);
+    if (st != SSM_OK) return st;
+    st = launch_sqdiff(a, sys_a, b, sys_b, a->dstage);
+    if (st != SSM_OK) return st;
+    HIP_TRY(hipMemcpyAsync(out, a->dstage, sizeof(double), hipMemcpyDeviceToHost, a->stream));
     return ssm_sync(a);
 }
 

@@ -122,6 +122,12 @@ class SSM:
         check(_lib.load().ssm_rmse(self._h, other._h, per.ctypes.data_as(C.POINTER(C.c_double)), C.byref(r)))
         return r.value, per
 
+    def sqdiff(self, sys: int, other: "SSM", other_sys: int) -> float:
+        """sum_i |X_self^i - X_other^i|^2 over one system of each context."""
+        r = C.c_double()
+        check(_lib.load().ssm_sqdiff(self._h, sys, other._h, other_sys, C.byref(r)))
+        return r.value
+
     def profile(self, enable: bool = True) -> None:
         check(_lib.load().ssm_profile(self._h, 1 if enable else 0))
 

@@ -317,3 +317,36 @@ def test_errors_are_reported(torch_cuda):
         with _ssm(w, "fp64") as s:
             s.run()
     assert e.value.status == -2
+
+
+def test_batched_levels_rmse_match_oracle_within_5_percent(torch_cuda):
+    """Reduced batched case (uneven ensembles x three step sizes in one FP32
+    context): per-level strong error against a 2^-10 proxy on the same paths
+    matches the oracle's within 5 %, and the per-system sqdiff entry point
+    agrees with the host formula."""
+    import math
+    sizes = [64, 300, 129, 512, 1000, 77]
+    levels = (4, 5, 6)
+    w = W.batched(n_ens=len(sizes), levels=levels, h_fine=2.0 ** -10, sizes=sizes)
+    ref_w = W.with_systems(w, [(N, e, 2.0 ** -10) for e, N in enumerate(sizes)])
+    _say("oracle batched + reference")
+    o = oracle.run(w)
+    o_ref = oracle.run(ref_w)
+    with _ssm(w, "fp32_kahan") as a, _ssm(ref_w, "fp32_kahan") as b:
+        a.run()
+        b.run()
+        for li, l in enumerate(levels):
+            sq_g = sq_o = 0.0
+            cnt = 0
+            for e, N in enumerate(sizes):
+                k = e * len(levels) + li
+                assert w["systems"][k] == (N, e, 2.0 ** -l)
+                g = a.sqdiff(k, b, e)
+                host = float(np.sum((a.state(k) - b.state(e)) ** 2))
+                assert g == pytest.approx(host, rel=1e-12, abs=1e-300)
+                sq_g += g
+                sq_o += float(np.sum((o[k] - o_ref[e]) ** 2))
+                cnt += N
+            r_g, r_o = math.sqrt(sq_g / cnt), math.sqrt(sq_o / cnt)
+            _say(f"level 2^-{l}: rmse gpu {r_g:.6e} oracle {r_o:.6e}")
+            assert abs(r_g - r_o) <= 0.05 * r_o
