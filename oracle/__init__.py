@@ -70,6 +70,13 @@ def _load():
     lib.ssmo_run.argtypes = [C.POINTER(_Cfg), C.c_int64, dp, C.POINTER(C.c_int64)]
     lib.ssmo_run.restype = C.c_int
     lib.ssmo_moments.argtypes = [C.c_int, C.c_int64, dp, dp, dp]
+    lib.ssmo_rff_omegas.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_double, dp]
+    lib.ssmo_rff_moments.argtypes = [C.c_int, C.c_int64, dp, C.c_int, dp, dp]
+    lib.ssmo_mlp_num_params.argtypes = [C.c_int, C.c_int, C.c_int]
+    lib.ssmo_mlp_num_params.restype = C.c_int64
+    lib.ssmo_mlp_forward.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_int64, dp, dp]
+    lib.ssmo_mlp_loss_grad.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_int64, dp, dp, dp]
+    lib.ssmo_mlp_loss_grad.restype = C.c_double
     lib.ssmo_num_threads.restype = C.c_int
     lib.ssmo_set_num_threads.argtypes = [C.c_int]
     _lib = lib
@@ -230,6 +237,50 @@ def moments(X: np.ndarray):
     m, v = np.zeros(d), np.zeros(d)
     lib.ssmo_moments(d, N, _dp(X), _dp(m), _dp(v))
     return m, v
+
+
+# ---------------------------------------------------------------- learned surrogate (not in the paper)
+def rff_omegas(seed: int, d: int, K: int, ell: float) -> np.ndarray:
+    """Frequencies omega_k = Z(3, k, 0, 0)[:d] / ell, [K][d]."""
+    lib = _load()
+    om = np.zeros((K, d))
+    lib.ssmo_rff_omegas(seed, d, K, ell, _dp(om))
+    return om
+
+
+def rff_moments(Y: np.ndarray, omega: np.ndarray) -> np.ndarray:
+    """[cos moments (K), sin moments (K)] of the empirical measure of Y [d][N]."""
+    lib = _load()
+    Y = _f64(np.atleast_2d(Y))
+    om = _f64(omega)
+    K = om.shape[0]
+    m = np.zeros(2 * K)
+    lib.ssmo_rff_moments(Y.shape[0], Y.shape[1], _dp(Y), K, _dp(om), _dp(m))
+    return m
+
+
+def mlp_num_params(n_in: int, H: int, n_out: int) -> int:
+    return int(_load().ssmo_mlp_num_params(n_in, H, n_out))
+
+
+def mlp_forward(params, X, n_in: int, H: int, n_out: int) -> np.ndarray:
+    lib = _load()
+    p = _f64(params)
+    X = _f64(X).reshape(-1, n_in)
+    Y = np.zeros((X.shape[0], n_out))
+    lib.ssmo_mlp_forward(n_in, H, n_out, _dp(p), X.shape[0], _dp(X), _dp(Y))
+    return Y
+
+
+def mlp_loss_grad(params, X, T, n_in: int, H: int, n_out: int):
+    """(loss, gradient) of L = (1/B) sum_b |MLP(X_b) - T_b|^2."""
+    lib = _load()
+    p = _f64(params)
+    X = _f64(X).reshape(-1, n_in)
+    T = _f64(T).reshape(-1, n_out)
+    g = np.zeros_like(p)
+    loss = lib.ssmo_mlp_loss_grad(n_in, H, n_out, _dp(p), X.shape[0], _dp(X), _dp(T), _dp(g))
+    return float(loss), g
 
 
 def num_threads() -> int:

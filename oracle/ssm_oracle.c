@@ -358,6 +358,168 @@ void ssmo_moments(int d, int64_t N, const double *X, double *mean, double *var)
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Learned-surrogate support: random Fourier feature moments and an MLP.     */
+/* Not part of the paper; plain definitions for checking the GPU kernels.   */
+/* ------------------------------------------------------------------------ */
+void ssmo_rff_omegas(uint64_t seed, int d, int K, double ell, double *omega)
+{
+    for (int k = 0; k < K; ++k) {
+        double z[4];
+        ssmo_normals4(seed, 3u, (uint64_t)k, 0u, 0u, z);
+        for (int c = 0; c < d; ++c) omega[k * d + c] = z[c] / ell;
+    }
+}
+
+void ssmo_rff_moments(int d, int64_t N, const double *Y, int K, const double *omega, double *m)
+{
+    for (int k = 0; k < K; ++k) {
+        double sc = 0.0, ss = 0.0;
+        for (int64_t j = 0; j < N; ++j) {
+            double ph = 0.0;
+            for (int c = 0; c < d; ++c) ph += omega[k * d + c] * Y[(int64_t)c * N + j];
+            sc += cos(ph);
+            ss += sin(ph);
+        }
+        m[k] = sc / (double)N;
+        m[K + k] = ss / (double)N;
+    }
+}
+
+int64_t ssmo_mlp_num_params(int in, int H, int out)
+{
+    return (int64_t)H * in + H + 2 * ((int64_t)H * H + H) + (int64_t)out * H + out;
+}
+
+static double silu(double z) { return z / (1.0 + exp(-z)); }
+
+/* derivative of z / (1 + e^-z): s(z) (1 + z (1 - s(z))) with s the logistic function */
+static double silu_prime(double z)
+{
+    double sg = 1.0 / (1.0 + exp(-z));
+    return sg * (1.0 + z * (1.0 - sg));
+}
+
+/* y[o] = b[o] + sum_i W[o][i] x[i] */
+static void dense(int nin, int nout, const double *W, const double *b, const double *x, double *y)
+{
+    for (int o = 0; o < nout; ++o) {
+        double acc = b[o];
+        for (int i = 0; i < nin; ++i) acc += W[(int64_t)o * nin + i] * x[i];
+        y[o] = acc;
+    }
+}
+
+typedef struct {
+    const double *W[4];
+    const double *b[4];
+} mlp_view;
+
+static mlp_view mlp_split(int in, int H, int out, const double *p)
+{
+    mlp_view v;
+    v.W[0] = p; p += (int64_t)H * in;
+    v.b[0] = p; p += H;
+    v.W[1] = p; p += (int64_t)H * H;
+    v.b[1] = p; p += H;
+    v.W[2] = p; p += (int64_t)H * H;
+    v.b[2] = p; p += H;
+    v.W[3] = p; p += (int64_t)out * H;
+    v.b[3] = p;
+    (void)out;
+    return v;
+}
+
+void ssmo_mlp_forward(int in, int H, int out, const double *params, int64_t B, const double *X,
+                      double *Y)
+{
+    const mlp_view v = mlp_split(in, H, out, params);
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < B; ++b) {
+        double z[256], a[256], a2[256];
+        dense(in, H, v.W[0], v.b[0], X + b * in, z);
+        for (int h = 0; h < H; ++h) a[h] = silu(z[h]);
+        dense(H, H, v.W[1], v.b[1], a, z);
+        for (int h = 0; h < H; ++h) a2[h] = silu(z[h]);
+        dense(H, H, v.W[2], v.b[2], a2, z);
+        for (int h = 0; h < H; ++h) a[h] = silu(z[h]);
+        dense(H, out, v.W[3], v.b[3], a, Y + b * out);
+    }
+}
+
+double ssmo_mlp_loss_grad(int in, int H, int out, const double *params, int64_t B,
+                          const double *X, const double *T, double *grad)
+{
+    const mlp_view v = mlp_split(in, H, out, params);
+    const int64_t P = ssmo_mlp_num_params(in, H, out);
+    for (int64_t q = 0; q < P; ++q) grad[q] = 0.0;
+    double *gW[4], *gb[4];
+    {
+        double *g = grad;
+        gW[0] = g; g += (int64_t)H * in; gb[0] = g; g += H;
+        gW[1] = g; g += (int64_t)H * H; gb[1] = g; g += H;
+        gW[2] = g; g += (int64_t)H * H; gb[2] = g; g += H;
+        gW[3] = g; g += (int64_t)out * H; gb[3] = g;
+    }
+    double loss = 0.0;
+    /* sequential over samples: gradients accumulate in sample order */
+    for (int64_t b = 0; b < B; ++b) {
+        const double *x0 = X + b * in;
+        double z1[256], a1[256], z2[256], a2[256], z3[256], a3[256], y[16];
+        dense(in, H, v.W[0], v.b[0], x0, z1);
+        for (int h = 0; h < H; ++h) a1[h] = silu(z1[h]);
+        dense(H, H, v.W[1], v.b[1], a1, z2);
+        for (int h = 0; h < H; ++h) a2[h] = silu(z2[h]);
+        dense(H, H, v.W[2], v.b[2], a2, z3);
+        for (int h = 0; h < H; ++h) a3[h] = silu(z3[h]);
+        dense(H, out, v.W[3], v.b[3], a3, y);
+        /* dL/dy */
+        double gy[16];
+        for (int o = 0; o < out; ++o) {
+            double r = y[o] - T[b * out + o];
+            loss += r * r;
+            gy[o] = 2.0 * r / (double)B;
+        }
+        /* output layer */
+        double g3[256], g2[256], g1[256];
+        for (int o = 0; o < out; ++o) {
+            gb[3][o] += gy[o];
+            for (int h = 0; h < H; ++h) gW[3][(int64_t)o * H + h] += gy[o] * a3[h];
+        }
+        for (int h = 0; h < H; ++h) {
+            double s = 0.0;
+            for (int o = 0; o < out; ++o) s += v.W[3][(int64_t)o * H + h] * gy[o];
+            g3[h] = s * silu_prime(z3[h]);
+        }
+        /* third hidden layer */
+        for (int o = 0; o < H; ++o) {
+            gb[2][o] += g3[o];
+            for (int h = 0; h < H; ++h) gW[2][(int64_t)o * H + h] += g3[o] * a2[h];
+        }
+        for (int h = 0; h < H; ++h) {
+            double s = 0.0;
+            for (int o = 0; o < H; ++o) s += v.W[2][(int64_t)o * H + h] * g3[o];
+            g2[h] = s * silu_prime(z2[h]);
+        }
+        /* second hidden layer */
+        for (int o = 0; o < H; ++o) {
+            gb[1][o] += g2[o];
+            for (int h = 0; h < H; ++h) gW[1][(int64_t)o * H + h] += g2[o] * a1[h];
+        }
+        for (int h = 0; h < H; ++h) {
+            double s = 0.0;
+            for (int o = 0; o < H; ++o) s += v.W[1][(int64_t)o * H + h] * g2[o];
+            g1[h] = s * silu_prime(z1[h]);
+        }
+        /* first layer */
+        for (int o = 0; o < H; ++o) {
+            gb[0][o] += g1[o];
+            for (int i = 0; i < in; ++i) gW[0][(int64_t)o * in + i] += g1[o] * x0[i];
+        }
+    }
+    return loss / (double)B;
+}
+
 int ssmo_num_threads(void)
 {
 #ifdef _OPENMP

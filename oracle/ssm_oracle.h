@@ -103,6 +103,30 @@ int ssmo_run(const ssmo_cfg *cfg, int64_t stop_after, double *X_out, int64_t *st
 /* mean_k and var_k = (1/N) sum (X_k - mean_k)^2, two passes, for [d][N]. */
 void ssmo_moments(int d, int64_t N, const double *X, double *mean, double *var);
 
+/* ---- learned-surrogate support (not in the paper; test infrastructure) ----
+ * Random Fourier feature frequencies: omega_k = Z(3, k, 0, 0)[0..d) / ell,
+ * i.e. omega_k ~ N(0, I / ell^2), for which E cos(omega.(x - z)) =
+ * exp(-|x - z|^2 / (2 ell^2)).  omega: [K][d]. */
+void ssmo_rff_omegas(uint64_t seed, int d, int K, double ell, double *omega);
+
+/* Moments of the empirical measure of Y ([d][N]) at the K frequencies:
+ * m[k] = (1/N) sum_j cos(omega_k . Y^j), m[K + k] = (1/N) sum_j sin(omega_k . Y^j). */
+void ssmo_rff_moments(int d, int64_t N, const double *Y, int K, const double *omega, double *m);
+
+/* Multilayer perceptron in -> H -> H -> H -> out, SiLU (s(z) = z / (1 + e^-z))
+ * after each hidden layer, linear output.  params (flat, row-major):
+ * W1[H][in], b1[H], W2[H][H], b2[H], W3[H][H], b3[H], W4[out][H], b4[out].
+ * X: [B][in], Y: [B][out]. */
+int64_t ssmo_mlp_num_params(int in, int H, int out);
+void ssmo_mlp_forward(int in, int H, int out, const double *params, int64_t B, const double *X,
+                      double *Y);
+
+/* Loss L = (1/B) sum_b sum_o (Y_bo - T_bo)^2 and its gradient dL/dparams
+ * (same layout as params) by reverse-mode differentiation written out layer by
+ * layer.  Returns L. */
+double ssmo_mlp_loss_grad(int in, int H, int out, const double *params, int64_t B,
+                          const double *X, const double *T, double *grad);
+
 /* Threads OpenMP will use (1 when built without OpenMP). */
 int ssmo_num_threads(void);
 void ssmo_set_num_threads(int n);
