@@ -123,7 +123,24 @@ typedef struct {
     double pair_ms;          /* their summed duration, milliseconds */
     int64_t update_launches; /* launches of the per-particle update (+ implicit solve) kernels */
     double update_ms;
+    /* learned surrogate (ssm_surrogate_enable) */
+    int64_t surr_checks;         /* check ticks: exact pair term computed and compared */
+    int64_t surr_ticks;          /* ticks whose update used the surrogate */
+    int64_t surr_fallback_ticks; /* non-check ticks that used the exact term after a failed check */
+    double surr_last_err;        /* relative error of the last check */
+    double surr_max_err;         /* largest relative error seen */
 } ssm_info_t;
+
+/* Training settings of ssm_mlp_train (Adam; zeros select the defaults in brackets). */
+typedef struct {
+    int64_t steps;   /* optimizer steps (>= 1) */
+    int32_t batch;   /* samples per step, multiple of 64 */
+    float lr;        /* learning rate (> 0) */
+    float beta1;     /* [0.9] */
+    float beta2;     /* [0.999] */
+    float eps;       /* [1e-8] */
+    uint64_t seed;   /* minibatch draws: Philox stream tag 4 */
+} ssm_train_cfg;
 
 typedef struct ssm_ctx ssm_ctx; /* opaque; owned by the library */
 
@@ -226,6 +243,60 @@ ssm_status ssm_brownian(int32_t d, int64_t N, uint64_t seed, int32_t ens, int64_
  * uint64 [4 count].  Asynchronous on stream. */
 ssm_status ssm_philox_blocks(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
                              uint64_t k1, int64_t count, uint64_t *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned surrogate of the pairwise term (an extension; not in the paper).
+ *
+ * Features of particle i: u = [Y*_i (d values), C_1..C_K, S_1..S_K] with
+ * C_k = (1/N) sum_j cos(omega_k . Y*_j), S_k = (1/N) sum_j sin(omega_k . Y*_j),
+ * K = 16, omega_k = Z(3, k, 0, 0)[0..d) / b_ell (so E cos(omega.(x - z)) is the
+ * Gaussian kernel of the pairwise term).  Network: u -> 64 -> 64 -> 64 -> d,
+ * SiLU after each hidden layer, BF16 weights and activations on the matrix
+ * cores with FP32 accumulation.  Parameters are FP32 "master" weights in the
+ * flat layout W1[64][d+2K] b1[64] W2[64][64] b2[64] W3[64][64] b3[64]
+ * W4[d][64] b4[d] (row-major, [out][in]).  The output approximates
+ * b_g (1/N) sum_j (Y^j - Y^i) exp(-|Y^i - Y^j|^2 / (2 b_ell^2)).
+ * ------------------------------------------------------------------------- */
+
+/* Number of parameters for state dimension d (0 if d is out of range). */
+int64_t ssm_mlp_num_params(int32_t d);
+
+/* Load master weights (host [n], n = ssm_mlp_num_params(d)) into a context
+ * with a pairwise term.  Synchronizes. */
+ssm_status ssm_surrogate_load(ssm_ctx *ctx, const float *master, int64_t n);
+
+/* Use the loaded surrogate in place of the O(N^2) pairwise sums.  Every
+ * check_every-th tick (tick % check_every == 0) the exact sums are computed
+ * as well, the update uses them, and the relative error
+ * sqrt(sum_i |s_i - p_i|^2 / sum_i |p_i|^2) over the stepping systems decides
+ * whether the following ticks use the surrogate (error <= tol) or the exact
+ * sums (until the next check).  Check ticks synchronize the stream.
+ * check_every = 0 turns the surrogate off. */
+ssm_status ssm_surrogate_enable(ssm_ctx *ctx, int32_t check_every, double tol);
+
+/* Training pairs from the current state of system sys: n draws (with
+ * replacement, Philox stream tag 4 under seed) of a particle i, writing its
+ * features to U (device float [n][d + 2K]) and its exact pairwise term to T
+ * (device float [n][d]).  Synchronizes. */
+ssm_status ssm_surrogate_samples(ssm_ctx *ctx, int32_t sys, int64_t n, uint64_t seed, float *U, float *T);
+
+/* Network output for explicit features: out (device float [n][d]) from U
+ * (device float [n][d + 2K]) and master weights (device float).  Synchronizes stream. */
+ssm_status ssm_mlp_forward(int32_t d, const float *master, const float *U, int64_t n, float *out,
+                           void *stream);
+
+/* Loss L = (1/n) sum_rows |net(U_r) - T_r|^2 and dL/dparams (device float,
+ * flat layout) for the n rows in order (n a multiple of 64), computed with
+ * the training kernels.  *loss (host, may be NULL).  Synchronizes stream. */
+ssm_status ssm_mlp_loss_grad(int32_t d, const float *master, const float *U, const float *T, int64_t n,
+                             float *grad, double *loss, void *stream);
+
+/* Adam training of the master weights (device float, updated in place) on
+ * n_samples pairs (U, T) with minibatches drawn with replacement.
+ * loss_hist (host float [steps], may be NULL) receives each step's minibatch
+ * loss.  Synchronizes stream. */
+ssm_status ssm_mlp_train(int32_t d, const float *U, const float *T, int64_t n_samples,
+                         const ssm_train_cfg *cfg, float *master, float *loss_hist, void *stream);
 
 #ifdef __cplusplus
 }

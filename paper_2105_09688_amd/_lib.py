@@ -18,7 +18,8 @@ EXPORTS = (
     "ssm_init", "ssm_step", "ssm_run", "ssm_sync", "ssm_moments", "ssm_get_state",
     "ssm_set_state", "ssm_rmse", "ssm_sqdiff", "ssm_info", "ssm_profile", "ssm_destroy", "ssm_last_error",
     "ssm_pair_sum", "ssm_pair_workspace_bytes", "ssm_implicit_solve", "ssm_brownian",
-    "ssm_philox_blocks",
+    "ssm_philox_blocks", "ssm_mlp_num_params", "ssm_surrogate_load", "ssm_surrogate_enable",
+    "ssm_surrogate_samples", "ssm_mlp_forward", "ssm_mlp_loss_grad", "ssm_mlp_train",
 )
 
 
@@ -44,6 +45,15 @@ class Info(C.Structure):
         ("targets_per_lane", C.c_int32), ("sources_per_item", C.c_int32), ("device_bytes", C.c_int64),
         ("pair_launches", C.c_int64), ("pair_ms", C.c_double),
         ("update_launches", C.c_int64), ("update_ms", C.c_double),
+        ("surr_checks", C.c_int64), ("surr_ticks", C.c_int64), ("surr_fallback_ticks", C.c_int64),
+        ("surr_last_err", C.c_double), ("surr_max_err", C.c_double),
+    ]
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [
+        ("steps", C.c_int64), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+        ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64),
     ]
 
 
@@ -81,6 +91,13 @@ def load():
                                     C.c_double, dp, C.c_double, i32, vp, vp, vp]),
         "ssm_brownian": (st, [i32, i64, u64, i32, i64, i32, C.c_double, vp, vp]),
         "ssm_philox_blocks": (st, [u64, u64, u64, u64, u64, u64, i64, vp, vp]),
+        "ssm_mlp_num_params": (i64, [i32]),
+        "ssm_surrogate_load": (st, [vp, vp, i64]),
+        "ssm_surrogate_enable": (st, [vp, i32, C.c_double]),
+        "ssm_surrogate_samples": (st, [vp, i32, i64, u64, vp, vp]),
+        "ssm_mlp_forward": (st, [i32, vp, vp, i64, vp, vp]),
+        "ssm_mlp_loss_grad": (st, [i32, vp, vp, vp, i64, vp, dp, vp]),
+        "ssm_mlp_train": (st, [i32, vp, vp, i64, C.POINTER(TrainCfg), vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

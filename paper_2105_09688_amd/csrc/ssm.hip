@@ -11,7 +11,7 @@
 #include <vector>
 
 #include "../../include/ssm.h"
-#include "ssm_kernels.hpp"
+#include "ssm_surrogate.hpp"
 
 using namespace ssm;
 
@@ -190,6 +190,22 @@ struct ssm_ctx {
     std::vector<int64_t> pair_off, pair_cnt, blk_off, blk_cnt;
     std::vector<int64_t> all_blk_off;  // blocks of every system (init / set_state)
     int64_t all_blk_cnt = 0;
+    // learned surrogate of the pair term
+    bool surr_loaded = false;
+    int32_t surr_check_every = 0;  // 0: surrogate off
+    double surr_tol = 1e-3;
+    bool surr_fallback = false;
+    int64_t surr_checks = 0, surr_fallback_ticks = 0, surr_ticks = 0;
+    double surr_last_err = 0.0, surr_max_err = 0.0;
+    MlpPacked* dmlp = nullptr;
+    float* surr = nullptr;         // [d][P] surrogate pair term
+    double* rff_part = nullptr;    // [nblk_tot][2K]
+    float* mom = nullptr;          // [n_sys][2K]
+    double* err_part = nullptr;    // [nblk_tot][2]
+    int32_t* dsys_list = nullptr;  // per phase: active systems
+    std::vector<int64_t> sys_list_off, sys_list_cnt;
+    RffFreq rff{};
+    double ell = 1.0;
     // kernel timing: event pairs recorded around launches while profiling
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pair, ev_update;
@@ -246,7 +262,8 @@ static void free_ctx(ssm_ctx* c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    void* bufs[] = {c->X, c->Y, c->Ys, c->Bp, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage};
+    void* bufs[] = {c->X, c->Y, c->Ys, c->Bp, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
+                    c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     recycle_events(c, c->ev_pair);
@@ -308,6 +325,25 @@ static void build_blk_items(const ssm_ctx* c, const std::vector<int>& systems, s
 }
 
 template <typename T>
+static ssm_status launch_surrogate(ssm_ctx* c, int64_t ph)
+{
+    const int d = c->d;
+    const BlkItem* items = c->dblk + c->blk_off[ph];
+    const int64_t nb = c->blk_cnt[ph];
+    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, items,
+                                         c->dsys, c->P, (const T*)c->Y, c->rff, c->rff_part));
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_rff_final, dim3((unsigned)c->sys_list_cnt[ph]), dim3(64), 0, c->stream,
+                       c->dsys_list + c->sys_list_off[ph], c->dsys, c->rff_part, c->mom);
+    HIP_TRY(hipGetLastError());
+    const unsigned grid = (unsigned)std::min<int64_t>(nb, 2048);
+    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_mlp_infer<T, D>), dim3(grid), dim3(256), 0, c->stream, items, (int)nb,
+                                         c->dsys, c->P, (const T*)c->Y, c->mom, c->dmlp, c->surr));
+    HIP_TRY(hipGetLastError());
+    return SSM_OK;
+}
+
+template <typename T>
 static ssm_status launch_tick(ssm_ctx* c)
 {
     const int64_t ph = c->tick % c->max_stride;
@@ -316,7 +352,11 @@ static ssm_status launch_tick(ssm_ctx* c)
     T* Y = (T*)c->Y;
     T* Ys = (T*)c->Ys;
     const int d = c->d;
-    if (c->has_pair && np > 0) {
+    const bool surr_on = c->surr_check_every > 0 && c->has_pair;
+    const bool check = surr_on && (c->tick % c->surr_check_every == 0);
+    const bool run_exact = !surr_on || check || c->surr_fallback;
+    const bool run_surr = surr_on && (check || !c->surr_fallback);
+    if (c->has_pair && np > 0 && run_exact) {
         dim3 grid((unsigned)((np + kWaves - 1) / kWaves));
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->profiling) {
@@ -332,6 +372,17 @@ static ssm_status launch_tick(ssm_ctx* c)
             c->ev_pair.push_back({e0, e1});
         }
     }
+    if (run_surr && nb > 0) {
+        ssm_status st = launch_surrogate<T>(c, ph);
+        if (st != SSM_OK) return st;
+    }
+    if (check && nb > 0) {
+        const BlkItem* items = c->dblk + c->blk_off[ph];
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_surr_err<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, items,
+                                             c->dsys, c->P, c->Bp, c->surr, c->err_part));
+        HIP_TRY(hipGetLastError());
+    }
+    const int use_surr = (run_surr && !check) ? 1 : 0;
     if (nb > 0) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->profiling) {
@@ -341,8 +392,8 @@ static ssm_status launch_tick(ssm_ctx* c)
         }
         const BlkItem* items = c->dblk + c->blk_off[ph];
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_update<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream,
-                                             items, c->dsys, c->coef, c->P, c->tick, X, Y, Ys, c->Bp,
-                                             c->psumX, c->psumY, c->nblk_tot, c->dflags));
+                                             items, c->dsys, c->coef, c->P, c->tick, X, Y, Ys, c->Bp, c->surr,
+                                             use_surr, c->psumX, c->psumY, c->nblk_tot, c->dflags));
         HIP_TRY(hipGetLastError());
         if (!c->fused) {
             SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_newton<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream,
@@ -354,6 +405,27 @@ static ssm_status launch_tick(ssm_ctx* c)
             if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
             c->ev_update.push_back({e0, e1});
         }
+    }
+    if (surr_on) {
+        if (use_surr) c->surr_ticks++;
+        if (!check && c->surr_fallback) c->surr_fallback_ticks++;
+    }
+    if (check && nb > 0) {
+        // relative error of the surrogate pair term over the active systems; decides
+        // whether the next ticks use it (until the next check)
+        std::vector<double> h(2 * nb);
+        HIP_TRY(hipMemcpyAsync(h.data(), c->err_part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        double se = 0.0, sb = 0.0;
+        for (int64_t q = 0; q < nb; ++q) {
+            se += h[2 * q];
+            sb += h[2 * q + 1];
+        }
+        const double err = sb > 0.0 ? std::sqrt(se / sb) : (se > 0.0 ? INFINITY : 0.0);
+        c->surr_last_err = err;
+        c->surr_max_err = std::max(c->surr_max_err, err);
+        c->surr_checks++;
+        c->surr_fallback = !(err <= c->surr_tol);
     }
     for (auto& S : c->sys)
         if (c->tick % S.stride == 0) S.steps_done++;
@@ -430,6 +502,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
         cf.x0_mean[k] = in ? cfg->x0_mean[k] : 0.0; cf.x0_std[k] = in ? cfg->x0_std[k] : 0.0;
     }
     const double ell = c->has_pair ? cfg->b_ell : 1.0;
+    c->ell = ell;
     cf.coord_scale = std::sqrt(kLog2e / (2.0 * ell * ell));
     cf.sqrt_hf = std::sqrt(cfg->h_fine);
     cf.seed = cfg->seed;
@@ -493,6 +566,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     // work lists per phase
     std::vector<PairItem> pairs;
     std::vector<BlkItem> blks;
+    std::vector<int32_t> sys_lists;
     c->pair_off.resize(c->max_stride);
     c->pair_cnt.resize(c->max_stride);
     c->blk_off.resize(c->max_stride);
@@ -507,6 +581,9 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
         c->blk_off[ph] = (int64_t)blks.size();
         build_blk_items(c, act, blks);
         c->blk_cnt[ph] = (int64_t)blks.size() - c->blk_off[ph];
+        c->sys_list_off.push_back((int64_t)sys_lists.size());
+        for (int s : act) sys_lists.push_back(s);
+        c->sys_list_cnt.push_back((int64_t)act.size());
     }
     {
         std::vector<int> all;
@@ -545,6 +622,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     ALLOC(c->dpair, std::max<size_t>(pairs.size(), 1) * sizeof(PairItem));
     ALLOC(c->dblk, blks.size() * sizeof(BlkItem));
     ALLOC(c->dflags, sizeof(Flags));
+    ALLOC(c->dsys_list, sys_lists.size() * sizeof(int32_t));
     int64_t maxN = 0;
     for (auto& S : c->sys) maxN = std::max(maxN, S.N);
     ALLOC(c->dstage, std::max<size_t>((size_t)c->d * maxN * sizeof(double), 2 * kMaxD * sizeof(double)));
@@ -552,6 +630,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     hipError_t he = hipMemcpyAsync(c->dsys, sd.data(), sd.size() * sizeof(SysDev), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess && !pairs.empty()) he = hipMemcpyAsync(c->dpair, pairs.data(), pairs.size() * sizeof(PairItem), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipMemcpyAsync(c->dblk, blks.data(), blks.size() * sizeof(BlkItem), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess) he = hipMemcpyAsync(c->dsys_list, sys_lists.data(), sys_lists.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(c->dflags, 0, sizeof(Flags), c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);  // host vectors go out of scope
     if (he != hipSuccess) { std::string m = hipGetErrorString(he); free_ctx(c); return fail(SSM_ERR_HIP, "upload: " + m); }
@@ -807,6 +886,11 @@ extern "C" ssm_status ssm_info(ssm_ctx* c, ssm_info_t* out)
     out->pair_ms = elapsed_ms(c->ev_pair);
     out->update_launches = (int64_t)c->ev_update.size();
     out->update_ms = elapsed_ms(c->ev_update);
+    out->surr_checks = c->surr_checks;
+    out->surr_ticks = c->surr_ticks;
+    out->surr_fallback_ticks = c->surr_fallback_ticks;
+    out->surr_last_err = c->surr_last_err;
+    out->surr_max_err = c->surr_max_err;
     return SSM_OK;
 }
 
@@ -938,5 +1022,238 @@ extern "C" ssm_status ssm_philox_blocks(uint64_t c0, uint64_t c1, uint64_t c2, u
     hipLaunchKernelGGL(k_philox, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, (hipStream_t)stream, c0, c1, c2, c3,
                        k0, k1, count, out);
     HIP_TRY(hipGetLastError());
+    return SSM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned surrogate
+// ---------------------------------------------------------------------------
+namespace ssm {
+
+__global__ void k_rff_freq(uint64_t seed, int d, double ell, RffFreq* out)
+{
+    const int q = threadIdx.x;
+    if (q >= kRff) return;
+    double z[kMaxD];
+    normals(seed, 3u, (uint64_t)q, 0ull, 0ull, 4, z);
+    for (int k = 0; k < kMaxD; ++k) out->w[q][k] = (k < d) ? (float)(z[k] / ell) : 0.0f;
+}
+
+__global__ void k_loss_reduce(const float* __restrict__ part, int nb, int B, float* __restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int q = 0; q < nb; ++q) s += part[q];
+    out[0] = (float)(s / (double)B);
+}
+
+}  // namespace ssm
+
+extern "C" int64_t ssm_mlp_num_params(int32_t d)
+{
+    if (d < 1 || d > SSM_MAX_D) return 0;
+    return mlp_params(d);
+}
+
+static ssm_status ensure_surrogate_buffers(ssm_ctx* c)
+{
+    if (c->dmlp) return SSM_OK;
+    ssm_status st;
+#define ALLOC2(ptr, bytes) do { st = dev_alloc(c, (void**)&(ptr), (bytes)); if (st != SSM_OK) return st; } while (0)
+    ALLOC2(c->dmlp, sizeof(MlpPacked));
+    ALLOC2(c->surr, (size_t)c->d * c->P * sizeof(float));
+    ALLOC2(c->rff_part, (size_t)c->nblk_tot * 2 * kRff * sizeof(double));
+    ALLOC2(c->mom, c->sys.size() * 2 * kRff * sizeof(float));
+    ALLOC2(c->err_part, (size_t)c->nblk_tot * 2 * sizeof(double));
+#undef ALLOC2
+    RffFreq* dfq = nullptr;
+    HIP_TRY(hipMalloc((void**)&dfq, sizeof(RffFreq)));
+    hipLaunchKernelGGL(k_rff_freq, dim3(1), dim3(64), 0, c->stream, c->coef.seed, c->d, c->ell, dfq);
+    hipError_t he = hipGetLastError();
+    if (he == hipSuccess) he = hipMemcpyAsync(&c->rff, dfq, sizeof(RffFreq), hipMemcpyDeviceToHost, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    (void)hipFree(dfq);
+    if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("rff frequencies: ") + hipGetErrorString(he));
+    return SSM_OK;
+}
+
+static ssm_status pack_weights(const float* master_dev, int d, MlpPacked* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_pack, dim3((kHid * kStride + 255) / 256), dim3(256), 0, st, master_dev, d, out);
+    HIP_TRY(hipGetLastError());
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_surrogate_load(ssm_ctx* c, const float* master_host, int64_t n)
+{
+    if (!c || !master_host) return fail(SSM_ERR_INVALID, "NULL argument");
+    if (!c->has_pair) return fail(SSM_ERR_STATE, "the surrogate replaces the pairwise term; b_g is 0");
+    if (n != mlp_params(c->d)) return fail(SSM_ERR_INVALID, "expected " + std::to_string(mlp_params(c->d)) + " parameters");
+    ssm_status st = ensure_surrogate_buffers(c);
+    if (st != SSM_OK) return st;
+    float* dm = nullptr;
+    HIP_TRY(hipMalloc((void**)&dm, n * sizeof(float)));
+    hipError_t he = hipMemcpyAsync(dm, master_host, n * sizeof(float), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess) {
+        st = pack_weights(dm, c->d, c->dmlp, c->stream);
+        he = hipStreamSynchronize(c->stream);
+    }
+    (void)hipFree(dm);
+    if (st != SSM_OK) return st;
+    if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("surrogate_load: ") + hipGetErrorString(he));
+    c->surr_loaded = true;
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_surrogate_enable(ssm_ctx* c, int32_t check_every, double tol)
+{
+    if (!c) return fail(SSM_ERR_INVALID, "ctx is NULL");
+    if (check_every < 0 || !(tol > 0.0)) return fail(SSM_ERR_INVALID, "check_every >= 0 and tol > 0 required");
+    if (check_every > 0 && !c->surr_loaded) return fail(SSM_ERR_STATE, "load surrogate weights first");
+    c->surr_check_every = check_every;
+    c->surr_tol = tol;
+    c->surr_fallback = false;
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_surrogate_samples(ssm_ctx* c, int32_t sys, int64_t n, uint64_t seed, float* U, float* Tt)
+{
+    if (!c || !U || !Tt || n < 1) return fail(SSM_ERR_INVALID, "bad argument");
+    if (sys < 0 || sys >= (int32_t)c->sys.size()) return fail(SSM_ERR_INVALID, "sys out of range");
+    if (!c->has_pair) return fail(SSM_ERR_STATE, "b_g is 0: no pairwise term to sample");
+    ssm_status st = ensure_surrogate_buffers(c);
+    if (st != SSM_OK) return st;
+    // exact pair sums and RFF moments of the current Y* of every system (phase-0 lists hold all)
+    const int64_t np = c->pair_cnt[0], nb = c->blk_cnt[0];
+    const int d = c->d;
+    if (c->prec == SSM_FP64) {
+        launch_pair<double>(d, c->R, false, dim3((unsigned)((np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const double*)c->Ys, c->P, c->Bp);
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<double, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const double*)c->Y, c->rff, c->rff_part));
+    } else {
+        launch_pair<float>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)((np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const float*)c->Ys, c->P, c->Bp);
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<float, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const float*)c->Y, c->rff, c->rff_part));
+    }
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_rff_final, dim3((unsigned)c->sys_list_cnt[0]), dim3(64), 0, c->stream, c->dsys_list + c->sys_list_off[0], c->dsys, c->rff_part, c->mom);
+    HIP_TRY(hipGetLastError());
+    const dim3 g((unsigned)((n + 255) / 256));
+    if (c->prec == SSM_FP64) {
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_gather_samples<double, D>), g, dim3(256), 0, c->stream, c->dsys, sys, c->P, (const double*)c->Y, c->Bp, c->mom, n, seed, U, Tt));
+    } else {
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_gather_samples<float, D>), g, dim3(256), 0, c->stream, c->dsys, sys, c->P, (const float*)c->Y, c->Bp, c->mom, n, seed, U, Tt));
+    }
+    HIP_TRY(hipGetLastError());
+    return ssm_sync(c);
+}
+
+extern "C" ssm_status ssm_mlp_forward(int32_t d, const float* master, const float* U, int64_t n, float* out, void* stream)
+{
+    if (d < 1 || d > SSM_MAX_D || !master || !U || !out || n < 1) return fail(SSM_ERR_INVALID, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    MlpPacked* W = nullptr;
+    HIP_TRY(hipMalloc((void**)&W, sizeof(MlpPacked)));
+    ssm_status s = pack_weights(master, d, W, st);
+    if (s == SSM_OK) {
+        const unsigned grid = (unsigned)std::min<int64_t>((n + 63) / 64, 4096);
+        hipLaunchKernelGGL(k_mlp_apply, dim3(grid), dim3(256), 0, st, U, n, d, W, out);
+        hipError_t he = hipGetLastError();
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+        if (he != hipSuccess) s = fail(SSM_ERR_HIP, std::string("mlp_forward: ") + hipGetErrorString(he));
+    }
+    (void)hipFree(W);
+    return s;
+}
+
+struct TrainWork {
+    TrainBufs tb{};
+    void* base = nullptr;
+    MlpPacked* W = nullptr;
+};
+
+static ssm_status alloc_train(int B, TrainWork* w)
+{
+    const size_t feat = (size_t)kKpad * B * sizeof(__bf16);
+    const size_t out = (size_t)kOutPad * B * sizeof(__bf16);
+    const size_t bytes = 4 * feat + 3 * feat + out + (size_t)(B / 64) * sizeof(float) + sizeof(MlpPacked) + 1024;
+    HIP_TRY(hipMalloc(&w->base, bytes));
+    char* p = (char*)w->base;
+    for (int q = 0; q < 4; ++q) { w->tb.act[q] = (__bf16*)p; p += feat; }
+    for (int q = 0; q < 3; ++q) { w->tb.delta[q] = (__bf16*)p; p += feat; }
+    w->tb.delta[3] = (__bf16*)p; p += out;
+    w->W = (MlpPacked*)p; p += (sizeof(MlpPacked) + 255) & ~(size_t)255;
+    w->tb.loss_part = (float*)p;
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_mlp_loss_grad(int32_t d, const float* master, const float* U, const float* Tt, int64_t n,
+                                        float* grad, double* loss, void* stream)
+{
+    if (d < 1 || d > SSM_MAX_D || !master || !U || !Tt || !grad) return fail(SSM_ERR_INVALID, "bad argument");
+    if (n < 64 || n % 64 != 0 || n > (1 << 24)) return fail(SSM_ERR_INVALID, "n must be a positive multiple of 64");
+    hipStream_t st = (hipStream_t)stream;
+    TrainWork w;
+    ssm_status s = alloc_train((int)n, &w);
+    if (s != SSM_OK) return s;
+    s = pack_weights(master, d, w.W, st);
+    hipError_t he = hipSuccess;
+    std::vector<float> lp(n / 64);
+    if (s == SSM_OK) {
+        hipLaunchKernelGGL(k_train_fwdbwd, dim3((unsigned)(n / 64)), dim3(256), 0, st, w.W, U, Tt, n, d, (int)n, 0ull, (int64_t)0, 1, w.tb);
+        hipLaunchKernelGGL(k_train_wgrad, dim3(52), dim3(64), 0, st, w.tb, d, (int)n, grad);
+        he = hipGetLastError();
+        if (he == hipSuccess) he = hipMemcpyAsync(lp.data(), w.tb.loss_part, lp.size() * sizeof(float), hipMemcpyDeviceToHost, st);
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+    }
+    (void)hipFree(w.base);
+    if (s != SSM_OK) return s;
+    if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("mlp_loss_grad: ") + hipGetErrorString(he));
+    if (loss) {
+        double t = 0.0;
+        for (float v : lp) t += v;
+        *loss = t / (double)n;
+    }
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_mlp_train(int32_t d, const float* U, const float* Tt, int64_t n_samples,
+                                    const ssm_train_cfg* cfg, float* master, float* loss_hist, void* stream)
+{
+    if (d < 1 || d > SSM_MAX_D || !U || !Tt || !master || !cfg || n_samples < 1) return fail(SSM_ERR_INVALID, "bad argument");
+    const int B = cfg->batch;
+    if (B < 64 || B % 64 != 0 || B > (1 << 20)) return fail(SSM_ERR_INVALID, "batch must be a positive multiple of 64");
+    if (cfg->steps < 1 || !(cfg->lr > 0.0f)) return fail(SSM_ERR_INVALID, "steps >= 1 and lr > 0 required");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t P = mlp_params(d);
+    TrainWork w;
+    ssm_status s = alloc_train(B, &w);
+    if (s != SSM_OK) return s;
+    float *m = nullptr, *g = nullptr, *lh = nullptr;
+    hipError_t he = hipMalloc((void**)&m, 3 * P * sizeof(float) + cfg->steps * sizeof(float));
+    if (he != hipSuccess) { (void)hipFree(w.base); return fail(SSM_ERR_OOM, "mlp_train workspace"); }
+    float* v = m + P;
+    g = v + P;
+    lh = g + P;
+    he = hipMemsetAsync(m, 0, 2 * P * sizeof(float), st);
+    const float b1 = cfg->beta1 > 0.0f ? cfg->beta1 : 0.9f, b2 = cfg->beta2 > 0.0f ? cfg->beta2 : 0.999f;
+    const float eps = cfg->eps > 0.0f ? cfg->eps : 1e-8f;
+    double c1 = 1.0, c2 = 1.0;
+    for (int64_t t = 0; t < cfg->steps && he == hipSuccess; ++t) {
+        c1 *= b1;
+        c2 *= b2;
+        s = pack_weights(master, d, w.W, st);
+        if (s != SSM_OK) break;
+        hipLaunchKernelGGL(k_train_fwdbwd, dim3((unsigned)(B / 64)), dim3(256), 0, st, w.W, U, Tt, n_samples, d, B, cfg->seed, t, 0, w.tb);
+        hipLaunchKernelGGL(k_train_wgrad, dim3(52), dim3(64), 0, st, w.tb, d, B, g);
+        hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(64), 0, st, w.tb.loss_part, B / 64, B, lh + t);
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, master, m, v, g, P, cfg->lr, b1, b2,
+                           eps, (float)(1.0 - c1), (float)(1.0 - c2));
+        he = hipGetLastError();
+    }
+    if (he == hipSuccess && loss_hist) he = hipMemcpyAsync(loss_hist, lh, cfg->steps * sizeof(float), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    (void)hipFree(m);
+    (void)hipFree(w.base);
+    if (s != SSM_OK) return s;
+    if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("mlp_train: ") + hipGetErrorString(he));
     return SSM_OK;
 }

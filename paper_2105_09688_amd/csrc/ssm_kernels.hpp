@@ -252,6 +252,7 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
                                                  int64_t P, int64_t tick, T* __restrict__ X,
                                                  T* __restrict__ Y, T* __restrict__ Ys,
                                                  const double* __restrict__ Bp,
+                                                 const float* __restrict__ surr, int use_surr,
                                                  double* __restrict__ psumX,
                                                  double* __restrict__ psumY, int64_t nblk_tot,
                                                  Flags* flags)
@@ -284,7 +285,9 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
         for (int k = 0; k < D; ++k) {
             const double y = (double)Y[k * P + slot];
             double pair = 0.0;
-            if (cf.has_pair) {
+            if (use_surr) {
+                pair = (double)surr[k * P + slot];  // learned surrogate of the pair term
+            } else if (cf.has_pair) {
                 for (int q = 0; q < S.splits; ++q) pair += Bp[((int64_t)q * D + k) * P + slot];
                 pair *= S.pair_scale;
             }

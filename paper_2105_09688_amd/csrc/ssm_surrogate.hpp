@@ -1,0 +1,659 @@
+// ssm_surrogate.hpp -- learned surrogate of the interaction drift (not in the
+// paper): random-Fourier-feature moments of mu^Y and a small MLP
+//   [y (d), C_1..C_K, S_1..S_K] -> 64 -> 64 -> 64 -> d,  SiLU hidden layers,
+// BF16 operands with FP32 accumulation on the matrix cores (MFMA), trained
+// on (y, moments, exact pair term) samples by hand-written kernels with Adam.
+//
+// Matrix-core tiles: v_mfma_f32_16x16x32_bf16.  For one wavefront (lane l):
+//   A (16 x 32): lane holds A[l % 16][8 (l / 16) + 0..7]
+//   B (32 x 16): lane holds B[8 (l / 16) + 0..7][l % 16]
+//   D (16 x 16): lane holds D[4 (l / 16) + 0..3][l % 16]
+// A wavefront always works on 16 samples (rows); features are columns.
+#pragma once
+
+#include "ssm_kernels.hpp"
+
+namespace ssm {
+
+constexpr int kRff = 16;         // frequencies; 2 kRff moments
+constexpr int kHid = 64;         // hidden width
+constexpr int kKpad = 64;        // input features padded: d + 2 kRff <= 36 -> 64
+constexpr int kOutPad = 16;      // outputs padded to one 16-column tile
+constexpr int kStride = 72;      // LDS/global row stride (bf16) of 64-wide rows (bank spread)
+constexpr int kStrideT4 = 40;    // row stride of the transposed output layer (32 used)
+constexpr int kRffWaves = 4;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Packed device weights: BF16 row-major [out][in] rows padded to kStride, and
+// the transposes needed by the backward pass; FP32 biases.
+struct MlpPacked {
+    __bf16 W1[kHid * kStride];      // [64 out][64 in (d + 2K used)]
+    __bf16 W2[kHid * kStride];
+    __bf16 W3[kHid * kStride];
+    __bf16 W4[kOutPad * kStride];   // [16 out (d used)][64 in]
+    __bf16 W2t[kHid * kStride];     // [64 in][64 out]
+    __bf16 W3t[kHid * kStride];
+    __bf16 W4t[kHid * kStrideT4];   // [64 in][32 out (d used)]
+    float b1[kHid], b2[kHid], b3[kHid], b4[kOutPad];
+};
+
+// Flat master layout (FP32), as the oracle's: W1[64][in] b1[64] W2[64][64] b2
+// W3[64][64] b3 W4[d][64] b4[d], in = d + 2 kRff.
+__host__ __device__ constexpr int mlp_in(int d) { return d + 2 * kRff; }
+__host__ __device__ constexpr int64_t mlp_params(int d)
+{
+    return (int64_t)kHid * mlp_in(d) + kHid + 2 * ((int64_t)kHid * kHid + kHid) + (int64_t)d * kHid + d;
+}
+
+struct MlpOffsets {
+    int64_t W1, b1, W2, b2, W3, b3, W4, b4;
+};
+
+__host__ __device__ inline MlpOffsets mlp_offsets(int d)
+{
+    MlpOffsets o{};
+    const int in = mlp_in(d);
+    o.W1 = 0;
+    o.b1 = o.W1 + (int64_t)kHid * in;
+    o.W2 = o.b1 + kHid;
+    o.b2 = o.W2 + kHid * kHid;
+    o.W3 = o.b2 + kHid;
+    o.b3 = o.W3 + kHid * kHid;
+    o.W4 = o.b3 + kHid;
+    o.b4 = o.W4 + (int64_t)d * kHid;
+    return o;
+}
+
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+
+__device__ __forceinline__ float silu_prime_f(float z)
+{
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// ---------------------------------------------------------------------------
+// master (flat FP32) -> packed BF16 (+ transposes), zero padding
+// ---------------------------------------------------------------------------
+__global__ void k_mlp_pack(const float* __restrict__ master, int d, MlpPacked* __restrict__ P)
+{
+    const MlpOffsets o = mlp_offsets(d);
+    const int in = mlp_in(d);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    // t indexes a (row, col) of a 64 x 72 grid, reused for every matrix
+    if (t >= kHid * kStride) return;
+    const int r = t / kStride, c = t % kStride;
+    auto bf = [](float x) { return (__bf16)x; };
+    P->W1[t] = bf((c < in) ? master[o.W1 + (int64_t)r * in + c] : 0.0f);
+    P->W2[t] = bf((c < kHid) ? master[o.W2 + (int64_t)r * kHid + c] : 0.0f);
+    P->W3[t] = bf((c < kHid) ? master[o.W3 + (int64_t)r * kHid + c] : 0.0f);
+    P->W2t[t] = bf((c < kHid) ? master[o.W2 + (int64_t)c * kHid + r] : 0.0f);  // [in r][out c]
+    P->W3t[t] = bf((c < kHid) ? master[o.W3 + (int64_t)c * kHid + r] : 0.0f);
+    if (r < kOutPad) P->W4[t] = bf((r < d && c < kHid) ? master[o.W4 + (int64_t)r * kHid + c] : 0.0f);
+    if (c < kStrideT4) P->W4t[r * kStrideT4 + c] = bf((c < d) ? master[o.W4 + (int64_t)c * kHid + r] : 0.0f);
+    if (c == 0) {
+        P->b1[r] = master[o.b1 + r];
+        P->b2[r] = master[o.b2 + r];
+        P->b3[r] = master[o.b3 + r];
+        if (r < kOutPad) P->b4[r] = (r < d) ? master[o.b4 + r] : 0.0f;
+    }
+}
+
+// Copy the forward weights (W1..W4, biases) into LDS.
+__device__ __forceinline__ void load_fwd_weights(const MlpPacked* __restrict__ P, __bf16* sW1, __bf16* sW2,
+                                                 __bf16* sW3, __bf16* sW4, float* sb)
+{
+    const int nt = blockDim.x;
+    const uint4* g1 = (const uint4*)P->W1;
+    const uint4* g2 = (const uint4*)P->W2;
+    const uint4* g3 = (const uint4*)P->W3;
+    const uint4* g4 = (const uint4*)P->W4;
+    const int n64 = kHid * kStride * 2 / 16;
+    const int n16 = kOutPad * kStride * 2 / 16;
+    for (int q = threadIdx.x; q < n64; q += nt) {
+        ((uint4*)sW1)[q] = g1[q];
+        ((uint4*)sW2)[q] = g2[q];
+        ((uint4*)sW3)[q] = g3[q];
+    }
+    for (int q = threadIdx.x; q < n16; q += nt) ((uint4*)sW4)[q] = g4[q];
+    for (int q = threadIdx.x; q < 3 * kHid + kOutPad; q += nt) {
+        float v;
+        if (q < kHid) v = P->b1[q];
+        else if (q < 2 * kHid) v = P->b2[q - kHid];
+        else if (q < 3 * kHid) v = P->b3[q - 2 * kHid];
+        else v = P->b4[q - 3 * kHid];
+        sb[q] = v;
+    }
+}
+
+// One dense layer for the wavefront's 16 samples: acc[nt] = A (16 x 64) * W^T
+// for NT column tiles; W is LDS [NT*16][kStride] (row = output feature).
+template <int NT>
+__device__ __forceinline__ void dense_tiles(const __bf16* W, const bf16x8 a[2], f32x4 acc[NT])
+{
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const bf16x8 b = *(const bf16x8*)&W[(nt * 16 + (l & 15)) * kStride + ks * 32 + 8 * (l >> 4)];
+            c = mfma_bf16(a[ks], b, c);
+        }
+        acc[nt] = c;
+    }
+}
+
+// Write 16 x (16 NT) values held in D layout into an LDS tile [16][kStride]
+// as BF16, then read them back in A layout (two K slices of 32).
+template <int NT>
+__device__ __forceinline__ void d_to_a(const f32x4 v[NT], __bf16* tile, bf16x8 a[2])
+{
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tile[(4 * (l >> 4) + i) * kStride + nt * 16 + (l & 15)] = (__bf16)v[nt][i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) a[ks] = *(const bf16x8*)&tile[(l & 15) * kStride + ks * 32 + 8 * (l >> 4)];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Input features of one sample in A layout: lane (l) holds features
+// k = 32 ks + 8 (l / 16) + 0..7 of sample l % 16:  u = [y_0..y_{d-1}, m_0..m_{2K-1}, 0...].
+// y: the sample's coordinates (y0..y3), mom: moments in LDS.
+__device__ __forceinline__ void build_input(float y0, float y1, float y2, float y3, const float* mom, int d,
+                                            bf16x8 a[2])
+{
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = ks * 32 + 8 * (l >> 4) + i;
+            float v = 0.0f;
+            if (k < d) v = (k == 0) ? y0 : (k == 1) ? y1 : (k == 2) ? y2 : y3;
+            else if (k < d + 2 * kRff) v = mom[k - d];
+            a[ks][i] = (__bf16)v;
+        }
+}
+
+// Forward pass of the wavefront's 16 samples.  Returns the output tile
+// (D layout, columns 0..d-1 valid, bias added) and optionally the
+// pre-activations z1..z3 (D layout) for the backward pass.
+__device__ __forceinline__ void mlp_forward16(const __bf16* sW1, const __bf16* sW2, const __bf16* sW3,
+                                              const __bf16* sW4, const float* sb, bf16x8 a[2],
+                                              __bf16* tile, f32x4 z[3][4], f32x4& out, bf16x8 act[3][2])
+{
+    const int l = threadIdx.x & 63;
+    const __bf16* Ws[3] = {sW1, sW2, sW3};
+#pragma unroll
+    for (int layer = 0; layer < 3; ++layer) {
+        f32x4 acc[4];
+        dense_tiles<4>(Ws[layer], a, acc);
+        f32x4 h[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const float bias = sb[layer * kHid + nt * 16 + (l & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float zz = acc[nt][i] + bias;
+                z[layer][nt][i] = zz;
+                h[nt][i] = silu_f(zz);
+            }
+        }
+        d_to_a<4>(h, tile, a);
+        act[layer][0] = a[0];
+        act[layer][1] = a[1];
+    }
+    f32x4 o[1];
+    dense_tiles<1>(sW4, a, o);
+    const float b4 = sb[3 * kHid + (l & 15)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[i] = o[0][i] + b4;
+}
+
+// ---------------------------------------------------------------------------
+// RFF moments: per-block sums of cos / sin(omega_k . y) (FP32 within a block,
+// FP64 partials), then one block per system reduces its partials in order.
+// ---------------------------------------------------------------------------
+struct RffFreq {
+    float w[kRff][kMaxD];  // omega_k (already divided by ell)
+};
+
+template <typename T, int D>
+__global__ __launch_bounds__(kBlk) void k_rff_partial(const BlkItem* __restrict__ items,
+                                                      const SysDev* __restrict__ sys, int64_t P,
+                                                      const T* __restrict__ Y, RffFreq fq,
+                                                      double* __restrict__ part /*[nblk_tot][2K]*/)
+{
+    __shared__ float red[2 * kRff][kBlk + 1];
+    const BlkItem it = items[blockIdx.x];
+    const SysDev S = sys[it.sys];
+    const int i = it.blk * kBlk + threadIdx.x;
+    const bool valid = i < S.N;
+    float y[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) y[k] = valid ? (float)Y[k * P + S.off + i] : 0.0f;
+#pragma unroll
+    for (int q = 0; q < kRff; ++q) {
+        float ph = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) ph = fmaf(fq.w[q][k], y[k], ph);
+        float sn, cs;
+        __sincosf(ph, &sn, &cs);
+        red[q][threadIdx.x] = valid ? cs : 0.0f;
+        red[kRff + q][threadIdx.x] = valid ? sn : 0.0f;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kRff) {
+        double s = 0.0;
+        for (int t = 0; t < kBlk; ++t) s += (double)red[threadIdx.x][t];
+        part[(int64_t)(S.blk0 + it.blk) * (2 * kRff) + threadIdx.x] = s;
+    }
+}
+
+// one block per listed system: mom[sys][q] = (1/N) sum of its block partials
+__global__ void k_rff_final(const int32_t* __restrict__ sys_list, const SysDev* __restrict__ sys,
+                            const double* __restrict__ part, float* __restrict__ mom)
+{
+    const int s = sys_list[blockIdx.x];
+    const SysDev S = sys[s];
+    const int q = threadIdx.x;
+    if (q >= 2 * kRff) return;
+    double acc = 0.0;
+    for (int b = 0; b < S.nblk; ++b) acc += part[(int64_t)(S.blk0 + b) * (2 * kRff) + q];
+    mom[(int64_t)s * (2 * kRff) + q] = (float)(acc / (double)S.N);
+}
+
+// ---------------------------------------------------------------------------
+// Inference: surrogate pair term for every particle of the listed blocks.
+// Each wavefront takes 16 consecutive particles of a 256-particle block.
+// Writes surr[k][slot] (FP32) for k < d.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_mlp_infer(const BlkItem* __restrict__ items, int n_items,
+                                                   const SysDev* __restrict__ sys, int64_t P,
+                                                   const T* __restrict__ Y, const float* __restrict__ mom,
+                                                   const MlpPacked* __restrict__ W, float* __restrict__ surr)
+{
+    __shared__ __align__(16) __bf16 sW1[kHid * kStride];
+    __shared__ __align__(16) __bf16 sW2[kHid * kStride];
+    __shared__ __align__(16) __bf16 sW3[kHid * kStride];
+    __shared__ __align__(16) __bf16 sW4[kOutPad * kStride];
+    __shared__ float sb[3 * kHid + kOutPad];
+    __shared__ __align__(16) __bf16 tiles[4][16 * kStride];
+    __shared__ float smom[2 * kRff];
+    load_fwd_weights(W, sW1, sW2, sW3, sW4, sb);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    const int l = threadIdx.x & 63;
+    for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
+        const BlkItem it = items[itx];
+        const SysDev S = sys[it.sys];
+        __syncthreads();
+        if (threadIdx.x < 2 * kRff) smom[threadIdx.x] = mom[(int64_t)it.sys * (2 * kRff) + threadIdx.x];
+        __syncthreads();
+        // 256 particles per block item, 16 per wavefront pass
+        for (int sub = wave; sub < kBlk / 16; sub += 4) {
+            const int i0 = it.blk * kBlk + sub * 16;
+            if (i0 >= S.N) continue;  // wave-uniform
+            const int i = i0 + (l & 15);
+            float y[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int k = 0; k < D; ++k) y[k] = (i < S.N) ? (float)Y[k * P + S.off + i] : 0.0f;
+            bf16x8 a[2];
+            build_input(y[0], y[1], y[2], y[3], smom, D, a);
+            f32x4 z[3][4];
+            bf16x8 act[3][2];
+            f32x4 out;
+            mlp_forward16(sW1, sW2, sW3, sW4, sb, a, tiles[wave], z, out, act);
+            // out: rows 4 (l/16) + r (samples), column l % 16 (output component)
+            const int comp = l & 15;
+            if (comp < D) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ii = i0 + 4 * (l >> 4) + r;
+                    if (ii < S.N) surr[(int64_t)comp * P + S.off + ii] = out[r];
+                }
+            }
+        }
+    }
+}
+
+// Inference on explicit feature rows U [n][d + 2K] -> out [n][d].
+__global__ __launch_bounds__(256) void k_mlp_apply(const float* __restrict__ U, int64_t n, int d,
+                                                   const MlpPacked* __restrict__ W, float* __restrict__ out)
+{
+    __shared__ __align__(16) __bf16 sW1[kHid * kStride];
+    __shared__ __align__(16) __bf16 sW2[kHid * kStride];
+    __shared__ __align__(16) __bf16 sW3[kHid * kStride];
+    __shared__ __align__(16) __bf16 sW4[kOutPad * kStride];
+    __shared__ float sb[3 * kHid + kOutPad];
+    __shared__ __align__(16) __bf16 tiles[4][16 * kStride];
+    load_fwd_weights(W, sW1, sW2, sW3, sW4, sb);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    const int l = threadIdx.x & 63;
+    const int in = d + 2 * kRff;
+    for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 16; r0 < n; r0 += (int64_t)gridDim.x * 64) {
+        const int64_t row = r0 + (l & 15);
+        bf16x8 a[2];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = ks * 32 + 8 * (l >> 4) + i;
+                a[ks][i] = (__bf16)((row < n && k < in) ? U[row * in + k] : 0.0f);
+            }
+        f32x4 z[3][4];
+        bf16x8 act[3][2];
+        f32x4 o;
+        mlp_forward16(sW1, sW2, sW3, sW4, sb, a, tiles[wave], z, o, act);
+        const int comp = l & 15;
+        if (comp < d) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t rr = r0 + 4 * (l >> 4) + r;
+                if (rr < n) out[rr * d + comp] = o[r];
+            }
+        }
+    }
+}
+
+// Sampled training pairs of one system: u = [y_i, moments], t = exact pair term
+// at particle i, for n draws of i (Philox tag 4, counter (q, 0, 1)).
+template <typename T, int D>
+__global__ void k_gather_samples(const SysDev* __restrict__ sys, int s, int64_t P, const T* __restrict__ Y,
+                                 const double* __restrict__ Bp, const float* __restrict__ mom, int64_t n,
+                                 uint64_t seed, float* __restrict__ U, float* __restrict__ Tt)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const SysDev S = sys[s];
+    const Block4 rb = philox4x64_10((uint64_t)q, 0ull, 1ull, 4ull << 32, seed, 0ull);
+    const int64_t i = (int64_t)(rb.w[0] % (uint64_t)S.N);
+    const int64_t slot = S.off + i;
+    const int in = D + 2 * kRff;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        U[q * in + k] = (float)Y[k * P + slot];
+        double pair = 0.0;
+        for (int p = 0; p < S.splits; ++p) pair += Bp[((int64_t)p * D + k) * P + slot];
+        Tt[q * D + k] = (float)(pair * S.pair_scale);
+    }
+    for (int m = 0; m < 2 * kRff; ++m) U[q * in + D + m] = mom[(int64_t)s * (2 * kRff) + m];
+}
+
+// ---------------------------------------------------------------------------
+// Training.  k_train_fwdbwd: 64 samples per block (16 per wavefront), drawn
+// with replacement by Philox (tag 4) from the sample set; forward, loss and
+// back-propagated deltas; activations and deltas stored feature-major
+// ([feature][batch], BF16) for the weight-gradient kernel.
+// ---------------------------------------------------------------------------
+// Row `row` of minibatch `step`: a uniform draw (with replacement) from the
+// sample set, Philox stream tag 4; or row itself for sequential batches.
+__device__ __forceinline__ int64_t sample_index(int row, int64_t step, uint64_t seed, int64_t n, int sequential)
+{
+    if (sequential) return (int64_t)row % n;
+    const Block4 rb = philox4x64_10((uint64_t)row, (uint64_t)step, 0ull, 4ull << 32, seed, 0ull);
+    return (int64_t)(rb.w[0] % (uint64_t)n);
+}
+
+struct TrainBufs {
+    __bf16* act[4];    // act[0]: inputs [64][B]; act[1..3]: SiLU outputs [64][B]
+    __bf16* delta[4];  // delta[0..2]: dL/dz of hidden layers 1..3 [64][B]; delta[3]: dL/dy [16][B]
+    float* loss_part;  // [B / 64]
+};
+
+__global__ __launch_bounds__(256) void k_train_fwdbwd(const MlpPacked* __restrict__ W, const float* __restrict__ U,
+                                                      const float* __restrict__ Tg, int64_t n_samples, int d,
+                                                      int B, uint64_t seed, int64_t step, int sequential,
+                                                      TrainBufs tb)
+{
+    __shared__ __align__(16) __bf16 sW1[kHid * kStride];
+    __shared__ __align__(16) __bf16 sW2[kHid * kStride];
+    __shared__ __align__(16) __bf16 sW3[kHid * kStride];
+    __shared__ __align__(16) __bf16 sW4[kOutPad * kStride];
+    __shared__ __align__(16) __bf16 sW2t[kHid * kStride];
+    __shared__ __align__(16) __bf16 sW3t[kHid * kStride];
+    __shared__ __align__(16) __bf16 sW4t[kHid * kStrideT4];
+    __shared__ float sb[3 * kHid + kOutPad];
+    __shared__ __align__(16) __bf16 tiles[4][16 * kStride];
+    __shared__ float lossw[4];
+    load_fwd_weights(W, sW1, sW2, sW3, sW4, sb);
+    {
+        const int n64 = kHid * kStride * 2 / 16;
+        const int n4 = kHid * kStrideT4 * 2 / 16;
+        for (int q = threadIdx.x; q < n64; q += blockDim.x) {
+            ((uint4*)sW2t)[q] = ((const uint4*)W->W2t)[q];
+            ((uint4*)sW3t)[q] = ((const uint4*)W->W3t)[q];
+        }
+        for (int q = threadIdx.x; q < n4; q += blockDim.x) ((uint4*)sW4t)[q] = ((const uint4*)W->W4t)[q];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    const int l = threadIdx.x & 63;
+    const int in = d + 2 * kRff;
+    const int b0 = blockIdx.x * 64 + wave * 16;  // first batch row of this wavefront
+    // this lane's sample (A layout row l % 16)
+    const int brow = b0 + (l & 15);
+    const int64_t sidx = sample_index(brow, step, seed, n_samples, sequential);
+    bf16x8 a[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = ks * 32 + 8 * (l >> 4) + i;
+            a[ks][i] = (__bf16)((k < in) ? U[sidx * in + k] : 0.0f);
+        }
+    // inputs, feature-major
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) tb.act[0][(int64_t)(ks * 32 + 8 * (l >> 4) + i) * B + brow] = a[ks][i];
+
+    f32x4 z[3][4];
+    bf16x8 act[3][2];
+    f32x4 out;
+    mlp_forward16(sW1, sW2, sW3, sW4, sb, a, tiles[wave], z, out, act);
+
+    // dL/dy in D layout: rows = samples 4 (l/16) + r, column = output l % 16
+    const int comp = l & 15;
+    f32x4 dy;
+    float lsum = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = b0 + 4 * (l >> 4) + r;
+        float g = 0.0f;
+        if (comp < d) {
+            const int64_t si = sample_index(row, step, seed, n_samples, sequential);
+            const float res = out[r] - Tg[si * d + comp];
+            lsum += res * res;
+            g = 2.0f * res / (float)B;
+        }
+        dy[r] = g;
+        tb.delta[3][(int64_t)comp * B + row] = (__bf16)g;
+    }
+    // activations of the hidden layers, feature-major, from the D-layout values
+    // (recomputed SiLU of z, rounded to BF16 exactly as the forward pass fed them)
+#pragma unroll
+    for (int layer = 0; layer < 3; ++layer)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                tb.act[layer + 1][(int64_t)(nt * 16 + (l & 15)) * B + b0 + 4 * (l >> 4) + r] =
+                    (__bf16)silu_f(z[layer][nt][r]);
+
+    // back-propagation: delta_3 = (dy W4) * silu'(z3) ...
+    bf16x8 ga[2];
+    {
+        // dy (16 x 16, D layout) -> A layout with K = 32 (outputs 16..31 zero)
+        f32x4 v[1] = {dy};
+        __bf16* tile = tiles[wave];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tile[(4 * (l >> 4) + i) * kStride + (l & 15)] = (__bf16)v[0][i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tile[(4 * (l >> 4) + i) * kStride + 16 + (l & 15)] = (__bf16)0.0f;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        ga[0] = *(const bf16x8*)&tile[(l & 15) * kStride + 8 * (l >> 4)];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    f32x4 g[4];
+    // layer 4 backward: K = 32 (padded outputs), B operand from W4t [in][out]
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+        const bf16x8 b = *(const bf16x8*)&sW4t[(nt * 16 + (l & 15)) * kStrideT4 + 8 * (l >> 4)];
+        c = mfma_bf16(ga[0], b, c);
+        g[nt] = c;
+    }
+    const __bf16* Wt[2] = {sW3t, sW2t};
+#pragma unroll
+    for (int layer = 2; layer >= 0; --layer) {
+        // delta of hidden layer (layer+1) = g * silu'(z)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) g[nt][r] *= silu_prime_f(z[layer][nt][r]);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                tb.delta[layer][(int64_t)(nt * 16 + (l & 15)) * B + b0 + 4 * (l >> 4) + r] = (__bf16)g[nt][r];
+        if (layer == 0) break;
+        d_to_a<4>(g, tiles[wave], ga);
+        f32x4 nxt[4];
+        dense_tiles<4>(Wt[2 - layer], ga, nxt);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) g[nt] = nxt[nt];
+    }
+    // loss partial of this block, fixed order
+    float ls = lsum;
+    for (int off = 32; off > 0; off >>= 1) ls += __shfl_down(ls, off, 64);
+    if (l == 0) lossw[wave] = ls;
+    __syncthreads();
+    if (threadIdx.x == 0) tb.loss_part[blockIdx.x] = (lossw[0] + lossw[1]) + (lossw[2] + lossw[3]);
+}
+
+// Weight gradients: one wavefront per 16 x 16 tile of a layer's weight matrix,
+// summing over the batch with K = 32 samples per MFMA (fixed order); the
+// tiles of input-column block 0 also produce the bias gradients.
+// Tiles: layer 1: 4 x 4, layers 2 and 3: 4 x 4, layer 4: 1 x 4  -> 52.
+__global__ __launch_bounds__(64) void k_train_wgrad(TrainBufs tb, int d, int B, float* __restrict__ grad)
+{
+    int t = blockIdx.x;
+    int layer, ot, it;
+    if (t < 48) {
+        layer = t / 16;
+        ot = (t % 16) / 4;
+        it = t % 4;
+    } else {
+        layer = 3;
+        ot = 0;
+        it = t - 48;
+    }
+    const int l = threadIdx.x & 63;
+    const __bf16* dl = tb.delta[layer];  // [out][B]
+    const __bf16* al = tb.act[layer];    // [in][B]
+    const int nout = layer < 3 ? kHid : d;
+    const int nin = layer == 0 ? d + 2 * kRff : kHid;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4 bacc = {0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 ones;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ones[i] = (__bf16)1.0f;
+    const int orow = ot * 16 + (l & 15);
+    const int icol = it * 16 + (l & 15);
+    for (int k0 = 0; k0 < B; k0 += 32) {
+        bf16x8 a, b;
+        const int kk = k0 + 8 * (l >> 4);
+        if (layer == 3 && orow >= kOutPad) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a[i] = (__bf16)0.0f;
+        } else {
+            a = *(const bf16x8*)&dl[(int64_t)orow * B + kk];
+        }
+        b = *(const bf16x8*)&al[(int64_t)icol * B + kk];
+        acc = mfma_bf16(a, b, acc);
+        if (it == 0) bacc = mfma_bf16(a, ones, bacc);
+    }
+    const MlpOffsets o = mlp_offsets(d);
+    const int64_t wo[4] = {o.W1, o.W2, o.W3, o.W4};
+    const int64_t bo[4] = {o.b1, o.b2, o.b3, o.b4};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int orr = ot * 16 + 4 * (l >> 4) + r;  // D row = output feature
+        const int ic = it * 16 + (l & 15);          // D column = input feature
+        if (orr < nout && ic < nin) grad[wo[layer] + (int64_t)orr * nin + ic] = acc[r];
+        if (it == 0 && (l & 15) == 0 && orr < nout) grad[bo[layer] + orr] = bacc[r];
+    }
+}
+
+// Adam on the flat FP32 master weights (Kingma & Ba), bias-corrected.
+__global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const float gg = g[q];
+    const float mm = b1 * m[q] + (1.0f - b1) * gg;
+    const float vv = b2 * v[q] + (1.0f - b2) * gg * gg;
+    m[q] = mm;
+    v[q] = vv;
+    w[q] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// Squared surrogate error and squared exact pair term, per update block
+// (fixed-order block sums), for the listed blocks.
+template <typename T, int D>
+__global__ __launch_bounds__(kBlk) void k_surr_err(const BlkItem* __restrict__ items,
+                                                   const SysDev* __restrict__ sys, int64_t P,
+                                                   const double* __restrict__ Bp,
+                                                   const float* __restrict__ surr,
+                                                   double* __restrict__ err_part /*[nblk][2]*/)
+{
+    __shared__ double red[kBlk];
+    const BlkItem it = items[blockIdx.x];
+    const SysDev S = sys[it.sys];
+    const int i = it.blk * kBlk + threadIdx.x;
+    double e2 = 0.0, b2 = 0.0;
+    if (i < S.N) {
+        const int64_t slot = S.off + i;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            double pair = 0.0;
+            for (int q = 0; q < S.splits; ++q) pair += Bp[((int64_t)q * D + k) * P + slot];
+            pair *= S.pair_scale;
+            const double df = (double)surr[k * P + slot] - pair;
+            e2 += df * df;
+            b2 += pair * pair;
+        }
+    }
+    const double se = block_sum(e2, red);
+    const double sb = block_sum(b2, red);
+    if (threadIdx.x == 0) {
+        err_part[2 * blockIdx.x] = se;
+        err_part[2 * blockIdx.x + 1] = sb;
+    }
+}
+
+}  // namespace ssm

@@ -128,6 +128,23 @@ class SSM:
         check(_lib.load().ssm_sqdiff(self._h, sys, other._h, other_sys, C.byref(r)))
         return r.value
 
+    # -- learned surrogate ----------------------------------------------------
+    def surrogate_load(self, master) -> None:
+        """Load FP32 master weights (numpy or CPU tensor, flat layout of include/ssm.h)."""
+        m = np.ascontiguousarray(np.asarray(master, dtype=np.float32).ravel())
+        check(_lib.load().ssm_surrogate_load(self._h, m.ctypes.data, m.size))
+
+    def surrogate_enable(self, check_every: int = 16, tol: float = 1e-3) -> None:
+        check(_lib.load().ssm_surrogate_enable(self._h, int(check_every), float(tol)))
+
+    def surrogate_samples(self, n: int, seed: int, sys: int = 0):
+        """(U [n][d+32], T [n][d]) float32 device tensors from the current state."""
+        torch = _torch()
+        U = torch.empty((n, self.d + 32), dtype=torch.float32, device="cuda")
+        T = torch.empty((n, self.d), dtype=torch.float32, device="cuda")
+        check(_lib.load().ssm_surrogate_samples(self._h, sys, n, seed, U.data_ptr(), T.data_ptr()))
+        return U, T
+
     def profile(self, enable: bool = True) -> None:
         check(_lib.load().ssm_profile(self._h, 1 if enable else 0))
 
@@ -194,3 +211,51 @@ def philox_blocks(ctr, key, count: int, device="cuda"):
     k = [int(v) & (2 ** 64 - 1) for v in key]
     check(_lib.load().ssm_philox_blocks(c[0], c[1], c[2], c[3], k[0], k[1], count, out.data_ptr(), _cur_stream()))
     return out
+
+
+# -------------------------------------------------------------------------- surrogate network
+def mlp_num_params(d: int) -> int:
+    return int(_lib.load().ssm_mlp_num_params(d))
+
+
+def mlp_init(d: int, seed: int = 0):
+    """Seeded initial FP32 master weights (uniform +-sqrt(6/(fan_in+fan_out)) per matrix, zero biases)."""
+    rng = np.random.Generator(np.random.Philox(key=seed + 5))
+    shapes = [(64, d + 32), (64, 64), (64, 64), (d, 64)]
+    parts = []
+    for (o, i) in shapes:
+        lim = np.sqrt(6.0 / (i + o))
+        parts.append(rng.uniform(-lim, lim, size=o * i))
+        parts.append(np.zeros(o))
+    out = np.concatenate(parts).astype(np.float32)
+    assert out.size == mlp_num_params(d)
+    return out
+
+
+def mlp_forward(d: int, master, U):
+    """Network output for device float32 features U [n][d+32]; master: device float32 tensor."""
+    torch = _torch()
+    out = torch.empty((U.shape[0], d), dtype=torch.float32, device=U.device)
+    check(_lib.load().ssm_mlp_forward(d, master.data_ptr(), U.contiguous().data_ptr(), U.shape[0],
+                                      out.data_ptr(), _cur_stream()))
+    return out
+
+
+def mlp_loss_grad(d: int, master, U, T):
+    """(loss, grad) for the rows of U, T in order (row count a multiple of 64)."""
+    torch = _torch()
+    g = torch.zeros_like(master)
+    loss = C.c_double()
+    check(_lib.load().ssm_mlp_loss_grad(d, master.data_ptr(), U.contiguous().data_ptr(), T.contiguous().data_ptr(),
+                                        U.shape[0], g.data_ptr(), C.byref(loss), _cur_stream()))
+    return loss.value, g
+
+
+def mlp_train(d: int, master, U, T, steps: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0):
+    """Adam on the device master weights (in place); returns the per-step loss history."""
+    cfg = _lib.TrainCfg()
+    cfg.steps, cfg.batch, cfg.lr, cfg.seed = int(steps), int(batch), float(lr), int(seed)
+    hist = np.zeros(int(steps), dtype=np.float32)
+    check(_lib.load().ssm_mlp_train(d, U.contiguous().data_ptr(), T.contiguous().data_ptr(), U.shape[0],
+                                    C.byref(cfg), master.data_ptr(), hist.ctypes.data, _cur_stream()))
+    return hist

@@ -1,0 +1,164 @@
+"""Learned surrogate of the pairwise term (an extension, not in the paper):
+its kernels against the FP64 oracle, and its use inside the SSM step."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_09688_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+D = 2
+IN = D + 32
+
+
+def _say(msg):
+    print(f"[gpu-surrogate] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return torch
+
+
+def _bf16(x):
+    """Round float values to bfloat16 (nearest even), returned as float64."""
+    import torch
+    return torch.tensor(np.asarray(x, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _small_w(N=4096, T=2.0 ** -4):
+    w = W.surrogate_d2(N=N, h=2.0 ** -9, h_fine=2.0 ** -9)
+    w["T"] = T
+    return w
+
+
+def test_mfma_forward_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    from paper_2105_09688_amd.ssm import mlp_forward, mlp_init
+    p = mlp_init(D, seed=1)
+    rng = np.random.default_rng(2)
+    U = rng.normal(size=(1000, IN)).astype(np.float32)
+    _say("mlp forward")
+    got = mlp_forward(D, torch.tensor(p, device="cuda"), torch.tensor(U, device="cuda")).cpu().numpy()
+    ref = oracle.mlp_forward(_bf16(p), _bf16(U), IN, 64, D)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    _say(f"forward rel err {rel:.3e}")
+    assert rel <= 1e-2
+
+
+def test_mfma_gradient_matches_oracle(torch_cuda):
+    """GPU BF16/FP32 gradient vs the oracle's FP64 back-propagation at the same
+    BF16-rounded weights and inputs: per-tensor relative error <= 2e-2 and
+    cosine >= 0.999."""
+    torch = torch_cuda
+    from paper_2105_09688_amd.ssm import mlp_init, mlp_loss_grad
+    p = mlp_init(D, seed=3)
+    p += np.random.default_rng(4).normal(size=p.size).astype(np.float32) * 0.05  # nonzero biases
+    rng = np.random.default_rng(5)
+    U = rng.normal(size=(512, IN)).astype(np.float32)
+    T = rng.normal(size=(512, D)).astype(np.float32) * 0.3
+    _say("mlp gradient")
+    loss, g = mlp_loss_grad(D, torch.tensor(p, device="cuda"), torch.tensor(U, device="cuda"),
+                            torch.tensor(T, device="cuda"))
+    g = g.cpu().numpy().astype(np.float64)
+    loss_ref, g_ref = oracle.mlp_loss_grad(_bf16(p), _bf16(U), T.astype(np.float64), IN, 64, D)
+    assert loss == pytest.approx(loss_ref, rel=1e-2)
+    sizes = [64 * IN, 64, 64 * 64, 64, 64 * 64, 64, D * 64, D]
+    off = 0
+    for k, n in enumerate(sizes):
+        a, b = g[off:off + n], g_ref[off:off + n]
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+        _say(f"tensor {k}: rel {rel:.3e} cos {cos:.6f}")
+        assert rel <= 2e-2 and cos >= 0.999, k
+        off += n
+
+
+def test_training_fits_a_smooth_target(torch_cuda):
+    torch = torch_cuda
+    from paper_2105_09688_amd.ssm import mlp_forward, mlp_init, mlp_train
+    rng = np.random.default_rng(6)
+    U = rng.normal(size=(20000, IN)).astype(np.float32)
+    T = np.stack([np.tanh(U[:, 0] - 0.5 * U[:, 3]), 0.3 * U[:, 1] * U[:, 2]], axis=1).astype(np.float32)
+    p = torch.tensor(mlp_init(D, seed=7), device="cuda")
+    Ud, Td = torch.tensor(U, device="cuda"), torch.tensor(T, device="cuda")
+    _say("training")
+    hist = mlp_train(D, p, Ud, Td, steps=1500, batch=1024, lr=3e-3, seed=1)
+    assert np.all(np.isfinite(hist))
+    first, last = float(np.mean(hist[:20])), float(np.mean(hist[-50:]))
+    _say(f"loss {first:.4f} -> {last:.5f}")
+    assert last < 0.05 * first
+    out = mlp_forward(D, p, Ud).cpu().numpy()
+    assert np.mean(np.sum((out - T) ** 2, axis=1)) < 0.1 * np.mean(np.sum(T ** 2, axis=1))
+
+
+def test_samples_are_moments_and_exact_pair_terms(torch_cuda):
+    from paper_2105_09688_amd.ssm import SSM
+    w = _small_w(N=3000)
+    with SSM(w, precision="fp32_kahan") as s:
+        s.step(3)
+        Y = s.state(0, "y")
+        U, T = s.surrogate_samples(500, seed=11)
+    U, T = U.cpu().numpy().astype(np.float64), T.cpu().numpy().astype(np.float64)
+    om = oracle.rff_omegas(w["seed"], D, 16, w["b"]["ell"])
+    mref = oracle.rff_moments(Y, om)
+    assert np.max(np.abs(U[:, D:] - mref[None, :])) <= 2e-5
+    lookup = {(float(Y[0, i]), float(Y[1, i])): i for i in range(Y.shape[1])}
+    idx = np.array([lookup[(U[q, 0], U[q, 1])] for q in range(U.shape[0])])
+    Kref = oracle.pair_sum_at(Y, w["b"]["ell"], idx) * w["b"]["g"]
+    assert np.max(np.abs(T - Kref.T)) <= 2e-6
+
+
+def test_surrogate_step_and_fallback(torch_cuda):
+    """A surrogate that fails its checks leaves the run identical to the
+    exact one; one that is always accepted changes the run only by its own
+    error; the counters reflect both."""
+    torch = torch_cuda
+    from paper_2105_09688_amd.ssm import SSM, mlp_init, mlp_train
+    w = _small_w()
+    # training pairs from another ensemble
+    wt = W.with_systems(w, [(4096, 1, 2.0 ** -9)])
+    Us, Ts = [], []
+    with SSM(wt, precision="fp32_kahan") as s:
+        for t in range(8):
+            U, T = s.surrogate_samples(4096, seed=t)
+            Us.append(U)
+            Ts.append(T)
+            s.step(4)
+    U, T = torch.cat(Us), torch.cat(Ts)
+    p = torch.tensor(mlp_init(D, seed=0), device="cuda")
+    hist = mlp_train(D, p, U, T, steps=800, batch=1024, lr=2e-3, seed=3)
+    _say(f"train loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    master = p.cpu().numpy()
+    with SSM(w, precision="fp32_kahan") as ex:
+        ex.run()
+        X_exact = ex.state(0)
+    # impossible tolerance: every check fails, every tick is exact
+    with SSM(w, precision="fp32_kahan") as s:
+        s.surrogate_load(master)
+        s.surrogate_enable(check_every=4, tol=1e-12)
+        s.run()
+        info = s.info()
+        X_fb = s.state(0)
+    _say(f"fallback run: {info['surr_checks']} checks, last err {info['surr_last_err']:.3e}")
+    assert info["surr_ticks"] == 0 and info["surr_checks"] == 8
+    assert info["surr_fallback_ticks"] == 32 - 8
+    assert np.array_equal(X_fb, X_exact)
+    # accepting tolerance: every non-check tick uses the network
+    with SSM(w, precision="fp32_kahan") as s:
+        s.surrogate_load(master)
+        s.surrogate_enable(check_every=4, tol=1e9)
+        s.run()
+        info = s.info()
+        X_s = s.state(0)
+    _say(f"surrogate run: {info['surr_ticks']} ticks, max err {info['surr_max_err']:.3e}")
+    assert info["surr_ticks"] == 32 - 8 and info["surr_fallback_ticks"] == 0
+    assert 0.0 < info["surr_max_err"] < 1.0
+    d_rms = float(np.sqrt(np.mean(np.sum((X_s - X_exact) ** 2, axis=0))))
+    _say(f"pathwise rms difference to exact: {d_rms:.3e}")
+    assert d_rms < 0.05
