@@ -72,10 +72,12 @@ def cpu_baseline(w, budget_s: float):
             "sample": f"{steps} full time steps of the same system (N={N}, d={w['d']}), FP64, from X_0"}
 
 
-def timed_run(SSM, w, precision, stream, steps=None, profile=True, **kw):
+def timed_run(SSM, w, precision, stream, steps=None, profile=True, setup=None, **kw):
     """Fresh context, then `steps` ticks (default: to T) between HIP events on its stream."""
     import torch
     s = SSM(w, precision=precision, stream=stream, **kw)
+    if setup is not None:
+        setup(s)
     s.sync()
     if profile:
         s.profile(True)
@@ -175,6 +177,105 @@ def study_batched(args, stream):
     return out
 
 
+def study_surrogate(args, stream):
+    """Learned surrogate (d=2, N=2^20, h=2^-9, T=1): training pairs from exact
+    runs of other ensembles, Adam on the GPU, then the exact run and surrogate
+    runs (exact check every 16 steps) of the same paths."""
+    import numpy as np
+    import torch
+    from paper_2105_09688_amd import workloads as W
+    from paper_2105_09688_amd.ssm import SSM, mlp_init, mlp_train
+    prec = args.precision
+    w = W.surrogate_d2(N=args.N or 2 ** 20)
+    N, _, h = w["systems"][0]
+    d = w["d"]
+    n_runs, N_train, per_snap, every = 2, 2 ** 18, 2 ** 16, 16
+    t0 = time.perf_counter()
+    Us, Ts = [], []
+    for r in range(n_runs):
+        wt = W.with_systems(w, [(N_train, 1 + r, h)])
+        with SSM(wt, precision=prec, stream=stream) as s:
+            ticks = s.info()["ticks_total"]
+            for t in range(0, ticks, every):
+                U, T = s.surrogate_samples(per_snap, seed=1000 * (r + 1) + t)
+                Us.append(U)
+                Ts.append(T)
+                s.step(every)
+    U, T = torch.cat(Us), torch.cat(Ts)
+    t_data = time.perf_counter() - t0
+    print(f"[surrogate] {U.shape[0]} training pairs in {t_data:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    p = torch.tensor(mlp_init(d, seed=0), device="cuda")
+    hist = []
+    for steps, lr, seed in ((args.train_steps, 1e-3, 1), (args.train_steps // 2, 2e-4, 2), (args.train_steps // 4, 4e-5, 3)):
+        hist.append(mlp_train(d, p, U, T, steps=steps, batch=4096, lr=lr, seed=seed))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    hist = np.concatenate(hist)
+    print(f"[surrogate] training {hist.size} steps in {t_train:.1f} s, loss {hist[:50].mean():.3e} -> "
+          f"{hist[-200:].mean():.3e}", file=sys.stderr, flush=True)
+    master = p.cpu().numpy()
+    tsq = float(T.pow(2).sum(dim=1).mean())
+
+    ex, dt_ex, n = timed_run(SSM, w, prec, stream)
+    X_ex = ex.state(0)
+    m_ex, v_ex = ex.moments(0)
+    info_ex = ex.info()
+    ex.close()
+    print(f"[surrogate] exact run {dt_ex:.1f} s", file=sys.stderr, flush=True)
+    runs = {}
+    for tol in (1e-3, 1e-2, 1e9):
+        def setup(s, tol=tol):
+            s.surrogate_load(master)
+            s.surrogate_enable(check_every=every, tol=tol)
+        su, dt_su, _ = timed_run(SSM, w, prec, stream, setup=setup)
+        info = su.info()
+        X = su.state(0)
+        m, v = su.moments(0)
+        su.close()
+        D = X - X_ex
+        runs[f"tol={tol:g}"] = {
+            "seconds": dt_su, "particle_steps_per_s": N * n / dt_su, "speedup_vs_exact": dt_ex / dt_su,
+            "checks": info["surr_checks"], "surrogate_ticks": info["surr_ticks"],
+            "fallback_ticks": info["surr_fallback_ticks"], "check_rel_err_last": info["surr_last_err"],
+            "check_rel_err_max": info["surr_max_err"], "check_rel_err_last_without_gain": info["surr_last_raw_err"],
+            "gain_last": info["surr_gain"],
+            "pathwise_rms_vs_exact": float(np.sqrt(np.sum(D * D) / N)),
+            "mean_diff": [float(x) for x in m - m_ex], "var_diff": [float(x) for x in v - v_ex],
+        }
+        print(f"[surrogate] tol {tol:g}: {dt_su:.2f} s, {info['surr_ticks']} surrogate ticks, "
+              f"max err {info['surr_max_err']:.3e}", file=sys.stderr, flush=True)
+    # strong error at fixed h against a 2^-13 proxy solution on the same paths,
+    # at N = min(N, 2^18), the size the network was trained at (the proxy run
+    # takes 8192 exact steps)
+    Nr = min(N, 2 ** 18)
+    wr = W.with_systems(w, [(Nr, 0, h)])
+    wr["h_fine"] = 2.0 ** -13
+    ref = SSM(W.with_h(wr, 2.0 ** -13), precision=prec, stream=stream)
+    ref.run()
+    rm = {}
+    for label, tol in (("exact", None), ("surrogate tol=1e-2", 1e-2), ("surrogate always", 1e9)):
+        with SSM(wr, precision=prec, stream=stream) as a:
+            if tol is not None:
+                a.surrogate_load(master)
+                a.surrogate_enable(check_every=every, tol=tol)
+            a.run()
+            rm[label] = math.sqrt(a.sqdiff(0, ref, 0) / Nr)
+    ref.close()
+    rm["ratio tol=1e-2 / exact"] = rm["surrogate tol=1e-2"] / rm["exact"]
+    rm["ratio always / exact"] = rm["surrogate always"] / rm["exact"]
+    pair_avg = info_ex["pair_ms"] / 1e3 / max(1, info_ex["pair_launches"])
+    return {"study": "surrogate", f"rmse_vs_2^-13_at_N={Nr}": rm, "workload": f"d=2 N={N} T=1 h=2^-9, exact check every {every} steps, {prec}",
+            "training": {"pairs": int(U.shape[0]), "from": f"{n_runs} exact runs of other ensembles at N={N_train}",
+                         "data_seconds": t_data, "steps": int(hist.size), "batch": 4096,
+                         "train_seconds": t_train, "loss_first": float(hist[:50].mean()),
+                         "loss_last": float(hist[-200:].mean()), "target_mean_sq": tsq},
+            "exact": {"seconds": dt_ex, "steps": n, "particle_steps_per_s": N * n / dt_ex,
+                      "pair_kernel_avg_ms": pair_avg * 1e3,
+                      "pair_tflops": float(N) * N * flops_per_pair(d) / pair_avg / 1e12},
+            "surrogate": runs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,7 +283,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--precision", default="fp32_kahan", choices=["fp64", "fp32", "fp32_kahan"])
     ap.add_argument("--N", type=int, default=0)
-    ap.add_argument("--study", choices=["none", "precision", "batched"], default="none",
+    ap.add_argument("--train-steps", type=int, default=32000)
+    ap.add_argument("--study", choices=["none", "precision", "batched", "surrogate"], default="none",
                     help="run a study of another workload instead of the throughput line")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -204,7 +306,7 @@ def main():
     torch.cuda.set_device(0)
     if args.study != "none":
         stream = torch.cuda.Stream()
-        fn = {"precision": study_precision, "batched": study_batched}[args.study]
+        fn = {"precision": study_precision, "batched": study_batched, "surrogate": study_surrogate}[args.study]
         print(json.dumps(fn(args, stream)), flush=True)
         return
     w = W.single_gpu_d1(N=args.N or 2 ** 16)

@@ -127,8 +127,10 @@ typedef struct {
     int64_t surr_checks;         /* check ticks: exact pair term computed and compared */
     int64_t surr_ticks;          /* ticks whose update used the surrogate */
     int64_t surr_fallback_ticks; /* non-check ticks that used the exact term after a failed check */
-    double surr_last_err;        /* relative error of the last check */
-    double surr_max_err;         /* largest relative error seen */
+    double surr_last_err;        /* relative error of the last check (with the fitted gain) */
+    double surr_max_err;         /* largest such error seen */
+    double surr_last_raw_err;    /* relative error of the last check without the gain */
+    double surr_gain[SSM_MAX_D]; /* per-component gain fitted at the last check */
 } ssm_info_t;
 
 /* Training settings of ssm_mlp_train (Adam; zeros select the defaults in brackets). */
@@ -247,15 +249,20 @@ ssm_status ssm_philox_blocks(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
 /* ---------------------------------------------------------------------------
  * Learned surrogate of the pairwise term (an extension; not in the paper).
  *
- * Features of particle i: u = [Y*_i (d values), C_1..C_K, S_1..S_K] with
+ * Raw features of particle i: [Y*_i (d values), C_1..C_K, S_1..S_K] with
  * C_k = (1/N) sum_j cos(omega_k . Y*_j), S_k = (1/N) sum_j sin(omega_k . Y*_j),
  * K = 16, omega_k = Z(3, k, 0, 0)[0..d) / b_ell (so E cos(omega.(x - z)) is the
- * Gaussian kernel of the pairwise term).  Network: u -> 64 -> 64 -> 64 -> d,
- * SiLU after each hidden layer, BF16 weights and activations on the matrix
- * cores with FP32 accumulation.  Parameters are FP32 "master" weights in the
- * flat layout W1[64][d+2K] b1[64] W2[64][64] b2[64] W3[64][64] b3[64]
+ * Gaussian kernel of the pairwise term).  Network input: [hi(y), lo(y),
+ * C, S] (2d + 2K values) with hi(y) = bf16(y), lo(y) = bf16(y - hi(y)), so the
+ * position passes the BF16 input layer with about 16 significant bits.
+ * Network: input -> 64 -> 64 -> 64 -> d, SiLU after each hidden layer, BF16
+ * weights and activations on the matrix cores with FP32 accumulation.
+ * Parameters are FP32 "master" weights in the flat layout
+ * W1[64][2d+2K] b1[64] W2[64][64] b2[64] W3[64][64] b3[64]
  * W4[d][64] b4[d] (row-major, [out][in]).  The output approximates
- * b_g (1/N) sum_j (Y^j - Y^i) exp(-|Y^i - Y^j|^2 / (2 b_ell^2)).
+ * b_g (1/N) sum_j (Y^j - Y^i) exp(-|Y^i - Y^j|^2 / (2 b_ell^2)); inside a
+ * step its mean over the system's particles is subtracted, since the exact
+ * term has zero net force (odd kernel).
  * ------------------------------------------------------------------------- */
 
 /* Number of parameters for state dimension d (0 if d is out of range). */
@@ -270,7 +277,12 @@ ssm_status ssm_surrogate_load(ssm_ctx *ctx, const float *master, int64_t n);
  * as well, the update uses them, and the relative error
  * sqrt(sum_i |s_i - p_i|^2 / sum_i |p_i|^2) over the stepping systems decides
  * whether the following ticks use the surrogate (error <= tol) or the exact
- * sums (until the next check).  Check ticks synchronize the stream.
+ * sums (until the next check).  The surrogate enters the update as
+ * g_k (s_k - mean(s_k)): its mean over the system is removed (the exact term
+ * has zero net force) and g_k = sum p_k s_k / sum s_k^2 is the least-squares
+ * gain fitted at the last check (1 before the first).  The error compared
+ * with tol is that of g (s - mean s) against the exact term p.  Check ticks
+ * synchronize the stream.
  * check_every = 0 turns the surrogate off. */
 ssm_status ssm_surrogate_enable(ssm_ctx *ctx, int32_t check_every, double tol);
 
@@ -280,7 +292,7 @@ ssm_status ssm_surrogate_enable(ssm_ctx *ctx, int32_t check_every, double tol);
  * (device float [n][d]).  Synchronizes. */
 ssm_status ssm_surrogate_samples(ssm_ctx *ctx, int32_t sys, int64_t n, uint64_t seed, float *U, float *T);
 
-/* Network output for explicit features: out (device float [n][d]) from U
+/* Network output for explicit raw rows: out (device float [n][d]) from U
  * (device float [n][d + 2K]) and master weights (device float).  Synchronizes stream. */
 ssm_status ssm_mlp_forward(int32_t d, const float *master, const float *U, int64_t n, float *out,
                            void *stream);

@@ -47,6 +47,7 @@ class Info(C.Structure):
         ("update_launches", C.c_int64), ("update_ms", C.c_double),
         ("surr_checks", C.c_int64), ("surr_ticks", C.c_int64), ("surr_fallback_ticks", C.c_int64),
         ("surr_last_err", C.c_double), ("surr_max_err", C.c_double),
+        ("surr_last_raw_err", C.c_double), ("surr_gain", C.c_double * MAX_D),
     ]
 
 

@@ -196,12 +196,15 @@ struct ssm_ctx {
     double surr_tol = 1e-3;
     bool surr_fallback = false;
     int64_t surr_checks = 0, surr_fallback_ticks = 0, surr_ticks = 0;
-    double surr_last_err = 0.0, surr_max_err = 0.0;
+    double surr_last_err = 0.0, surr_max_err = 0.0, surr_last_raw_err = 0.0;
+    double surr_gain[kMaxD] = {1.0, 1.0, 1.0, 1.0};
     MlpPacked* dmlp = nullptr;
     float* surr = nullptr;         // [d][P] surrogate pair term
     double* rff_part = nullptr;    // [nblk_tot][2K]
     float* mom = nullptr;          // [n_sys][2K]
     double* err_part = nullptr;    // [nblk_tot][2]
+    double* smean_part = nullptr;  // [nblk_tot][kMaxD]
+    float* smean = nullptr;        // [n_sys][kMaxD]
     int32_t* dsys_list = nullptr;  // per phase: active systems
     std::vector<int64_t> sys_list_off, sys_list_cnt;
     RffFreq rff{};
@@ -263,7 +266,7 @@ static void free_ctx(ssm_ctx* c)
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* bufs[] = {c->X, c->Y, c->Ys, c->Bp, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
-                    c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list};
+                    c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list, c->smean_part, c->smean};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     recycle_events(c, c->ev_pair);
@@ -340,6 +343,12 @@ static ssm_status launch_surrogate(ssm_ctx* c, int64_t ph)
     SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_mlp_infer<T, D>), dim3(grid), dim3(256), 0, c->stream, items, (int)nb,
                                          c->dsys, c->P, (const T*)c->Y, c->mom, c->dmlp, c->surr));
     HIP_TRY(hipGetLastError());
+    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_surr_partial<D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, items,
+                                         c->dsys, c->P, c->surr, c->smean_part));
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_surr_final, dim3((unsigned)c->sys_list_cnt[ph]), dim3(64), 0, c->stream,
+                       c->dsys_list + c->sys_list_off[ph], c->dsys, d, c->smean_part, c->smean);
+    HIP_TRY(hipGetLastError());
     return SSM_OK;
 }
 
@@ -379,7 +388,7 @@ static ssm_status launch_tick(ssm_ctx* c)
     if (check && nb > 0) {
         const BlkItem* items = c->dblk + c->blk_off[ph];
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_surr_err<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, items,
-                                             c->dsys, c->P, c->Bp, c->surr, c->err_part));
+                                             c->dsys, c->P, c->Bp, c->surr, c->smean, c->err_part));
         HIP_TRY(hipGetLastError());
     }
     const int use_surr = (run_surr && !check) ? 1 : 0;
@@ -393,7 +402,10 @@ static ssm_status launch_tick(ssm_ctx* c)
         const BlkItem* items = c->dblk + c->blk_off[ph];
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_update<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream,
                                              items, c->dsys, c->coef, c->P, c->tick, X, Y, Ys, c->Bp, c->surr,
-                                             use_surr, c->psumX, c->psumY, c->nblk_tot, c->dflags));
+                                             c->smean, use_surr,
+                                             make_float4((float)c->surr_gain[0], (float)c->surr_gain[1],
+                                                         (float)c->surr_gain[2], (float)c->surr_gain[3]),
+                                             c->psumX, c->psumY, c->nblk_tot, c->dflags));
         HIP_TRY(hipGetLastError());
         if (!c->fused) {
             SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_newton<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream,
@@ -411,17 +423,32 @@ static ssm_status launch_tick(ssm_ctx* c)
         if (!check && c->surr_fallback) c->surr_fallback_ticks++;
     }
     if (check && nb > 0) {
-        // relative error of the surrogate pair term over the active systems; decides
-        // whether the next ticks use it (until the next check)
-        std::vector<double> h(2 * nb);
+        // Least-squares gain per component from the check's exact and surrogate
+        // terms, then the relative error of the gained surrogate over the
+        // stepping systems; it decides whether the ticks until the next check
+        // use the surrogate (with that gain) or the exact sums.
+        std::vector<double> h(kErrStats * nb);
         HIP_TRY(hipMemcpyAsync(h.data(), c->err_part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
-        double se = 0.0, sb = 0.0;
+        double se = 0.0, sb = 0.0, sps[kMaxD] = {0, 0, 0, 0}, sss[kMaxD] = {0, 0, 0, 0};
         for (int64_t q = 0; q < nb; ++q) {
-            se += h[2 * q];
-            sb += h[2 * q + 1];
+            const double* r = &h[kErrStats * q];
+            se += r[0];
+            sb += r[1];
+            for (int k = 0; k < d; ++k) {
+                sps[k] += r[2 + 2 * k];
+                sss[k] += r[3 + 2 * k];
+            }
         }
-        const double err = sb > 0.0 ? std::sqrt(se / sb) : (se > 0.0 ? INFINITY : 0.0);
+        double se_g = sb;  // |g s - p|^2 = g^2 |s|^2 - 2 g s.p + |p|^2, per component
+        for (int k = 0; k < d; ++k) {
+            const double g = sss[k] > 0.0 ? sps[k] / sss[k] : 1.0;
+            c->surr_gain[k] = g;
+            se_g += g * g * sss[k] - 2.0 * g * sps[k];
+        }
+        se_g = std::max(se_g, 0.0);
+        const double err = sb > 0.0 ? std::sqrt(se_g / sb) : (se_g > 0.0 ? INFINITY : 0.0);
+        c->surr_last_raw_err = sb > 0.0 ? std::sqrt(se / sb) : 0.0;
         c->surr_last_err = err;
         c->surr_max_err = std::max(c->surr_max_err, err);
         c->surr_checks++;
@@ -891,6 +918,8 @@ extern "C" ssm_status ssm_info(ssm_ctx* c, ssm_info_t* out)
     out->surr_fallback_ticks = c->surr_fallback_ticks;
     out->surr_last_err = c->surr_last_err;
     out->surr_max_err = c->surr_max_err;
+    out->surr_last_raw_err = c->surr_last_raw_err;
+    for (int k = 0; k < SSM_MAX_D; ++k) out->surr_gain[k] = c->surr_gain[k];
     return SSM_OK;
 }
 
@@ -1064,7 +1093,9 @@ static ssm_status ensure_surrogate_buffers(ssm_ctx* c)
     ALLOC2(c->surr, (size_t)c->d * c->P * sizeof(float));
     ALLOC2(c->rff_part, (size_t)c->nblk_tot * 2 * kRff * sizeof(double));
     ALLOC2(c->mom, c->sys.size() * 2 * kRff * sizeof(float));
-    ALLOC2(c->err_part, (size_t)c->nblk_tot * 2 * sizeof(double));
+    ALLOC2(c->err_part, (size_t)c->nblk_tot * kErrStats * sizeof(double));
+    ALLOC2(c->smean_part, (size_t)c->nblk_tot * kMaxD * sizeof(double));
+    ALLOC2(c->smean, c->sys.size() * kMaxD * sizeof(float));
 #undef ALLOC2
     RffFreq* dfq = nullptr;
     HIP_TRY(hipMalloc((void**)&dfq, sizeof(RffFreq)));
@@ -1113,6 +1144,7 @@ extern "C" ssm_status ssm_surrogate_enable(ssm_ctx* c, int32_t check_every, doub
     c->surr_check_every = check_every;
     c->surr_tol = tol;
     c->surr_fallback = false;
+    for (int k = 0; k < kMaxD; ++k) c->surr_gain[k] = 1.0;
     return SSM_OK;
 }
 

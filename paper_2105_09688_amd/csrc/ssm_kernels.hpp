@@ -252,7 +252,9 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
                                                  int64_t P, int64_t tick, T* __restrict__ X,
                                                  T* __restrict__ Y, T* __restrict__ Ys,
                                                  const double* __restrict__ Bp,
-                                                 const float* __restrict__ surr, int use_surr,
+                                                 const float* __restrict__ surr,
+                                                 const float* __restrict__ surr_mean, int use_surr,
+                                                 float4 surr_gain,
                                                  double* __restrict__ psumX,
                                                  double* __restrict__ psumY, int64_t nblk_tot,
                                                  Flags* flags)
@@ -286,7 +288,10 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
             const double y = (double)Y[k * P + slot];
             double pair = 0.0;
             if (use_surr) {
-                pair = (double)surr[k * P + slot];  // learned surrogate of the pair term
+                // learned surrogate of the pair term, projected to zero net force and
+                // scaled by the gain fitted at the last check
+                const float gk = k == 0 ? surr_gain.x : k == 1 ? surr_gain.y : k == 2 ? surr_gain.z : surr_gain.w;
+                pair = (double)gk * ((double)surr[k * P + slot] - (double)surr_mean[(int64_t)it.sys * kMaxD + k]);
             } else if (cf.has_pair) {
                 for (int q = 0; q < S.splits; ++q) pair += Bp[((int64_t)q * D + k) * P + slot];
                 pair *= S.pair_scale;

@@ -1,6 +1,8 @@
 // ssm_surrogate.hpp -- learned surrogate of the interaction drift (not in the
 // paper): random-Fourier-feature moments of mu^Y and a small MLP
-//   [y (d), C_1..C_K, S_1..S_K] -> 64 -> 64 -> 64 -> d,  SiLU hidden layers,
+//   [hi(y) (d), lo(y) (d), C_1..C_K, S_1..S_K] -> 64 -> 64 -> 64 -> d,
+// SiLU hidden layers, where hi(y) = bf16(y) and lo(y) = bf16(y - hi(y)) carry
+// the position to about 16 significant bits through the BF16 input layer,
 // BF16 operands with FP32 accumulation on the matrix cores (MFMA), trained
 // on (y, moments, exact pair term) samples by hand-written kernels with Adam.
 //
@@ -17,7 +19,7 @@ namespace ssm {
 
 constexpr int kRff = 16;         // frequencies; 2 kRff moments
 constexpr int kHid = 64;         // hidden width
-constexpr int kKpad = 64;        // input features padded: d + 2 kRff <= 36 -> 64
+constexpr int kKpad = 64;        // input features padded: 2 d + 2 kRff <= 40 -> 64
 constexpr int kOutPad = 16;      // outputs padded to one 16-column tile
 constexpr int kStride = 72;      // LDS/global row stride (bf16) of 64-wide rows (bank spread)
 constexpr int kStrideT4 = 40;    // row stride of the transposed output layer (32 used)
@@ -40,8 +42,13 @@ struct MlpPacked {
 };
 
 // Flat master layout (FP32), as the oracle's: W1[64][in] b1[64] W2[64][64] b2
-// W3[64][64] b3 W4[d][64] b4[d], in = d + 2 kRff.
-__host__ __device__ constexpr int mlp_in(int d) { return d + 2 * kRff; }
+// W3[64][64] b3 W4[d][64] b4[d], in = 2 d + 2 kRff network inputs.  Sample
+// rows handed to the library are "raw": [y (d), moments (2 kRff)].
+__host__ __device__ constexpr int mlp_in(int d) { return 2 * d + 2 * kRff; }
+__host__ __device__ constexpr int raw_in(int d) { return d + 2 * kRff; }
+
+__device__ __forceinline__ __bf16 bf_hi(float y) { return (__bf16)y; }
+__device__ __forceinline__ __bf16 bf_lo(float y) { return (__bf16)(y - (float)(__bf16)y); }
 __host__ __device__ constexpr int64_t mlp_params(int d)
 {
     return (int64_t)kHid * mlp_in(d) + kHid + 2 * ((int64_t)kHid * kHid + kHid) + (int64_t)d * kHid + d;
@@ -172,7 +179,7 @@ __device__ __forceinline__ void d_to_a(const f32x4 v[NT], __bf16* tile, bf16x8 a
 }
 
 // Input features of one sample in A layout: lane (l) holds features
-// k = 32 ks + 8 (l / 16) + 0..7 of sample l % 16:  u = [y_0..y_{d-1}, m_0..m_{2K-1}, 0...].
+// k = 32 ks + 8 (l / 16) + 0..7 of sample l % 16:  u = [hi(y), lo(y), m_0..m_{2K-1}, 0...].
 // y: the sample's coordinates (y0..y3), mom: moments in LDS.
 __device__ __forceinline__ void build_input(float y0, float y1, float y2, float y3, const float* mom, int d,
                                             bf16x8 a[2])
@@ -183,10 +190,34 @@ __device__ __forceinline__ void build_input(float y0, float y1, float y2, float 
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int k = ks * 32 + 8 * (l >> 4) + i;
-            float v = 0.0f;
-            if (k < d) v = (k == 0) ? y0 : (k == 1) ? y1 : (k == 2) ? y2 : y3;
-            else if (k < d + 2 * kRff) v = mom[k - d];
-            a[ks][i] = (__bf16)v;
+            __bf16 v = (__bf16)0.0f;
+            if (k < 2 * d) {
+                const int c = k < d ? k : k - d;
+                const float yc = (c == 0) ? y0 : (c == 1) ? y1 : (c == 2) ? y2 : y3;
+                v = k < d ? bf_hi(yc) : bf_lo(yc);
+            } else if (k < 2 * d + 2 * kRff) {
+                v = (__bf16)mom[k - 2 * d];
+            }
+            a[ks][i] = v;
+        }
+}
+
+// Same, from a raw row r = [y (d), m (2K)] in global memory (r may be null: zeros).
+__device__ __forceinline__ void build_input_row(const float* r, int d, bf16x8 a[2])
+{
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = ks * 32 + 8 * (l >> 4) + i;
+            __bf16 v = (__bf16)0.0f;
+            if (r) {
+                if (k < d) v = bf_hi(r[k]);
+                else if (k < 2 * d) v = bf_lo(r[k - d]);
+                else if (k < 2 * d + 2 * kRff) v = (__bf16)r[k - d];
+            }
+            a[ks][i] = v;
         }
 }
 
@@ -333,7 +364,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const BlkItem* __restrict__ i
     }
 }
 
-// Inference on explicit feature rows U [n][d + 2K] -> out [n][d].
+// Inference on explicit raw rows U [n][d + 2K] -> out [n][d].
 __global__ __launch_bounds__(256) void k_mlp_apply(const float* __restrict__ U, int64_t n, int d,
                                                    const MlpPacked* __restrict__ W, float* __restrict__ out)
 {
@@ -347,17 +378,11 @@ __global__ __launch_bounds__(256) void k_mlp_apply(const float* __restrict__ U, 
     __syncthreads();
     const int wave = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
-    const int in = d + 2 * kRff;
+    const int in = raw_in(d);
     for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 16; r0 < n; r0 += (int64_t)gridDim.x * 64) {
         const int64_t row = r0 + (l & 15);
         bf16x8 a[2];
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int k = ks * 32 + 8 * (l >> 4) + i;
-                a[ks][i] = (__bf16)((row < n && k < in) ? U[row * in + k] : 0.0f);
-            }
+        build_input_row(row < n ? U + row * in : nullptr, d, a);
         f32x4 z[3][4];
         bf16x8 act[3][2];
         f32x4 o;
@@ -386,7 +411,7 @@ __global__ void k_gather_samples(const SysDev* __restrict__ sys, int s, int64_t 
     const Block4 rb = philox4x64_10((uint64_t)q, 0ull, 1ull, 4ull << 32, seed, 0ull);
     const int64_t i = (int64_t)(rb.w[0] % (uint64_t)S.N);
     const int64_t slot = S.off + i;
-    const int in = D + 2 * kRff;
+    const int in = raw_in(D);
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         U[q * in + k] = (float)Y[k * P + slot];
@@ -446,19 +471,13 @@ __global__ __launch_bounds__(256) void k_train_fwdbwd(const MlpPacked* __restric
     __syncthreads();
     const int wave = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
-    const int in = d + 2 * kRff;
+    const int in = raw_in(d);
     const int b0 = blockIdx.x * 64 + wave * 16;  // first batch row of this wavefront
     // this lane's sample (A layout row l % 16)
     const int brow = b0 + (l & 15);
     const int64_t sidx = sample_index(brow, step, seed, n_samples, sequential);
     bf16x8 a[2];
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int k = ks * 32 + 8 * (l >> 4) + i;
-            a[ks][i] = (__bf16)((k < in) ? U[sidx * in + k] : 0.0f);
-        }
+    build_input_row(U + sidx * in, d, a);
     // inputs, feature-major
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks)
@@ -574,7 +593,7 @@ __global__ __launch_bounds__(64) void k_train_wgrad(TrainBufs tb, int d, int B, 
     const __bf16* dl = tb.delta[layer];  // [out][B]
     const __bf16* al = tb.act[layer];    // [in][B]
     const int nout = layer < 3 ? kHid : d;
-    const int nin = layer == 0 ? d + 2 * kRff : kHid;
+    const int nin = layer == 0 ? mlp_in(d) : kHid;
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     f32x4 bacc = {0.0f, 0.0f, 0.0f, 0.0f};
     bf16x8 ones;
@@ -622,20 +641,58 @@ __global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __re
     w[q] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
 }
 
-// Squared surrogate error and squared exact pair term, per update block
-// (fixed-order block sums), for the listed blocks.
-template <typename T, int D>
-__global__ __launch_bounds__(kBlk) void k_surr_err(const BlkItem* __restrict__ items,
-                                                   const SysDev* __restrict__ sys, int64_t P,
-                                                   const double* __restrict__ Bp,
-                                                   const float* __restrict__ surr,
-                                                   double* __restrict__ err_part /*[nblk][2]*/)
+// The exact pair term has zero net force (odd kernel: sum_i K^i = 0).  The
+// surrogate is projected onto that constraint: block sums of its outputs,
+// then per-system means that k_update / k_surr_err subtract.
+template <int D>
+__global__ __launch_bounds__(kBlk) void k_surr_partial(const BlkItem* __restrict__ items,
+                                                       const SysDev* __restrict__ sys, int64_t P,
+                                                       const float* __restrict__ surr,
+                                                       double* __restrict__ part /*[nblk_tot][kMaxD]*/)
 {
     __shared__ double red[kBlk];
     const BlkItem it = items[blockIdx.x];
     const SysDev S = sys[it.sys];
     const int i = it.blk * kBlk + threadIdx.x;
-    double e2 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double v = (i < S.N) ? (double)surr[k * P + S.off + i] : 0.0;
+        const double t = block_sum(v, red);
+        if (threadIdx.x == 0) part[(int64_t)(S.blk0 + it.blk) * kMaxD + k] = t;
+    }
+}
+
+__global__ void k_surr_final(const int32_t* __restrict__ sys_list, const SysDev* __restrict__ sys, int d,
+                             const double* __restrict__ part, float* __restrict__ mean /*[n_sys][kMaxD]*/)
+{
+    const int s = sys_list[blockIdx.x];
+    const SysDev S = sys[s];
+    const int k = threadIdx.x;
+    if (k >= d) return;
+    double acc = 0.0;
+    for (int b = 0; b < S.nblk; ++b) acc += part[(int64_t)(S.blk0 + b) * kMaxD + k];
+    mean[(int64_t)s * kMaxD + k] = (float)(acc / (double)S.N);
+}
+
+// Check statistics per update block (fixed-order block sums), for the listed
+// blocks, with s = surrogate minus its system mean and p = exact pair term:
+//   [0] sum |s - p|^2, [1] sum |p|^2, then per component k:
+//   [2 + 2k] sum p_k s_k, [3 + 2k] sum s_k^2.
+constexpr int kErrStats = 2 + 2 * kMaxD;
+
+template <typename T, int D>
+__global__ __launch_bounds__(kBlk) void k_surr_err(const BlkItem* __restrict__ items,
+                                                   const SysDev* __restrict__ sys, int64_t P,
+                                                   const double* __restrict__ Bp,
+                                                   const float* __restrict__ surr,
+                                                   const float* __restrict__ surr_mean,
+                                                   double* __restrict__ err_part /*[nblk][kErrStats]*/)
+{
+    __shared__ double red[kBlk];
+    const BlkItem it = items[blockIdx.x];
+    const SysDev S = sys[it.sys];
+    const int i = it.blk * kBlk + threadIdx.x;
+    double e2 = 0.0, b2 = 0.0, ps[kMaxD] = {0.0, 0.0, 0.0, 0.0}, ss[kMaxD] = {0.0, 0.0, 0.0, 0.0};
     if (i < S.N) {
         const int64_t slot = S.off + i;
 #pragma unroll
@@ -643,16 +700,29 @@ __global__ __launch_bounds__(kBlk) void k_surr_err(const BlkItem* __restrict__ i
             double pair = 0.0;
             for (int q = 0; q < S.splits; ++q) pair += Bp[((int64_t)q * D + k) * P + slot];
             pair *= S.pair_scale;
-            const double df = (double)surr[k * P + slot] - pair;
+            const double sv = (double)surr[k * P + slot] - (double)surr_mean[(int64_t)it.sys * kMaxD + k];
+            const double df = sv - pair;
             e2 += df * df;
             b2 += pair * pair;
+            ps[k] = pair * sv;
+            ss[k] = sv * sv;
         }
     }
-    const double se = block_sum(e2, red);
-    const double sb = block_sum(b2, red);
+    double* out = err_part + (int64_t)blockIdx.x * kErrStats;
+    const double t0 = block_sum(e2, red);
+    const double t1 = block_sum(b2, red);
     if (threadIdx.x == 0) {
-        err_part[2 * blockIdx.x] = se;
-        err_part[2 * blockIdx.x + 1] = sb;
+        out[0] = t0;
+        out[1] = t1;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double a = block_sum(ps[k], red);
+        const double b = block_sum(ss[k], red);
+        if (threadIdx.x == 0) {
+            out[2 + 2 * k] = a;
+            out[3 + 2 * k] = b;
+        }
     }
 }
 

@@ -151,7 +151,9 @@ class SSM:
     def info(self) -> dict:
         i = _lib.Info()
         check(_lib.load().ssm_info(self._h, C.byref(i)))
-        return {f: getattr(i, f) for f, _ in i._fields_}
+        out = {f: getattr(i, f) for f, _ in i._fields_}
+        out["surr_gain"] = list(out["surr_gain"])[: self.d]
+        return out
 
 
 # -------------------------------------------------------------------------- kernel-level calls
@@ -221,7 +223,7 @@ def mlp_num_params(d: int) -> int:
 def mlp_init(d: int, seed: int = 0):
     """Seeded initial FP32 master weights (uniform +-sqrt(6/(fan_in+fan_out)) per matrix, zero biases)."""
     rng = np.random.Generator(np.random.Philox(key=seed + 5))
-    shapes = [(64, d + 32), (64, 64), (64, 64), (d, 64)]
+    shapes = [(64, 2 * d + 32), (64, 64), (64, 64), (d, 64)]
     parts = []
     for (o, i) in shapes:
         lim = np.sqrt(6.0 / (i + o))
@@ -233,7 +235,7 @@ def mlp_init(d: int, seed: int = 0):
 
 
 def mlp_forward(d: int, master, U):
-    """Network output for device float32 features U [n][d+32]; master: device float32 tensor."""
+    """Network output for raw device float32 rows U [n][d+32] = [y, moments]; master: device float32."""
     torch = _torch()
     out = torch.empty((U.shape[0], d), dtype=torch.float32, device=U.device)
     check(_lib.load().ssm_mlp_forward(d, master.data_ptr(), U.contiguous().data_ptr(), U.shape[0],
