@@ -138,6 +138,24 @@ def study_precision(args, stream):
     return {"study": "precision", "workload": f"d=3 N={N} T=1 h=2^-10 l=0.5", "results": res}
 
 
+def study_small(args, stream):
+    """Small parity case (10 ensembles x N=1000, d=1, 256 steps, FP64):
+    whole-run time with eager launches and with per-tick graph replays."""
+    from paper_2105_09688_amd import workloads as W
+    from paper_2105_09688_amd.ssm import SSM
+    w = W.small_parity()
+    out = {"study": "small", "workload": "10 ensembles x N=1000, d=1, h=2^-8, 256 steps"}
+    for prec in ("fp64", "fp32_kahan"):
+        for graphs in (False, True):
+            # the first tick (which captures the graph) is not timed
+            s, dt, n = timed_run(SSM, w, prec, stream, steps=255, profile=False, graphs=graphs,
+                                 setup=lambda c: c.step(1))
+            s.close()
+            out[f"{prec} {'graphs' if graphs else 'eager'}"] = {
+                "seconds": dt, "particle_steps_per_s": 10 * 1000 * n / dt, "us_per_step": dt / n * 1e6}
+    return out
+
+
 def study_batched(args, stream):
     """Batched case: 64 ensembles of uneven N x 5 step sizes in one context;
     throughput, and rMSE per step size against a 2^-12 proxy solution on the
@@ -284,11 +302,12 @@ def main():
     ap.add_argument("--precision", default="fp32_kahan", choices=["fp64", "fp32", "fp32_kahan"])
     ap.add_argument("--N", type=int, default=0)
     ap.add_argument("--train-steps", type=int, default=32000)
-    ap.add_argument("--study", choices=["none", "precision", "batched", "surrogate"], default="none",
+    ap.add_argument("--study", choices=["none", "precision", "batched", "surrogate", "small"], default="none",
                     help="run a study of another workload instead of the throughput line")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="library default tiling instead of the autotuned one")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, one plain device copy of this many MiB (calibrates byte counters)")
     args = ap.parse_args()
@@ -306,7 +325,8 @@ def main():
     torch.cuda.set_device(0)
     if args.study != "none":
         stream = torch.cuda.Stream()
-        fn = {"precision": study_precision, "batched": study_batched, "surrogate": study_surrogate}[args.study]
+        fn = {"precision": study_precision, "batched": study_batched, "surrogate": study_surrogate,
+              "small": study_small}[args.study]
         print(json.dumps(fn(args, stream)), flush=True)
         return
     w = W.single_gpu_d1(N=args.N or 2 ** 16)
@@ -317,11 +337,16 @@ def main():
         raise SystemExit(f"--steps must be in 1..{total_steps} (T/h)")
 
     stream = torch.cuda.Stream()
+    tiling = {}
+    if not args.no_tune:
+        from paper_2105_09688_amd.tune import autotune
+        t = autotune(w, args.precision, stream=stream)
+        tiling = {k: t[k] for k in ("targets_per_lane", "sources_per_item", "pair_scheme")}
     # warm-up (separate context: the timed one starts at t = 0)
-    with SSM(w, precision=args.precision, stream=stream) as s:
+    with SSM(w, precision=args.precision, stream=stream, **tiling) as s:
         s.step(min(args.warmup, total_steps))
         s.sync()
-    s = SSM(w, precision=args.precision, stream=stream)
+    s = SSM(w, precision=args.precision, stream=stream, **tiling)
     s.sync()
     s.profile(True)
     torch.cuda.synchronize()
@@ -368,7 +393,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": recorded_traffic(f"k_pair {args.precision} d={d} N={N} R={info['targets_per_lane']} "
-                                        f"L={info['sources_per_item']}"),
+                                        f"L={info['sources_per_item']} {info['pair_scheme']}"),
             "flop_per_pair": flops_per_pair(d),
             "pairs_per_launch": pairs,
             "avg_launch_ms": pair_avg_s * 1e3,
@@ -376,7 +401,8 @@ def main():
         },
         "update_kernel_avg_ms": info["update_ms"] / max(1, info["update_launches"]),
         "tiling": {"targets_per_lane": info["targets_per_lane"], "sources_per_item": info["sources_per_item"],
-                   "wavefront_items": info["n_pair_items"]},
+                   "pair_scheme": info["pair_scheme"], "wavefront_items": info["n_pair_items"],
+                   "autotuned": not args.no_tune},
     }
     if not args.no_check and args.precision != "fp64":
         # pathwise agreement of the timed run with the FP64 path after the same steps

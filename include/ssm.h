@@ -103,8 +103,15 @@ typedef struct {
     void *stream;              /* hipStream_t the context launches on; NULL -> a stream it owns */
     /* Tiling of the pairwise kernel; 0 = library default.  Results do not
      * depend on these beyond floating-point summation order. */
-    int32_t targets_per_lane;  /* 1, 2, 4 or 8 */
+    int32_t targets_per_lane;  /* 1, 2, 4 or 8 (a target block is 64 x this) */
     int32_t sources_per_item;  /* sources one wavefront sweeps per work item (>= 64) */
+    int32_t pair_scheme;       /* 0: default (symmetric for the FP32 modes, ordered pairs for FP64);
+                                  1: every ordered pair (i, j) evaluated; 2: symmetric: each unordered
+                                  pair evaluated once, +q to i and -q to j (the kernel is odd),
+                                  FP32 modes only */
+    int32_t graphs;            /* nonzero: each tick replays a HIP graph captured once per tick
+                                  phase (tick % (h_max/h_min)); not used while profiling or with
+                                  the surrogate enabled */
 } ssm_config;
 
 typedef struct {
@@ -116,6 +123,8 @@ typedef struct {
     int32_t n_pair_items;    /* wavefront work items of the pairwise kernel per tick (phase 0) */
     int32_t targets_per_lane;
     int32_t sources_per_item;
+    int32_t symmetric;       /* 1: symmetric pair scheme, 0: ordered pairs */
+    int32_t pad;
     int64_t device_bytes;    /* device memory the context holds */
     /* Kernel timing (ssm_profile enabled): HIP events recorded on the context's
      * stream around each launch since the last ssm_profile(ctx, 1). */

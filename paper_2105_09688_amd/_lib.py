@@ -34,7 +34,8 @@ class Config(C.Structure):
         ("x0_mean", C.c_double * MAX_D), ("x0_std", C.c_double * MAX_D),
         ("newton_max_iter", C.c_int32), ("allow_unstable_h", C.c_int32),
         ("stream", C.c_void_p),
-        ("targets_per_lane", C.c_int32), ("sources_per_item", C.c_int32),
+        ("targets_per_lane", C.c_int32), ("sources_per_item", C.c_int32), ("pair_scheme", C.c_int32),
+        ("graphs", C.c_int32),
     ]
 
 
@@ -42,7 +43,8 @@ class Info(C.Structure):
     _fields_ = [
         ("tick", C.c_int64), ("ticks_total", C.c_int64), ("newton_max_seen", C.c_int32),
         ("newton_failures", C.c_int32), ("nonfinite", C.c_int32), ("n_pair_items", C.c_int32),
-        ("targets_per_lane", C.c_int32), ("sources_per_item", C.c_int32), ("device_bytes", C.c_int64),
+        ("targets_per_lane", C.c_int32), ("sources_per_item", C.c_int32), ("symmetric", C.c_int32),
+        ("pad", C.c_int32), ("device_bytes", C.c_int64),
         ("pair_launches", C.c_int64), ("pair_ms", C.c_double),
         ("update_launches", C.c_int64), ("update_ms", C.c_double),
         ("surr_checks", C.c_int64), ("surr_ticks", C.c_int64), ("surr_fallback_ticks", C.c_int64),

@@ -42,18 +42,6 @@ extern "C" const char* ssm_last_error(void) { return g_last_error.c_str(); }
 // ---------------------------------------------------------------------------
 namespace ssm {
 
-__global__ void k_combine(const double* __restrict__ Bp, int splits, int d, int64_t P, int64_t N,
-                          double scale, double* __restrict__ K)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    for (int k = 0; k < d; ++k) {
-        double s = 0.0;
-        for (int q = 0; q < splits; ++q) s += Bp[((int64_t)q * d + k) * P + i];
-        K[(int64_t)k * N + i] = s * scale;
-    }
-}
-
 __global__ void k_brownian(int d, int64_t N, uint64_t seed, int32_t ens, int64_t n0, int32_t r,
                            double sqrt_hf, double* __restrict__ dW)
 {
@@ -100,15 +88,15 @@ __global__ void k_implicit_plain(int64_t N, const double* __restrict__ X, double
 // ---------------------------------------------------------------------------
 template <typename T, int D>
 static void launch_pair_T(int R, bool kahan, dim3 grid, hipStream_t st, const PairItem* items,
-                          int n, const SysDev* sys, const T* Ys, int64_t P, double* Bp)
+                          int n, const SysDev* sys, const T* Ys, int64_t P, double* Bp, float* Bpj)
 {
     dim3 block(64 * kWaves);
 #define SSM_PAIR_CASE(RR)                                                                      \
     case RR:                                                                                   \
         if (kahan)                                                                             \
-            hipLaunchKernelGGL((k_pair<T, D, RR, true>), grid, block, 0, st, items, n, sys, Ys, P, Bp); \
+            hipLaunchKernelGGL((k_pair<T, D, RR, true>), grid, block, 0, st, items, n, sys, Ys, P, Bp, Bpj); \
         else                                                                                   \
-            hipLaunchKernelGGL((k_pair<T, D, RR, false>), grid, block, 0, st, items, n, sys, Ys, P, Bp); \
+            hipLaunchKernelGGL((k_pair<T, D, RR, false>), grid, block, 0, st, items, n, sys, Ys, P, Bp, Bpj); \
         break;
     switch (R) {
         SSM_PAIR_CASE(1)
@@ -122,13 +110,13 @@ static void launch_pair_T(int R, bool kahan, dim3 grid, hipStream_t st, const Pa
 
 template <typename T>
 static void launch_pair(int d, int R, bool kahan, dim3 grid, hipStream_t st, const PairItem* items,
-                        int n, const SysDev* sys, const T* Ys, int64_t P, double* Bp)
+                        int n, const SysDev* sys, const T* Ys, int64_t P, double* Bp, float* Bpj)
 {
     switch (d) {
-        case 1: launch_pair_T<T, 1>(R, kahan, grid, st, items, n, sys, Ys, P, Bp); break;
-        case 2: launch_pair_T<T, 2>(R, kahan, grid, st, items, n, sys, Ys, P, Bp); break;
-        case 3: launch_pair_T<T, 3>(R, kahan, grid, st, items, n, sys, Ys, P, Bp); break;
-        case 4: launch_pair_T<T, 4>(R, kahan, grid, st, items, n, sys, Ys, P, Bp); break;
+        case 1: launch_pair_T<T, 1>(R, kahan, grid, st, items, n, sys, Ys, P, Bp, Bpj); break;
+        case 2: launch_pair_T<T, 2>(R, kahan, grid, st, items, n, sys, Ys, P, Bp, Bpj); break;
+        case 3: launch_pair_T<T, 3>(R, kahan, grid, st, items, n, sys, Ys, P, Bp, Bpj); break;
+        case 4: launch_pair_T<T, 4>(R, kahan, grid, st, items, n, sys, Ys, P, Bp, Bpj); break;
         default: break;
     }
 }
@@ -178,6 +166,9 @@ struct ssm_ctx {
     void* Y = nullptr;
     void* Ys = nullptr;
     double* Bp = nullptr;
+    float* Bpj = nullptr;      // symmetric scheme: j-side partials [nb_max][d][P]
+    bool sym = false;          // symmetric pair scheme (FP32 modes)
+    int64_t nb_max = 0;
     double* psumX = nullptr;
     double* psumY = nullptr;
     SysDev* dsys = nullptr;
@@ -209,6 +200,14 @@ struct ssm_ctx {
     std::vector<int64_t> sys_list_off, sys_list_cnt;
     RffFreq rff{};
     double ell = 1.0;
+    // device tick counter read by the update kernels; HIP graphs of one tick
+    // per phase (tick % max_stride), built on first use and replayed
+    int64_t* dtick = nullptr;
+    bool dtick_valid = true;  // device counter equals the host tick
+    double* dW = nullptr;  // [d][P] Brownian increments of the current tick
+    int bm_lanes = 1;      // lanes per particle in k_brownian_sum
+    bool use_graphs = false;
+    std::vector<hipGraphExec_t> phase_graph;
     // kernel timing: event pairs recorded around launches while profiling
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pair, ev_update;
@@ -265,13 +264,16 @@ static void free_ctx(ssm_ctx* c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    void* bufs[] = {c->X, c->Y, c->Ys, c->Bp, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
-                    c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list, c->smean_part, c->smean};
+    void* bufs[] = {c->X, c->Y, c->Ys, c->Bp, c->Bpj, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
+                    c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list, c->smean_part, c->smean,
+                    c->dtick, c->dW};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     recycle_events(c, c->ev_pair);
     recycle_events(c, c->ev_update);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    for (hipGraphExec_t g : c->phase_graph)
+        if (g) (void)hipGraphExecDestroy(g);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -285,21 +287,25 @@ static bool is_int_ratio(double a, double b, int64_t* out)
     return true;
 }
 
-// Work-list construction.  Pair items: for every system, tiles of 64 R targets
-// times source ranges of length L; ordered by decreasing cost (longest first),
-// and within a system source-range-major so that the wavefronts of one block
-// share their source stream.
-static void build_pair_items(const ssm_ctx* c, const std::vector<int>& systems,
-                             std::vector<PairItem>& out)
+// Work items of one system's pair sums.
+//  Ordered-pair scheme: tiles of 64 R targets x source ranges of L sources;
+//    i-side partial q = source range q.
+//  Symmetric scheme (FP32): target blocks of B = 64 R particles; block a has
+//    a diagonal item (its own sources, ordered pairs, partial 0) and items over
+//    the later sources [B (a+1), N) in ranges of L (partial 1, 2, ...), each
+//    also writing j-side partial row a.  Every unordered pair is visited once.
+// Each item carries a cost estimate (VALU issue slots) for ordering.
+static int64_t plan_system(int s, int64_t N, int R, bool sym, int64_t L,
+                           std::vector<std::pair<int64_t, PairItem>>& out, int64_t* nb_out)
 {
-    std::vector<std::pair<int64_t, PairItem>> tmp;
-    const int64_t tile = 64 * (int64_t)c->R;
-    for (int s : systems) {
-        const SysHost& S = c->sys[s];
-        const int64_t tiles = (S.N + tile - 1) / tile;
-        for (int64_t q = 0; q < S.splits; ++q) {
-            const int64_t j0 = q * c->L;
-            const int64_t nj = std::min<int64_t>(c->L, S.N - j0);
+    const int64_t tile = 64 * (int64_t)R;
+    const int64_t tiles = (N + tile - 1) / tile;
+    int64_t isplits = 0;
+    if (!sym) {
+        isplits = (N + L - 1) / L;
+        for (int64_t q = 0; q < isplits; ++q) {
+            const int64_t j0 = q * L;
+            const int64_t nj = std::min<int64_t>(L, N - j0);
             for (int64_t t = 0; t < tiles; ++t) {
                 PairItem it{};
                 it.sys = s;
@@ -307,15 +313,73 @@ static void build_pair_items(const ssm_ctx* c, const std::vector<int>& systems,
                 it.src0 = (int32_t)j0;
                 it.nsrc = (int32_t)nj;
                 it.split = (int32_t)q;
-                tmp.push_back({nj * std::min<int64_t>(tile, S.N - t * tile), it});
+                it.jrow = -1;
+                out.push_back({5 * nj * std::min<int64_t>(tile, N - t * tile), it});
             }
         }
+        if (nb_out) *nb_out = 0;
+        return isplits;
     }
+    for (int64_t a = 0; a < tiles; ++a) {
+        const int64_t t0 = a * tile;
+        const int64_t nt = std::min<int64_t>(tile, N - t0);
+        PairItem dg{};
+        dg.sys = s;
+        dg.tgt0 = (int32_t)t0;
+        dg.src0 = (int32_t)t0;
+        dg.nsrc = (int32_t)nt;
+        dg.split = 0;
+        dg.jrow = -1;
+        out.push_back({5 * nt * nt, dg});
+        int64_t q = 1;
+        for (int64_t j0 = t0 + tile; j0 < N; j0 += L, ++q) {
+            PairItem it{};
+            it.sys = s;
+            it.tgt0 = (int32_t)t0;
+            it.src0 = (int32_t)j0;
+            it.nsrc = (int32_t)std::min<int64_t>(L, N - j0);
+            it.split = (int32_t)q;
+            it.jrow = (int32_t)a;
+            out.push_back({6 * (int64_t)it.nsrc * tile + 64 * tile, it});
+        }
+        isplits = std::max(isplits, q);
+    }
+    if (nb_out) *nb_out = tiles;
+    return isplits;
+}
+
+// Longest first (stable), so that big items start early.
+static void order_items(std::vector<std::pair<int64_t, PairItem>>& tmp, std::vector<PairItem>& out)
+{
     std::stable_sort(tmp.begin(), tmp.end(),
                      [](const std::pair<int64_t, PairItem>& a, const std::pair<int64_t, PairItem>& b) {
                          return a.first > b.first;
                      });
     for (auto& p : tmp) out.push_back(p.second);
+}
+
+static void build_pair_items(const ssm_ctx* c, const std::vector<int>& systems, std::vector<PairItem>& out)
+{
+    std::vector<std::pair<int64_t, PairItem>> tmp;
+    for (int s : systems) plan_system(s, c->sys[s].N, c->R, c->sym, c->L, tmp, nullptr);
+    order_items(tmp, out);
+}
+
+// Default sources per item: about 16384 wavefront items per tick (16 per
+// SIMD) over the given sizes; at least 512 (ordered) / 256 (symmetric)
+// sources, a multiple of 64 / 16.  (Measured on MI355X: shorter items beat
+// longer ones down to this size for d = 1..3.)
+static int64_t default_L(const std::vector<int64_t>& Ns, int R, bool sym)
+{
+    const int64_t tile = 64 * (int64_t)R;
+    double work = 0.0;
+    for (int64_t N : Ns) {
+        const double tiles = (double)((N + tile - 1) / tile);
+        work += sym ? 0.5 * (double)N * (double)N / (double)tile : tiles * (double)N;
+    }
+    const double per_item = work / 16384.0;
+    if (sym) return std::max<int64_t>((int64_t)std::ceil(per_item / 16.0) * 16, 256);
+    return std::max<int64_t>((int64_t)std::ceil(per_item / 64.0) * 64, 512);
 }
 
 static void build_blk_items(const ssm_ctx* c, const std::vector<int>& systems, std::vector<BlkItem>& out)
@@ -353,8 +417,11 @@ static ssm_status launch_surrogate(ssm_ctx* c, int64_t ph)
 }
 
 template <typename T>
-static ssm_status launch_tick(ssm_ctx* c)
+static ssm_status launch_tick(ssm_ctx* c, bool capture)
 {
+    // eager launches pass the tick by value; a captured tick reads (and at its
+    // end advances) the device counter so that the graph can be replayed
+    const int64_t* tdev = capture ? c->dtick : nullptr;
     const int64_t ph = c->tick % c->max_stride;
     const int64_t np = c->pair_cnt[ph], nb = c->blk_cnt[ph];
     T* X = (T*)c->X;
@@ -374,7 +441,7 @@ static ssm_status launch_tick(ssm_ctx* c)
             if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
         }
         launch_pair<T>(d, c->R, c->prec == SSM_FP32_KAHAN, grid, c->stream, c->dpair + c->pair_off[ph],
-                       (int)np, c->dsys, Ys, c->P, c->Bp);
+                       (int)np, c->dsys, Ys, c->P, c->Bp, c->Bpj);
         HIP_TRY(hipGetLastError());
         if (c->profiling) {
             if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
@@ -388,7 +455,7 @@ static ssm_status launch_tick(ssm_ctx* c)
     if (check && nb > 0) {
         const BlkItem* items = c->dblk + c->blk_off[ph];
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_surr_err<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, items,
-                                             c->dsys, c->P, c->Bp, c->surr, c->smean, c->err_part));
+                                             c->dsys, c->P, c->Bp, c->Bpj, c->surr, c->smean, c->err_part));
         HIP_TRY(hipGetLastError());
     }
     const int use_surr = (run_surr && !check) ? 1 : 0;
@@ -400,16 +467,28 @@ static ssm_status launch_tick(ssm_ctx* c)
             if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
         }
         const BlkItem* items = c->dblk + c->blk_off[ph];
+        const unsigned gb = (unsigned)(nb * c->bm_lanes);
+#define SSM_BM(LPV) SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_brownian_sum<D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, \
+                                                         items, c->dsys, c->coef, c->P, c->tick, tdev, c->dW))
+        switch (c->bm_lanes) {
+            case 16: SSM_BM(16); break;
+            case 8: SSM_BM(8); break;
+            case 4: SSM_BM(4); break;
+            case 2: SSM_BM(2); break;
+            default: SSM_BM(1); break;
+        }
+#undef SSM_BM
+        HIP_TRY(hipGetLastError());
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_update<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream,
-                                             items, c->dsys, c->coef, c->P, c->tick, X, Y, Ys, c->Bp, c->surr,
+                                             items, c->dsys, c->coef, c->P, c->tick, tdev, X, Y, Ys, c->Bp, c->surr,
                                              c->smean, use_surr,
                                              make_float4((float)c->surr_gain[0], (float)c->surr_gain[1],
-                                                         (float)c->surr_gain[2], (float)c->surr_gain[3]),
+                                                         (float)c->surr_gain[2], (float)c->surr_gain[3]), c->dW, c->Bpj,
                                              c->psumX, c->psumY, c->nblk_tot, c->dflags));
         HIP_TRY(hipGetLastError());
         if (!c->fused) {
             SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_newton<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream,
-                                                 items, c->dsys, c->coef, c->P, c->tick, X, Y, Ys,
+                                                 items, c->dsys, c->coef, c->P, c->tick, tdev, X, Y, Ys,
                                                  c->psumX, c->psumY, c->nblk_tot, c->dflags));
             HIP_TRY(hipGetLastError());
         }
@@ -417,6 +496,10 @@ static ssm_status launch_tick(ssm_ctx* c)
             if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
             c->ev_update.push_back({e0, e1});
         }
+    }
+    if (capture) {
+        hipLaunchKernelGGL(k_tick_advance, dim3(1), dim3(64), 0, c->stream, c->dtick);
+        HIP_TRY(hipGetLastError());
     }
     if (surr_on) {
         if (use_surr) c->surr_ticks++;
@@ -454,9 +537,55 @@ static ssm_status launch_tick(ssm_ctx* c)
         c->surr_checks++;
         c->surr_fallback = !(err <= c->surr_tol);
     }
+    return SSM_OK;
+}
+
+static void advance_host(ssm_ctx* c)
+{
     for (auto& S : c->sys)
         if (c->tick % S.stride == 0) S.steps_done++;
     c->tick++;
+}
+
+// One tick: eager launches, or (graphs on, no profiling, no surrogate) the
+// replay of this phase's captured graph.
+template <typename T>
+static ssm_status run_tick(ssm_ctx* c)
+{
+    const bool graph_ok = c->use_graphs && !c->profiling && c->surr_check_every == 0;
+    if (!graph_ok) {
+        ssm_status st = launch_tick<T>(c, false);
+        if (st != SSM_OK) return st;
+        advance_host(c);
+        c->dtick_valid = false;
+        return SSM_OK;
+    }
+    const int64_t ph = c->tick % c->max_stride;
+    if (!c->dtick_valid) {
+        // the device counter lags after eager ticks: set it (value copied at the call)
+        const int64_t t = c->tick;
+        HIP_TRY(hipMemcpyAsync(c->dtick, &t, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        c->dtick_valid = true;
+    }
+    if (!c->phase_graph[ph]) {
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        ssm_status st = launch_tick<T>(c, true);
+        hipError_t he = hipStreamEndCapture(c->stream, &g);
+        if (st != SSM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(he));
+        hipGraphExec_t ex = nullptr;
+        he = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(he));
+        c->phase_graph[ph] = ex;
+    }
+    HIP_TRY(hipGraphLaunch(c->phase_graph[ph], c->stream));
+    advance_host(c);
     return SSM_OK;
 }
 
@@ -470,7 +599,7 @@ static ssm_status launch_init(ssm_ctx* c)
                                             c->nblk_tot));
     HIP_TRY(hipGetLastError());
     SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<T, D>), dim3(nb), dim3(kBlk), 0, c->stream, items, c->dsys,
-                                            c->coef, c->P, (int64_t)-1, (const T*)c->X, (T*)c->Y, (T*)c->Ys,
+                                            c->coef, c->P, (int64_t)-1, (const int64_t*)nullptr, (const T*)c->X, (T*)c->Y, (T*)c->Ys,
                                             c->psumX, c->psumY, c->nblk_tot, c->dflags));
     HIP_TRY(hipGetLastError());
     return SSM_OK;
@@ -563,23 +692,26 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     c->nblk_tot = blk;
     is_int_ratio(cfg->T, h_min, &c->ticks_total);
 
-    // pair tiling: R targets per lane, L sources per item
-    c->R = cfg->targets_per_lane > 0 ? cfg->targets_per_lane : 4;
-    if (cfg->sources_per_item > 0) {
-        c->L = cfg->sources_per_item;
-    } else {
-        // aim at ~8192 wavefronts per tick over all systems (8 per SIMD)
-        const int64_t tile = 64 * (int64_t)c->R;
-        double lane_pairs = 0.0;
-        for (auto& S : c->sys) lane_pairs += (double)((S.N + tile - 1) / tile) * tile * (double)S.N;
-        const double per_wave = lane_pairs / 8192.0 / (double)tile;
-        int64_t L = (int64_t)std::ceil(per_wave / 64.0) * 64;
-        c->L = std::max<int64_t>(L, 512);
+    // pair tiling: R targets per lane, L sources per item, scheme
+    // default: 4 targets per lane for d = 1, 2 for d >= 2 (fewer live registers
+    // per pair, measured faster on MI355X for both schemes)
+    c->R = cfg->targets_per_lane > 0 ? cfg->targets_per_lane : (c->d == 1 ? 4 : 2);
+    if (cfg->pair_scheme == 2 && c->prec == SSM_FP64) { free_ctx(c); return fail(SSM_ERR_INVALID, "the symmetric pair scheme is FP32 only"); }
+    c->sym = c->prec != SSM_FP64 && cfg->pair_scheme != 1;
+    {
+        std::vector<int64_t> Ns;
+        for (auto& S : c->sys) Ns.push_back(S.N);
+        c->L = cfg->sources_per_item > 0 ? (c->sym ? (cfg->sources_per_item + 15) / 16 * 16 : cfg->sources_per_item)
+                                         : default_L(Ns, c->R, c->sym);
     }
     c->max_splits = 1;
-    for (auto& S : c->sys) {
-        S.splits = (S.N + c->L - 1) / c->L;
-        c->max_splits = std::max(c->max_splits, S.splits);
+    c->nb_max = 0;
+    for (int s = 0; s < (int)c->sys.size(); ++s) {
+        std::vector<std::pair<int64_t, PairItem>> scratch;
+        int64_t nb = 0;
+        c->sys[s].splits = plan_system(s, c->sys[s].N, c->R, c->sym, c->L, scratch, &nb);
+        c->max_splits = std::max(c->max_splits, c->sys[s].splits);
+        c->nb_max = std::max(c->nb_max, nb);
     }
 
     // stream
@@ -594,6 +726,13 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     std::vector<PairItem> pairs;
     std::vector<BlkItem> blks;
     std::vector<int32_t> sys_lists;
+    {
+        int64_t rmax = 1;
+        for (auto& S : c->sys) rmax = std::max(rmax, S.r);
+        c->bm_lanes = rmax >= 16 ? 16 : rmax >= 8 ? 8 : rmax >= 4 ? 4 : rmax >= 2 ? 2 : 1;
+    }
+    c->phase_graph.assign(c->max_stride, nullptr);
+    c->use_graphs = cfg->graphs != 0;
     c->pair_off.resize(c->max_stride);
     c->pair_cnt.resize(c->max_stride);
     c->blk_off.resize(c->max_stride);
@@ -634,6 +773,8 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
         x.blk0 = (int32_t)S.blk0;
         x.nblk = (int32_t)S.nblk;
         x.splits = (int32_t)S.splits;
+        x.sym_B = c->sym ? 64 * c->R : 0;
+        x.sym_L = c->sym ? (int32_t)c->L : 0;
         x.h = S.h;
         x.pair_scale = c->has_pair ? cfg->b_g / ((double)S.N * cf.coord_scale) : 0.0;
         sd.push_back(x);
@@ -643,12 +784,15 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     ALLOC(c->Y, field);
     ALLOC(c->Ys, field);
     ALLOC(c->Bp, c->has_pair ? (size_t)c->max_splits * c->d * c->P * sizeof(double) : 0);
+    ALLOC(c->Bpj, (c->has_pair && c->sym) ? (size_t)std::max<int64_t>(c->nb_max - 1, 1) * c->d * c->P * sizeof(float) : 0);
     ALLOC(c->psumX, 2 * (size_t)(c->d + 1) * c->nblk_tot * sizeof(double));
     ALLOC(c->psumY, 2 * (size_t)c->d * c->nblk_tot * sizeof(double));
     ALLOC(c->dsys, sd.size() * sizeof(SysDev));
     ALLOC(c->dpair, std::max<size_t>(pairs.size(), 1) * sizeof(PairItem));
     ALLOC(c->dblk, blks.size() * sizeof(BlkItem));
     ALLOC(c->dflags, sizeof(Flags));
+    ALLOC(c->dtick, sizeof(int64_t));
+    ALLOC(c->dW, (size_t)c->d * c->P * sizeof(double));
     ALLOC(c->dsys_list, sys_lists.size() * sizeof(int32_t));
     int64_t maxN = 0;
     for (auto& S : c->sys) maxN = std::max(maxN, S.N);
@@ -659,6 +803,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     if (he == hipSuccess) he = hipMemcpyAsync(c->dblk, blks.data(), blks.size() * sizeof(BlkItem), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipMemcpyAsync(c->dsys_list, sys_lists.data(), sys_lists.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(c->dflags, 0, sizeof(Flags), c->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(c->dtick, 0, sizeof(int64_t), c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);  // host vectors go out of scope
     if (he != hipSuccess) { std::string m = hipGetErrorString(he); free_ctx(c); return fail(SSM_ERR_HIP, "upload: " + m); }
 
@@ -674,7 +819,7 @@ extern "C" ssm_status ssm_step(ssm_ctx* c, int64_t n_ticks)
     if (n_ticks < 0) return fail(SSM_ERR_INVALID, "n_ticks < 0");
     if (c->tick + n_ticks > c->ticks_total) return fail(SSM_ERR_STATE, "stepping past T");
     for (int64_t t = 0; t < n_ticks; ++t) {
-        ssm_status st = (c->prec == SSM_FP64) ? launch_tick<double>(c) : launch_tick<float>(c);
+        ssm_status st = (c->prec == SSM_FP64) ? run_tick<double>(c) : run_tick<float>(c);
         if (st != SSM_OK) return st;
     }
     return SSM_OK;
@@ -835,11 +980,11 @@ extern "C" ssm_status ssm_set_state(ssm_ctx* c, int32_t sys, const double* host)
     if (he == hipSuccess) {
         if (c->prec == SSM_FP64) {
             SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<double, D>), dim3((unsigned)items.size()), dim3(kBlk), 0, c->stream,
-                                                    ditems, c->dsys, c->coef, c->P, tick_arg, (const double*)c->X, (double*)c->Y,
+                                                    ditems, c->dsys, c->coef, c->P, tick_arg, (const int64_t*)nullptr, (const double*)c->X, (double*)c->Y,
                                                     (double*)c->Ys, c->psumX, c->psumY, c->nblk_tot, c->dflags));
         } else {
             SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<float, D>), dim3((unsigned)items.size()), dim3(kBlk), 0, c->stream,
-                                                    ditems, c->dsys, c->coef, c->P, tick_arg, (const float*)c->X, (float*)c->Y,
+                                                    ditems, c->dsys, c->coef, c->P, tick_arg, (const int64_t*)nullptr, (const float*)c->X, (float*)c->Y,
                                                     (float*)c->Ys, c->psumX, c->psumY, c->nblk_tot, c->dflags));
         }
         he = hipGetLastError();
@@ -908,6 +1053,7 @@ extern "C" ssm_status ssm_info(ssm_ctx* c, ssm_info_t* out)
     out->n_pair_items = (int32_t)c->pair_cnt[0];
     out->targets_per_lane = c->R;
     out->sources_per_item = (int32_t)c->L;
+    out->symmetric = c->sym ? 1 : 0;
     out->device_bytes = c->bytes;
     out->pair_launches = (int64_t)c->ev_pair.size();
     out->pair_ms = elapsed_ms(c->ev_pair);
@@ -938,28 +1084,54 @@ extern "C" void ssm_destroy(ssm_ctx* c) { free_ctx(c); }
 // ---------------------------------------------------------------------------
 // kernel-level entry points
 // ---------------------------------------------------------------------------
-static const int kPairR = 4;
+// Targets per lane of the kernel-level pair sum (the context default).
+static int kernel_R(int32_t d) { return d == 1 ? 4 : 2; }
 
-static void pair_plan(int64_t N, int64_t* L, int64_t* splits)
+// Plan of the kernel-level pair sum over one system of N particles.
+struct KPlan {
+    bool sym;
+    int64_t L, isplits, nb;
+    std::vector<PairItem> items;
+};
+
+static KPlan kernel_plan(int32_t d, int64_t N, int32_t precision)
 {
-    const int64_t tile = 64 * kPairR;
-    const double lane_pairs = (double)((N + tile - 1) / tile) * tile * (double)N;
-    int64_t l = (int64_t)std::ceil(lane_pairs / 8192.0 / (double)tile / 64.0) * 64;
-    *L = std::max<int64_t>(l, 512);
-    *splits = (N + *L - 1) / *L;
+    KPlan p{};
+    p.sym = precision != SSM_FP64;
+    p.L = default_L(std::vector<int64_t>{N}, kernel_R(d), p.sym);
+    std::vector<std::pair<int64_t, PairItem>> tmp;
+    p.isplits = plan_system(0, N, kernel_R(d), p.sym, p.L, tmp, &p.nb);
+    order_items(tmp, p.items);
+    return p;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+static size_t kernel_ws_bytes(int32_t d, int64_t N, int32_t precision, const KPlan& p)
+{
+    return align256(sizeof(SysDev)) + align256(p.items.size() * sizeof(PairItem)) +
+           align256((size_t)d * N * elt(precision)) + align256((size_t)p.isplits * d * N * sizeof(double)) +
+           align256((size_t)std::max<int64_t>(p.nb - 1, 1) * d * N * sizeof(float));
+}
+
+namespace ssm {
+template <int D>
+__global__ void k_combine_sys(const SysDev* __restrict__ sys, const double* __restrict__ Bp,
+                              const float* __restrict__ Bpj, int64_t P, double scale, double* __restrict__ K)
+{
+    const SysDev S = sys[0];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N) return;
+#pragma unroll
+    for (int k = 0; k < D; ++k) K[(int64_t)k * S.N + i] = pair_partials<D>(S, Bp, Bpj, k, P, i) * scale;
+}
+}  // namespace ssm
+
 extern "C" size_t ssm_pair_workspace_bytes(int32_t d, int64_t N, int32_t precision)
 {
-    if (d < 1 || d > SSM_MAX_D || N < 1) return 0;
-    int64_t L, splits;
-    pair_plan(N, &L, &splits);
-    const int64_t tile = 64 * kPairR;
-    const int64_t items = splits * ((N + tile - 1) / tile);
-    return align256(sizeof(SysDev)) + align256(items * sizeof(PairItem)) +
-           align256((size_t)d * N * elt(precision)) + align256((size_t)splits * d * N * sizeof(double));
+    if (d < 1 || d > SSM_MAX_D || N < 1 || N > 0x7fffffff - 1024) return 0;
+    if (precision < SSM_FP64 || precision > SSM_FP32_KAHAN) return 0;
+    return kernel_ws_bytes(d, N, precision, kernel_plan(d, N, precision));
 }
 
 extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, const void* Y, double ell,
@@ -970,45 +1142,42 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
     if (precision < SSM_FP64 || precision > SSM_FP32_KAHAN) return fail(SSM_ERR_INVALID, "unknown precision");
     if (!Y || !K || !workspace) return fail(SSM_ERR_INVALID, "NULL pointer");
     if (!(ell > 0.0)) return fail(SSM_ERR_INVALID, "ell must be > 0");
-    const size_t need = ssm_pair_workspace_bytes(d, N, precision);
+    const KPlan plan = kernel_plan(d, N, precision);
+    const size_t need = kernel_ws_bytes(d, N, precision, plan);
     if (workspace_bytes < need) return fail(SSM_ERR_INVALID, "workspace too small: need " + std::to_string(need));
     hipStream_t st = (hipStream_t)stream;
-    int64_t L, splits;
-    pair_plan(N, &L, &splits);
-    const int64_t tile = 64 * kPairR;
-    // plan on the host
     SysDev S{};
-    S.off = 0; S.N = (int32_t)N; S.stride = 1; S.r = 1; S.nblk = (int32_t)((N + kBlk - 1) / kBlk); S.splits = (int32_t)splits;
-    std::vector<PairItem> items;
-    for (int64_t q = 0; q < splits; ++q)
-        for (int64_t t = 0; t < (N + tile - 1) / tile; ++t) {
-            PairItem it{};
-            it.sys = 0; it.tgt0 = (int32_t)(t * tile); it.src0 = (int32_t)(q * L);
-            it.nsrc = (int32_t)std::min<int64_t>(L, N - q * L); it.split = (int32_t)q;
-            items.push_back(it);
-        }
+    S.off = 0;
+    S.N = (int32_t)N;
+    S.stride = 1;
+    S.r = 1;
+    S.nblk = (int32_t)((N + kBlk - 1) / kBlk);
+    S.splits = (int32_t)plan.isplits;
+    S.sym_B = plan.sym ? 64 * kernel_R(d) : 0;
+    S.sym_L = plan.sym ? (int32_t)plan.L : 0;
     char* w = (char*)workspace;
     SysDev* dS = (SysDev*)w; w += align256(sizeof(SysDev));
-    PairItem* dI = (PairItem*)w; w += align256(items.size() * sizeof(PairItem));
+    PairItem* dI = (PairItem*)w; w += align256(plan.items.size() * sizeof(PairItem));
     void* dYs = (void*)w; w += align256((size_t)d * N * elt(precision));
-    double* dBp = (double*)w;
+    double* dBp = (double*)w; w += align256((size_t)plan.isplits * d * N * sizeof(double));
+    float* dBpj = (float*)w;
     HIP_TRY(hipMemcpyAsync(dS, &S, sizeof(S), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(dI, items.data(), items.size() * sizeof(PairItem), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dI, plan.items.data(), plan.items.size() * sizeof(PairItem), hipMemcpyHostToDevice, st));
     const double c = std::sqrt(kLog2e / (2.0 * ell * ell));
     const int64_t n = (int64_t)d * N;
     const dim3 g1((unsigned)((n + 255) / 256));
-    const dim3 gp((unsigned)((items.size() + kWaves - 1) / kWaves));
+    const dim3 gp((unsigned)((plan.items.size() + kWaves - 1) / kWaves));
     if (precision == SSM_FP64) {
         hipLaunchKernelGGL(k_scale_copy<double>, g1, dim3(256), 0, st, (const double*)Y, (double*)dYs, n, c);
-        launch_pair<double>(d, kPairR, false, gp, st, dI, (int)items.size(), dS, (const double*)dYs, N, dBp);
+        launch_pair<double>(d, kernel_R(d), false, gp, st, dI, (int)plan.items.size(), dS, (const double*)dYs, N, dBp, dBpj);
     } else {
         hipLaunchKernelGGL(k_scale_copy<float>, g1, dim3(256), 0, st, (const float*)Y, (float*)dYs, n, c);
-        launch_pair<float>(d, kPairR, precision == SSM_FP32_KAHAN, gp, st, dI, (int)items.size(), dS, (const float*)dYs, N, dBp);
+        launch_pair<float>(d, kernel_R(d), precision == SSM_FP32_KAHAN, gp, st, dI, (int)plan.items.size(), dS, (const float*)dYs, N, dBp, dBpj);
     }
-    hipLaunchKernelGGL(k_combine, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, dBp, (int)splits, d, N, N,
-                       1.0 / ((double)N * c), K);
+    const dim3 gc((unsigned)((N + 255) / 256));
+    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine_sys<D>), gc, dim3(256), 0, st, dS, dBp, dBpj, N, 1.0 / ((double)N * c), K));
     HIP_TRY(hipGetLastError());
-    // the host-side item list must outlive the asynchronous copy
+    // the host-side plan must outlive the asynchronous copies
     HIP_TRY(hipStreamSynchronize(st));
     return SSM_OK;
 }
@@ -1159,10 +1328,10 @@ extern "C" ssm_status ssm_surrogate_samples(ssm_ctx* c, int32_t sys, int64_t n, 
     const int64_t np = c->pair_cnt[0], nb = c->blk_cnt[0];
     const int d = c->d;
     if (c->prec == SSM_FP64) {
-        launch_pair<double>(d, c->R, false, dim3((unsigned)((np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const double*)c->Ys, c->P, c->Bp);
+        launch_pair<double>(d, c->R, false, dim3((unsigned)((np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const double*)c->Ys, c->P, c->Bp, c->Bpj);
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<double, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const double*)c->Y, c->rff, c->rff_part));
     } else {
-        launch_pair<float>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)((np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const float*)c->Ys, c->P, c->Bp);
+        launch_pair<float>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)((np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const float*)c->Ys, c->P, c->Bp, c->Bpj);
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<float, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const float*)c->Y, c->rff, c->rff_part));
     }
     HIP_TRY(hipGetLastError());
@@ -1170,9 +1339,9 @@ extern "C" ssm_status ssm_surrogate_samples(ssm_ctx* c, int32_t sys, int64_t n, 
     HIP_TRY(hipGetLastError());
     const dim3 g((unsigned)((n + 255) / 256));
     if (c->prec == SSM_FP64) {
-        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_gather_samples<double, D>), g, dim3(256), 0, c->stream, c->dsys, sys, c->P, (const double*)c->Y, c->Bp, c->mom, n, seed, U, Tt));
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_gather_samples<double, D>), g, dim3(256), 0, c->stream, c->dsys, sys, c->P, (const double*)c->Y, c->Bp, c->Bpj, c->mom, n, seed, U, Tt));
     } else {
-        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_gather_samples<float, D>), g, dim3(256), 0, c->stream, c->dsys, sys, c->P, (const float*)c->Y, c->Bp, c->mom, n, seed, U, Tt));
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_gather_samples<float, D>), g, dim3(256), 0, c->stream, c->dsys, sys, c->P, (const float*)c->Y, c->Bp, c->Bpj, c->mom, n, seed, U, Tt));
     }
     HIP_TRY(hipGetLastError());
     return ssm_sync(c);

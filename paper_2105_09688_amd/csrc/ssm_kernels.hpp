@@ -32,7 +32,9 @@ struct SysDev {
     int32_t r;          // fine Brownian increments per step
     int32_t blk0;       // first global update block of the system
     int32_t nblk;       // update blocks of the system
-    int32_t splits;     // source ranges of the pair sum (partials to combine)
+    int32_t splits;     // i-side partial sums to combine (ordered-pair scheme)
+    int32_t sym_B;      // symmetric scheme: target block size (0: ordered-pair scheme)
+    int32_t sym_L;      // symmetric scheme: sources per off-diagonal work item
     int32_t pad;
     double h;           // time step
     double pair_scale;  // b_g / (N c): scaled pair sums -> b's pair term
@@ -43,8 +45,8 @@ struct PairItem {
     int32_t tgt0;   // first target (system-local)
     int32_t src0;   // first source (system-local)
     int32_t nsrc;   // sources in this item
-    int32_t split;  // which partial buffer
-    int32_t pad;
+    int32_t split;  // which i-side partial buffer
+    int32_t jrow;   // symmetric item: j-side partial row (target block index); -1: ordered pairs only
 };
 
 struct BlkItem {
@@ -86,6 +88,64 @@ template <>
 __device__ __forceinline__ double exp2_fast<double>(double x)
 {
     return exp2(x);
+}
+
+// sum_{q < splits} Bp[(q D + k) P + slot] in ascending q, with the loads
+// issued eight at a time (same rounding as the plain loop).
+template <int D>
+__device__ __forceinline__ double combine_splits(const double* __restrict__ Bp, int splits, int k, int64_t P,
+                                                 int64_t slot)
+{
+    double acc = 0.0;
+    int q0 = 0;
+    for (; q0 + 8 <= splits; q0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = Bp[((int64_t)(q0 + u) * D + k) * P + slot];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; q0 < splits; ++q0) acc += Bp[((int64_t)q0 * D + k) * P + slot];
+    return acc;
+}
+
+// Pair sum of particle i of a system under the symmetric scheme: i-side
+// partials (diagonal block, then the off-diagonal source ranges of i's block)
+// and j-side partials from every earlier target block, in that fixed order.
+template <int D>
+__device__ __forceinline__ double combine_sym(const SysDev& S, const double* __restrict__ Bp,
+                                              const float* __restrict__ Bpj, int k, int64_t P, int i)
+{
+    const int a = i / S.sym_B;
+    const int rest = S.N - S.sym_B * (a + 1);
+    const int ns = 1 + (rest > 0 ? (rest + S.sym_L - 1) / S.sym_L : 0);
+    const int64_t slot = S.off + i;
+    double acc = combine_splits<D>(Bp, ns, k, P, slot);
+    int q0 = 0;
+    for (; q0 + 8 <= a; q0 += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = Bpj[((int64_t)(q0 + u) * D + k) * P + slot];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (double)v[u];
+    }
+    for (; q0 < a; ++q0) acc += (double)Bpj[((int64_t)q0 * D + k) * P + slot];
+    return acc;
+}
+
+// Combined (unscaled) pair sum of particle i of system S, component k.
+template <int D>
+__device__ __forceinline__ double pair_partials(const SysDev& S, const double* __restrict__ Bp,
+                                                const float* __restrict__ Bpj, int k, int64_t P, int i)
+{
+    return S.sym_B ? combine_sym<D>(S, Bp, Bpj, k, P, i) : combine_splits<D>(Bp, S.splits, k, P, S.off + i);
+}
+
+// The tick a per-tick kernel works on: the context's device counter when
+// given (graph replays), else the value passed at launch.
+__device__ __forceinline__ int64_t tick_of(const int64_t* tick_dev, int64_t tick_arg)
+{
+    return tick_dev ? *tick_dev : tick_arg;
 }
 
 // Fixed-order tree sum of one double per thread over a kBlk-thread block.
@@ -203,12 +263,14 @@ __device__ __forceinline__ void solve_and_store(const SysDev& S, const Coef& cf,
 // ---------------------------------------------------------------------------
 // k_newton: Y* = F_h(X) for the listed blocks.  `done` is the number of steps
 // each listed system has completed: (tick / stride) + 1 after an update on
-// `tick`, or 0 at initialisation (tick < 0).
+// `tick`, or 0 at initialisation (tick < 0).  The tick is *tick_dev (the
+// context's device tick counter) when tick_dev is non-null, else tick_arg.
 // ---------------------------------------------------------------------------
 template <typename T, int D>
 __global__ __launch_bounds__(kBlk) void k_newton(const BlkItem* __restrict__ items,
                                                  const SysDev* __restrict__ sys, Coef cf,
-                                                 int64_t P, int64_t tick,
+                                                 int64_t P, int64_t tick_arg,
+                                                 const int64_t* __restrict__ tick_dev,
                                                  const T* __restrict__ X, T* __restrict__ Y,
                                                  T* __restrict__ Ys,
                                                  const double* __restrict__ psumX,
@@ -218,6 +280,7 @@ __global__ __launch_bounds__(kBlk) void k_newton(const BlkItem* __restrict__ ite
     __shared__ double red[kBlk];
     const BlkItem it = items[blockIdx.x];
     const SysDev S = sys[it.sys];
+    const int64_t tick = tick_of(tick_dev, tick_arg);
     const int64_t done = tick < 0 ? 0 : tick / S.stride + 1;
     const int par = (int)(done & 1);
     const double* pX = psumX + (int64_t)par * (D + 1) * nblk_tot;
@@ -243,18 +306,22 @@ __global__ __launch_bounds__(kBlk) void k_newton(const BlkItem* __restrict__ ite
 }
 
 // ---------------------------------------------------------------------------
-// k_update: eq. (2.4) for the listed blocks at `tick`, then (fused) the
-// implicit step (2.3) of the next step.
+// k_update: eq. (2.4) for the listed blocks at the tick *tick_dev (the
+// context's device tick counter), with the Brownian increments of
+// k_brownian_sum, then (fused) the implicit step (2.3) of the next step.
 // ---------------------------------------------------------------------------
 template <typename T, int D>
 __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ items,
                                                  const SysDev* __restrict__ sys, Coef cf,
-                                                 int64_t P, int64_t tick, T* __restrict__ X,
+                                                 int64_t P, int64_t tick_arg,
+                                                 const int64_t* __restrict__ tick_dev,
+                                                 T* __restrict__ X,
                                                  T* __restrict__ Y, T* __restrict__ Ys,
                                                  const double* __restrict__ Bp,
                                                  const float* __restrict__ surr,
                                                  const float* __restrict__ surr_mean, int use_surr,
-                                                 float4 surr_gain,
+                                                 float4 surr_gain, const double* __restrict__ dWbuf,
+                                                 const float* __restrict__ Bpj,
                                                  double* __restrict__ psumX,
                                                  double* __restrict__ psumY, int64_t nblk_tot,
                                                  Flags* flags)
@@ -262,7 +329,7 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
     __shared__ double red[kBlk];
     const BlkItem it = items[blockIdx.x];
     const SysDev S = sys[it.sys];
-    const int64_t n = tick / S.stride;  // step index of this update
+    const int64_t n = tick_of(tick_dev, tick_arg) / S.stride;  // step index of this update
     const int par_in = (int)(n & 1);
     const int par_out = par_in ^ 1;
     // mean of mu^Y_n
@@ -274,14 +341,6 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
     const int64_t slot = S.off + i;
     double xn[kMaxD] = {0.0, 0.0, 0.0, 0.0};
     if (valid) {
-        double zs[kMaxD] = {0.0, 0.0, 0.0, 0.0};
-        const uint64_t nf0 = (uint64_t)n * (uint64_t)S.r;
-        for (int m = 0; m < S.r; ++m) {
-            double z[kMaxD];
-            normals(cf.seed, 0u, (uint64_t)i, nf0 + (uint64_t)m, (uint64_t)S.ens, D, z);
-#pragma unroll
-            for (int k = 0; k < D; ++k) zs[k] += z[k];
-        }
         bool bad = false;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -293,12 +352,11 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
                 const float gk = k == 0 ? surr_gain.x : k == 1 ? surr_gain.y : k == 2 ? surr_gain.z : surr_gain.w;
                 pair = (double)gk * ((double)surr[k * P + slot] - (double)surr_mean[(int64_t)it.sys * kMaxD + k]);
             } else if (cf.has_pair) {
-                for (int q = 0; q < S.splits; ++q) pair += Bp[((int64_t)q * D + k) * P + slot];
-                pair *= S.pair_scale;
+                pair = pair_partials<D>(S, Bp, Bpj, k, P, i) * S.pair_scale;
             }
             const double b = cf.b_c0 * y + cf.b_lam * ybar[k] + pair;
             const double sig = cf.s0[k] + cf.s1[k] * y + cf.s2[k] * ybar[k];
-            const double dW = cf.sqrt_hf * zs[k];
+            const double dW = dWbuf[k * P + slot];
             xn[k] = (y + S.h * b) + sig * dW;
             bad |= !isfinite(xn[k]);
         }
@@ -327,6 +385,52 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
         const double s2 = block_sum(valid ? n2 : 0.0, red);
         if (threadIdx.x == 0) pX[(int64_t)D * nblk_tot + gb] = s2;
     }
+}
+
+// ---------------------------------------------------------------------------
+// k_brownian_sum: dW_n^i = sqrt(h_fine) sum_{m < r} Z(0, i, n r + m, ens) for
+// the listed blocks at the tick *tick_dev.  LP lanes (a power of two <= 16)
+// share one particle: lane q sums the normals m = q, q + LP, ... in order,
+// then the LP partial sums are combined by a fixed butterfly.  Block b of the
+// grid handles sub-block b % LP of item b / LP (256 / LP particles).
+// ---------------------------------------------------------------------------
+template <int D, int LP>
+__global__ __launch_bounds__(kBlk) void k_brownian_sum(const BlkItem* __restrict__ items,
+                                                       const SysDev* __restrict__ sys, Coef cf,
+                                                       int64_t P, int64_t tick_arg,
+                                                       const int64_t* __restrict__ tick_dev,
+                                                       double* __restrict__ dW)
+{
+    const BlkItem it = items[blockIdx.x / LP];
+    const int sub = blockIdx.x % LP;
+    const SysDev S = sys[it.sys];
+    const int q = threadIdx.x % LP;
+    const int i = it.blk * kBlk + sub * (kBlk / LP) + threadIdx.x / LP;
+    const int64_t n = tick_of(tick_dev, tick_arg) / S.stride;
+    double zs[kMaxD] = {0.0, 0.0, 0.0, 0.0};
+    if (i < S.N) {
+        const uint64_t nf0 = (uint64_t)n * (uint64_t)S.r;
+        for (int m = q; m < S.r; m += LP) {
+            double z[kMaxD];
+            normals(cf.seed, 0u, (uint64_t)i, nf0 + (uint64_t)m, (uint64_t)S.ens, D, z);
+#pragma unroll
+            for (int k = 0; k < D; ++k) zs[k] += z[k];
+        }
+    }
+#pragma unroll
+    for (int w = LP / 2; w > 0; w >>= 1)
+#pragma unroll
+        for (int k = 0; k < D; ++k) zs[k] += __shfl_xor(zs[k], w, 64);
+    if (q == 0 && i < S.N) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) dW[k * P + S.off + i] = cf.sqrt_hf * zs[k];
+    }
+}
+
+// Advance the context's device tick counter (last launch of every tick).
+__global__ void k_tick_advance(int64_t* tick_dev)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *tick_dev += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -386,12 +490,181 @@ __device__ __forceinline__ void pair_block(const T* __restrict__ src, int64_t P,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Symmetric (FP32) work item: each unordered pair (i, j), i in the wavefront's
+// target block and j in the item's source range, is evaluated once; +q goes to
+// i and -q to j (q = (s_j - s_i) exp2(-|s_j - s_i|^2) is odd in (i, j)).
+// Sources come in chunks of 16, one per lane of each 16-lane row (the four
+// rows see the same chunk).  At step k lane p reads the source of lane
+// (p + k) % 16 with DPP row_ror:(16 - k), so no source moves; its q's go to
+// the i-side accumulators and to a per-step j-side accumulator, and after the
+// 16 steps the per-step accumulators are sent to their owners with
+// row_ror:k, summed over the rows and written as the chunk's j-side partial.
+// Out-of-range targets and sources sit at +-1e15: their terms are exactly 0.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ float dpp_ror(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + N, 0xF, 0xF, false));
+}
+
+template <int D, int R, int K>
+__device__ __forceinline__ void sym_step(const float (&s)[D], const float (&yi)[R][D], float (&acc)[R][D],
+                                         float (&accj)[16][D])
+{
+    float sk[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) sk[c] = (K == 0) ? s[c] : dpp_ror<(16 - K) & 15>(s[c]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float z[D];
+        float t = 0.0f;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            z[c] = sk[c] - yi[r][c];
+            t = (c == 0) ? z[c] * z[c] : fmaf(z[c], z[c], t);
+        }
+        const float e = __builtin_amdgcn_exp2f(-t);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            acc[r][c] = fmaf(z[c], e, acc[r][c]);
+            accj[K][c] = fmaf(z[c], e, accj[K][c]);
+        }
+    }
+}
+
+template <int D, int K>
+__device__ __forceinline__ void sym_route(const float (&accj)[16][D], float (&tot)[D])
+{
+#pragma unroll
+    for (int c = 0; c < D; ++c) tot[c] += dpp_ror<K>(accj[K][c]);
+}
+
+template <int D, int R>
+__device__ __forceinline__ void sym_chunk(const float* __restrict__ base, int64_t P, int c0, int c_end,
+                                          const float (&yi)[R][D], float (&acc)[R][D], float* __restrict__ Bpj_row,
+                                          int64_t jslot0)
+{
+    const int lane = threadIdx.x & 63;
+    const int p = lane & 15;
+    const int j = c0 + p;
+    const bool vj = j < c_end;
+    float s[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) s[c] = vj ? base[c * P + j] : 1e15f;
+    float accj[16][D];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int c = 0; c < D; ++c) accj[k][c] = 0.0f;
+    sym_step<D, R, 0>(s, yi, acc, accj);
+    sym_step<D, R, 1>(s, yi, acc, accj);
+    sym_step<D, R, 2>(s, yi, acc, accj);
+    sym_step<D, R, 3>(s, yi, acc, accj);
+    sym_step<D, R, 4>(s, yi, acc, accj);
+    sym_step<D, R, 5>(s, yi, acc, accj);
+    sym_step<D, R, 6>(s, yi, acc, accj);
+    sym_step<D, R, 7>(s, yi, acc, accj);
+    sym_step<D, R, 8>(s, yi, acc, accj);
+    sym_step<D, R, 9>(s, yi, acc, accj);
+    sym_step<D, R, 10>(s, yi, acc, accj);
+    sym_step<D, R, 11>(s, yi, acc, accj);
+    sym_step<D, R, 12>(s, yi, acc, accj);
+    sym_step<D, R, 13>(s, yi, acc, accj);
+    sym_step<D, R, 14>(s, yi, acc, accj);
+    sym_step<D, R, 15>(s, yi, acc, accj);
+    float tot[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) tot[c] = accj[0][c];
+    sym_route<D, 1>(accj, tot);
+    sym_route<D, 2>(accj, tot);
+    sym_route<D, 3>(accj, tot);
+    sym_route<D, 4>(accj, tot);
+    sym_route<D, 5>(accj, tot);
+    sym_route<D, 6>(accj, tot);
+    sym_route<D, 7>(accj, tot);
+    sym_route<D, 8>(accj, tot);
+    sym_route<D, 9>(accj, tot);
+    sym_route<D, 10>(accj, tot);
+    sym_route<D, 11>(accj, tot);
+    sym_route<D, 12>(accj, tot);
+    sym_route<D, 13>(accj, tot);
+    sym_route<D, 14>(accj, tot);
+    sym_route<D, 15>(accj, tot);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        tot[c] += __shfl_xor(tot[c], 16, 64);
+        tot[c] += __shfl_xor(tot[c], 32, 64);
+    }
+    if (lane < 16 && vj) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) Bpj_row[c * P + jslot0 + j] = -tot[c];
+    }
+}
+
+template <int D, int R, bool KAHAN>
+__device__ __forceinline__ void pair_item_sym(const PairItem& it, const SysDev& S, const float* __restrict__ base,
+                                              int64_t P, double* __restrict__ Bp, float* __restrict__ Bpj)
+{
+    const int lane = threadIdx.x & 63;
+    float yi[R][D];
+    bool valid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = it.tgt0 + lane + 64 * r;
+        valid[r] = i < S.N;
+#pragma unroll
+        for (int c = 0; c < D; ++c) yi[r][c] = valid[r] ? base[c * P + i] : -1e15f;
+    }
+    float acc[R][D], hi[R][D], lo[R][D];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            acc[r][c] = 0.0f;
+            hi[r][c] = 0.0f;
+            lo[r][c] = 0.0f;
+        }
+    float* Bpj_row = Bpj + (int64_t)it.jrow * D * P;
+    const int c_end = it.src0 + it.nsrc;
+    int chunks = 0;
+    for (int c0 = it.src0; c0 < c_end; c0 += 16) {
+        sym_chunk<D, R>(base, P, c0, c_end, yi, acc, Bpj_row, S.off);
+        if constexpr (KAHAN) {
+            if (++chunks == kKahanChunk / 16 || c0 + 16 >= c_end) {
+                chunks = 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        const float a = acc[r][c];
+                        const float sm = hi[r][c] + a;
+                        const float err = (fabsf(hi[r][c]) >= fabsf(a)) ? (hi[r][c] - sm) + a : (a - sm) + hi[r][c];
+                        lo[r][c] += err;
+                        hi[r][c] = sm;
+                        acc[r][c] = 0.0f;
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = it.tgt0 + lane + 64 * r;
+        if (!valid[r]) continue;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const double v = KAHAN ? (double)hi[r][c] + (double)lo[r][c] : (double)acc[r][c];
+            Bp[((int64_t)it.split * D + c) * P + S.off + i] = v;
+        }
+    }
+}
+
 template <typename T, int D, int R, bool KAHAN>
 __global__ __launch_bounds__(64 * kWaves) void k_pair(const PairItem* __restrict__ items,
                                                       int n_items,
                                                       const SysDev* __restrict__ sys,
                                                       const T* __restrict__ Ys, int64_t P,
-                                                      double* __restrict__ Bp)
+                                                      double* __restrict__ Bp, float* __restrict__ Bpj)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -400,6 +673,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair(const PairItem* __restrict
     const PairItem it = items[idx];
     const SysDev S = sys[it.sys];
     const T* __restrict__ base = Ys + S.off;
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (it.jrow >= 0) {
+            pair_item_sym<D, R, KAHAN>(it, S, (const float*)base, P, Bp, Bpj);
+            return;
+        }
+    }
 
     T yi[R][D];
     bool valid[R];
@@ -481,9 +760,6 @@ __global__ void k_scale_copy(const T* __restrict__ in, T* __restrict__ out, int6
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g < n) out[g] = (T)(c * (double)in[g]);
 }
-
-__global__ void k_combine(const double* __restrict__ Bp, int splits, int d, int64_t P, int64_t N,
-                          double scale, double* __restrict__ K);
 
 __global__ void k_brownian(int d, int64_t N, uint64_t seed, int32_t ens, int64_t n0, int32_t r,
                            double sqrt_hf, double* __restrict__ dW);

@@ -402,7 +402,8 @@ __global__ __launch_bounds__(256) void k_mlp_apply(const float* __restrict__ U, 
 // at particle i, for n draws of i (Philox tag 4, counter (q, 0, 1)).
 template <typename T, int D>
 __global__ void k_gather_samples(const SysDev* __restrict__ sys, int s, int64_t P, const T* __restrict__ Y,
-                                 const double* __restrict__ Bp, const float* __restrict__ mom, int64_t n,
+                                 const double* __restrict__ Bp, const float* __restrict__ Bpj,
+                                 const float* __restrict__ mom, int64_t n,
                                  uint64_t seed, float* __restrict__ U, float* __restrict__ Tt)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -415,9 +416,7 @@ __global__ void k_gather_samples(const SysDev* __restrict__ sys, int s, int64_t 
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         U[q * in + k] = (float)Y[k * P + slot];
-        double pair = 0.0;
-        for (int p = 0; p < S.splits; ++p) pair += Bp[((int64_t)p * D + k) * P + slot];
-        Tt[q * D + k] = (float)(pair * S.pair_scale);
+        Tt[q * D + k] = (float)(pair_partials<D>(S, Bp, Bpj, k, P, (int)i) * S.pair_scale);
     }
     for (int m = 0; m < 2 * kRff; ++m) U[q * in + D + m] = mom[(int64_t)s * (2 * kRff) + m];
 }
@@ -684,6 +683,7 @@ template <typename T, int D>
 __global__ __launch_bounds__(kBlk) void k_surr_err(const BlkItem* __restrict__ items,
                                                    const SysDev* __restrict__ sys, int64_t P,
                                                    const double* __restrict__ Bp,
+                                                   const float* __restrict__ Bpj,
                                                    const float* __restrict__ surr,
                                                    const float* __restrict__ surr_mean,
                                                    double* __restrict__ err_part /*[nblk][kErrStats]*/)
@@ -697,9 +697,7 @@ __global__ __launch_bounds__(kBlk) void k_surr_err(const BlkItem* __restrict__ i
         const int64_t slot = S.off + i;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            double pair = 0.0;
-            for (int q = 0; q < S.splits; ++q) pair += Bp[((int64_t)q * D + k) * P + slot];
-            pair *= S.pair_scale;
+            const double pair = pair_partials<D>(S, Bp, Bpj, k, P, i) * S.pair_scale;
             const double sv = (double)surr[k * P + slot] - (double)surr_mean[(int64_t)it.sys * kMaxD + k];
             const double df = sv - pair;
             e2 += df * df;

@@ -32,7 +32,8 @@ class SSM:
     ``workload`` is the dict of ``paper_2105_09688_amd.workloads``."""
 
     def __init__(self, workload: dict, precision: str = "fp64", stream=None,
-                 targets_per_lane: int = 0, sources_per_item: int = 0):
+                 targets_per_lane: int = 0, sources_per_item: int = 0, graphs: bool = False,
+                 pair_scheme: str = "default"):
         lib = _lib.load()
         w = workload
         d = int(w["d"])
@@ -60,6 +61,8 @@ class SSM:
         c.stream = _stream_ptr(stream)
         c.targets_per_lane = int(targets_per_lane)
         c.sources_per_item = int(sources_per_item)
+        c.graphs = 1 if graphs else 0
+        c.pair_scheme = {"default": 0, "ordered": 1, "symmetric": 2}[pair_scheme]
         self._cfg = c
         h = C.c_void_p()
         check(lib.ssm_init(C.byref(c), C.byref(h)))
@@ -153,6 +156,8 @@ class SSM:
         check(_lib.load().ssm_info(self._h, C.byref(i)))
         out = {f: getattr(i, f) for f, _ in i._fields_}
         out["surr_gain"] = list(out["surr_gain"])[: self.d]
+        out["pair_scheme"] = "symmetric" if out.pop("symmetric") else "ordered"
+        out.pop("pad", None)
         return out
 
 

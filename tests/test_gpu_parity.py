@@ -350,3 +350,68 @@ def test_batched_levels_rmse_match_oracle_within_5_percent(torch_cuda):
             r_g, r_o = math.sqrt(sq_g / cnt), math.sqrt(sq_o / cnt)
             _say(f"level 2^-{l}: rmse gpu {r_g:.6e} oracle {r_o:.6e}")
             assert abs(r_g - r_o) <= 0.05 * r_o
+
+
+def test_graph_replays_match_eager_bitwise(torch_cuda):
+    """Each tick phase's captured graph is replayed many times, with eager work
+    (state copies, moments) and synchronizations between replays; every
+    checked state equals the eager run's bitwise."""
+    sizes = [300, 1000, 65]
+    w = W.batched(n_ens=3, levels=(4, 5, 6), h_fine=2.0 ** -8, sizes=sizes)
+    w["T"] = 0.5
+    with _ssm(w, "fp32_kahan") as eager, _ssm(w, "fp32_kahan", graphs=True) as g:
+        ticks = eager.info()["ticks_total"]
+        for t in range(ticks):
+            eager.step(1)
+            g.step(1)
+            if t % 5 == 0 or t == ticks - 1:
+                _say(f"graph replay tick {t}")
+                for k in range(len(w["systems"])):
+                    assert np.array_equal(eager.state(k), g.state(k)), (t, k)
+                    assert np.array_equal(eager.state(k, "y"), g.state(k, "y")), (t, k)
+                m1, _ = eager.moments(0)
+                m2, _ = g.moments(0)
+                assert np.array_equal(m1, m2)
+        assert g.info()["tick"] == ticks
+    # one long graph-mode run equals the oracle
+    w2 = W.small_parity(n_ens=2, N=700)
+    w2["T"] = 2.0 ** -3
+    ref = oracle.run(w2)
+    with _ssm(w2, "fp64", graphs=True) as s:
+        s.run()
+        for e in range(2):
+            assert _err(s.state(e), ref[e]) <= FP64_TOL
+
+
+def test_symmetric_and_ordered_schemes_agree(torch_cuda):
+    """The symmetric pair scheme (each unordered pair once, +q / -q) and the
+    ordered one give the same FP32 runs up to summation rounding, for every
+    dimension, for ragged sizes and across several target-block sizes."""
+    for w in (W.small_parity(n_ens=2, N=1500), W.precision_d3(N=777), W.surrogate_d2(N=1300, h_fine=2.0 ** -9)):
+        w["T"] = 2.0 ** -5 if w["d"] == 1 else 2.0 ** -6
+        base = None
+        for scheme, R, L in (("ordered", 2, 0), ("symmetric", 1, 64), ("symmetric", 2, 0), ("symmetric", 4, 272)):
+            _say(f"scheme d={w['d']} {scheme} R={R} L={L}")
+            with _ssm(w, "fp32_kahan", pair_scheme=scheme, targets_per_lane=R, sources_per_item=L) as s:
+                s.run()
+                got = s.states()
+                assert s.info()["pair_scheme"] == scheme
+            if base is None:
+                base = got
+            for g, b in zip(got, base):
+                assert _err(g, b) <= 2e-6
+
+
+def test_autotuner_choice_is_valid_and_cached(torch_cuda, tmp_path, monkeypatch):
+    from paper_2105_09688_amd.tune import autotune
+    monkeypatch.setenv("SSM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    w = W.single_gpu_d1(N=4096)
+    choice = autotune(w, "fp32_kahan", steps=2)
+    assert choice["pair_scheme"] in ("symmetric", "ordered") and choice["targets_per_lane"] in (1, 2, 4, 8)
+    assert (tmp_path / "tune.json").exists()
+    assert autotune(w, "fp32_kahan") == choice  # from the cache
+    ref = oracle.run(W.with_systems(w, [(4096, 0, 2.0 ** -10)]), stop_after=8)[0]
+    with _ssm(w, "fp32_kahan", targets_per_lane=choice["targets_per_lane"],
+              sources_per_item=choice["sources_per_item"], pair_scheme=choice["pair_scheme"]) as s:
+        s.step(8)
+        assert _err(s.state(0), ref) <= FP32_TOL
