@@ -71,13 +71,16 @@ typedef enum {
  * Systems: n_sys independent particle clouds advanced together.  System s has
  * N[s] particles, time step h[s] and ensemble id ens[s].  Brownian paths depend
  * on (ens, particle index) only, so systems of one ensemble with different h
- * see the same paths (Section 3 compares step sizes on the same paths).  The
- * increment over a step is the sum of the fine-grid increments
- *   dW_n^i = sqrt(h_fine) sum_{m < r} Z(0, i, n r + m, ens),  r = h / h_fine,
- * where Z(tag, i, n, e) are four standard normals: Philox4x64-10 (Salmon et
- * al., SC'11) of counter (i, n, e, tag << 32) under key (seed, 0), each word w
+ * see the same paths (Section 3 compares step sizes on the same paths).
+ * Z(tag, i, b, e) denotes four standard normals: Philox4x64-10 (Salmon et al.,
+ * SC'11) of counter (i, b, e, tag << 32) under key (seed, 0), each word w
  * mapped to u = ((w >> 11) + 0.5) 2^-53 and Box-Muller applied to (u0, u1) and
- * (u2, u3); component k uses normal k.  X_0^i = x0_mean + x0_std * Z(1, i, 0, ens).
+ * (u2, u3).  The Brownian stream of particle i is Z(0, i, 0, ens), Z(0, i, 1,
+ * ens), ... concatenated (normal q = component q % 4 of block q / 4), and fine
+ * step m, component k uses stream normal m d + k.  The increment over a step is
+ * the sum of its r = h / h_fine fine increments:
+ *   dW_{n,k}^i = sqrt(h_fine) sum_{m < r} (stream normal (n r + m) d + k).
+ * X_0^i = x0_mean + x0_std * Z(1, i, 0, ens) (component k uses normal k).
  *
  * Time: every h[s] must divide T and be an integer multiple of h_fine.  Let
  * h_min = min h[s]; a "tick" advances time by h_min, and system s takes a step
@@ -243,9 +246,10 @@ ssm_status ssm_implicit_solve(int32_t d, int64_t N, const double *X, double h, d
                               double v_a, double v_kappa, double v_lam, const double *xbar,
                               double m2, int32_t max_iter, double *Y, int32_t *iters, void *stream);
 
-/* Brownian increments of one step for particles 0..N-1 of ensemble ens:
- * dW[k][i] = sqrt(h_fine) sum_{m < r} Z(0, i, n0 + m, ens)_k.  dW: device [d][N]
- * double.  Asynchronous on stream. */
+/* Brownian increments over fine steps n0 .. n0 + r - 1 for particles
+ * 0..N-1 of ensemble ens: dW[k][i] = sqrt(h_fine) sum_{m < r} (stream normal
+ * (n0 + m) d + k of particle i).  dW: device [d][N] double.  Asynchronous on
+ * stream. */
 ssm_status ssm_brownian(int32_t d, int64_t N, uint64_t seed, int32_t ens, int64_t n0, int32_t r,
                         double h_fine, double *dW, void *stream);
 

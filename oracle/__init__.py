@@ -56,6 +56,10 @@ def _load():
     u64p = C.POINTER(C.c_uint64)
     lib.ssmo_philox4x64_10.argtypes = [u64p, u64p, u64p]
     lib.ssmo_normals4.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint64, dp]
+    lib.ssmo_stream_normal.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64]
+    lib.ssmo_stream_normal.restype = C.c_double
+    lib.ssmo_brownian.argtypes = [C.c_uint64, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int64,
+                                  C.c_double, dp]
     lib.ssmo_implicit.argtypes = [C.c_int, dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                   C.c_double, dp, C.c_double, C.c_int, dp]
     lib.ssmo_implicit.restype = C.c_int
@@ -118,6 +122,18 @@ def normals4(seed: int, tag: int, i: int, n: int, e: int) -> np.ndarray:
     z = np.zeros(4)
     lib.ssmo_normals4(seed, tag, i, n, e, _dp(z))
     return z
+
+
+def stream_normal(seed: int, i: int, e: int, q: int) -> float:
+    """Normal q of the Brownian stream of particle i, ensemble e (component q % 4 of block q / 4)."""
+    return float(_load().ssmo_stream_normal(seed, i, e, q))
+
+
+def brownian(seed: int, d: int, i: int, e: int, n0: int, r: int, h_fine: float) -> np.ndarray:
+    """Increment of particle i over fine steps n0 .. n0+r-1: [d]."""
+    dW = np.zeros(d)
+    _load().ssmo_brownian(seed, d, i, e, n0, r, h_fine, _dp(dW))
+    return dW
 
 
 # ---------------------------------------------------------------- scheme pieces

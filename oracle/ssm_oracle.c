@@ -79,6 +79,35 @@ void ssmo_normals4(uint64_t seed, uint32_t tag, uint64_t i, uint64_t n, uint64_t
     }
 }
 
+/* Normal number q of the Brownian stream of particle i in ensemble e: the
+ * stream is the concatenation of the four normals of blocks b = 0, 1, 2, ...
+ * of stream tag 0, so normal q is component q % 4 of block q / 4. */
+double ssmo_stream_normal(uint64_t seed, uint64_t i, uint64_t e, uint64_t q)
+{
+    double z[4];
+    ssmo_normals4(seed, 0u, i, q >> 2, e, z);
+    return z[q & 3];
+}
+
+void ssmo_brownian(uint64_t seed, int d, uint64_t i, uint64_t e, uint64_t n0, int64_t r, double h_fine,
+                   double *dW)
+{
+    double zsum[SSMO_MAX_D] = {0, 0, 0, 0};
+    const uint64_t q0 = n0 * (uint64_t)d;
+    const uint64_t q1 = q0 + (uint64_t)r * (uint64_t)d;
+    uint64_t cached = ~(uint64_t)0;
+    double z[4] = {0, 0, 0, 0};
+    for (uint64_t q = q0; q < q1; ++q) {
+        if ((q >> 2) != cached) {
+            cached = q >> 2;
+            ssmo_normals4(seed, 0u, i, cached, e, z);
+        }
+        zsum[(q - q0) % (uint64_t)d] += z[q & 3];
+    }
+    const double sq = sqrt(h_fine);
+    for (int k = 0; k < d; ++k) dW[k] = sq * zsum[k];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Implicit step (2.3), Lemma 4.1.                                          */
 /*                                                                          */
@@ -267,20 +296,14 @@ int ssmo_step(const ssmo_cfg *cfg, int32_t ens, int64_t N, double h, int64_t n,
     mean_of(d, N, Y, ybar);
 
     /* (2.4): X_{n+1}^i = Y*^i + b h + sigma dW */
-    const double sqrt_hf = sqrt(cfg->h_fine);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
-        double zsum[SSMO_MAX_D] = {0, 0, 0, 0};
-        for (int64_t m = 0; m < r; ++m) {
-            double z[4];
-            ssmo_normals4(cfg->seed, 0u, (uint64_t)i, (uint64_t)(n * r + m), (uint64_t)ens, z);
-            for (int k = 0; k < d; ++k) zsum[k] += z[k];
-        }
+        double dW[SSMO_MAX_D];
+        ssmo_brownian(cfg->seed, d, (uint64_t)i, (uint64_t)ens, (uint64_t)(n * r), r, cfg->h_fine, dW);
         for (int k = 0; k < d; ++k) {
             int64_t q = (int64_t)k * N + i;
-            double dW = sqrt_hf * zsum[k];
             double sig = cfg->s0[k] + cfg->s1[k] * Y[q] + cfg->s2[k] * ybar[k];
-            X[q] = (Y[q] + h * B[q]) + sig * dW;
+            X[q] = (Y[q] + h * B[q]) + sig * dW[k];
         }
     }
     for (int64_t q = 0; q < (int64_t)d * N; ++q)

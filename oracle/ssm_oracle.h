@@ -66,6 +66,16 @@ void ssmo_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t o
  * u = ((w >> 11) + 0.5) 2^-53 in (0,1); Box-Muller on (u0,u1) and (u2,u3). */
 void ssmo_normals4(uint64_t seed, uint32_t tag, uint64_t i, uint64_t n, uint64_t e, double z[4]);
 
+/* Brownian stream of particle i, ensemble e: normal q is component q % 4 of
+ * block q / 4 of stream tag 0 (ssmo_normals4(seed, 0, i, q / 4, e)). */
+double ssmo_stream_normal(uint64_t seed, uint64_t i, uint64_t e, uint64_t q);
+
+/* Increment over fine steps n0 .. n0 + r - 1 (grid step h_fine):
+ * dW[k] = sqrt(h_fine) sum_{m < r} stream normal (n0 + m) d + k, summed in
+ * ascending order. */
+void ssmo_brownian(uint64_t seed, int d, uint64_t i, uint64_t e, uint64_t n0, int64_t r, double h_fine,
+                   double *dW);
+
 /* Implicit step (2.3) for one particle: the unique c with c = x + h v(c, mu_X)
  * (Lemma 4.1), by safeguarded Newton on the radial cubic.  x, y are [d].
  * Returns the number of Newton iterations, or SSMO_ERR_NEWTON / SSMO_ERR_INVALID. */
@@ -87,7 +97,7 @@ void ssmo_pair_sum(int d, int64_t N, const double *Y, double ell, double *K);
 
 /* One SSM step (2.3)-(2.4) of one system in place.  X is [d][N].  n is the
  * step index (t_n = n h); the Brownian increment of particle i is
- * sqrt(h_fine) * sum_{m<r} Z(0, i, n r + m, ens) with r = h / h_fine.
+ * ssmo_brownian(seed, d, i, ens, n r, r, h_fine) with r = h / h_fine.
  * If Y_out is non-NULL it receives Y*_n.  Returns SSMO_OK or an error. */
 int ssmo_step(const ssmo_cfg *cfg, int32_t ens, int64_t N, double h, int64_t n,
               double *X, double *Y_out);

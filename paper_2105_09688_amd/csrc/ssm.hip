@@ -42,18 +42,16 @@ extern "C" const char* ssm_last_error(void) { return g_last_error.c_str(); }
 // ---------------------------------------------------------------------------
 namespace ssm {
 
-__global__ void k_brownian(int d, int64_t N, uint64_t seed, int32_t ens, int64_t n0, int32_t r,
-                           double sqrt_hf, double* __restrict__ dW)
+template <int D>
+__global__ void k_brownian(int64_t N, uint64_t seed, int32_t ens, int64_t n0, int32_t r, double sqrt_hf,
+                           double* __restrict__ dW)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double zs[kMaxD] = {0.0, 0.0, 0.0, 0.0};
-    for (int m = 0; m < r; ++m) {
-        double z[kMaxD];
-        normals(seed, 0u, (uint64_t)i, (uint64_t)(n0 + m), (uint64_t)ens, d, z);
-        for (int k = 0; k < d; ++k) zs[k] += z[k];
-    }
-    for (int k = 0; k < d; ++k) dW[(int64_t)k * N + i] = sqrt_hf * zs[k];
+    const uint64_t q0 = (uint64_t)n0 * D;
+    stream_sum<D>(seed, (uint64_t)i, (uint64_t)ens, q0, q0 + (uint64_t)r * D, q0 / 4, 1, zs);
+    for (int k = 0; k < D; ++k) dW[(int64_t)k * N + i] = sqrt_hf * zs[k];
 }
 
 __global__ void k_philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
@@ -727,9 +725,10 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     std::vector<BlkItem> blks;
     std::vector<int32_t> sys_lists;
     {
-        int64_t rmax = 1;
-        for (auto& S : c->sys) rmax = std::max(rmax, S.r);
-        c->bm_lanes = rmax >= 16 ? 16 : rmax >= 8 ? 8 : rmax >= 4 ? 4 : rmax >= 2 ? 2 : 1;
+        // Philox blocks per step and particle: about r d / 4
+        int64_t bmax = 1;
+        for (auto& S : c->sys) bmax = std::max<int64_t>(bmax, (S.r * c->d + 3) / 4);
+        c->bm_lanes = bmax >= 16 ? 16 : bmax >= 8 ? 8 : bmax >= 4 ? 4 : bmax >= 2 ? 2 : 1;
     }
     c->phase_graph.assign(c->max_stride, nullptr);
     c->use_graphs = cfg->graphs != 0;
@@ -1207,8 +1206,8 @@ extern "C" ssm_status ssm_brownian(int32_t d, int64_t N, uint64_t seed, int32_t 
 {
     if (d < 1 || d > SSM_MAX_D || N < 1 || r < 1 || n0 < 0 || !dW || !(h_fine > 0.0))
         return fail(SSM_ERR_INVALID, "bad argument");
-    hipLaunchKernelGGL(k_brownian, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, (hipStream_t)stream, d, N, seed, ens,
-                       n0, r, std::sqrt(h_fine), dW);
+    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_brownian<D>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
+                                         (hipStream_t)stream, N, seed, ens, n0, r, std::sqrt(h_fine), dW));
     HIP_TRY(hipGetLastError());
     return SSM_OK;
 }

@@ -388,12 +388,38 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
 }
 
 // ---------------------------------------------------------------------------
-// k_brownian_sum: dW_n^i = sqrt(h_fine) sum_{m < r} Z(0, i, n r + m, ens) for
-// the listed blocks at the tick *tick_dev.  LP lanes (a power of two <= 16)
-// share one particle: lane q sums the normals m = q, q + LP, ... in order,
-// then the LP partial sums are combined by a fixed butterfly.  Block b of the
-// grid handles sub-block b % LP of item b / LP (256 / LP particles).
+// Brownian increments.  The normals of particle i (ensemble e) form one
+// stream: normal q is component q % 4 of Philox block q / 4 of stream tag 0.
+// Fine step m, component k of a d-dimensional increment is normal m d + k, so
+// a step of r fine increments uses normals [n r d, (n + 1) r d).
+// stream_sum adds the normals of [q0, q1) that fall in the blocks
+// b = b_first, b_first + stride, ... (a lane's share), per component.
 // ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void stream_sum(uint64_t seed, uint64_t i, uint64_t e, uint64_t q0, uint64_t q1,
+                                           uint64_t b_first, uint64_t stride, double zs[kMaxD])
+{
+    for (uint64_t b = b_first; b * 4 < q1; b += stride) {
+        double z[kMaxD];
+        normals(seed, 0u, i, b, e, 4, z);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const uint64_t q = 4 * b + s;
+            if (q >= q0 && q < q1) {
+                const int k = (int)((q - q0) % (uint64_t)D);
+#pragma unroll
+                for (int c = 0; c < D; ++c)
+                    if (c == k) zs[c] += z[s];
+            }
+        }
+    }
+}
+
+// k_brownian_sum: dW_n^i = sqrt(h_fine) x (sum of the step's normals) for the
+// listed blocks at the tick *tick_dev (or tick_arg).  LP lanes (a power of two
+// <= 16) share one particle and take every LP-th Philox block of the step;
+// their partial sums are combined by a fixed butterfly.  Block g of the grid
+// handles sub-block g % LP of item g / LP (256 / LP particles).
 template <int D, int LP>
 __global__ __launch_bounds__(kBlk) void k_brownian_sum(const BlkItem* __restrict__ items,
                                                        const SysDev* __restrict__ sys, Coef cf,
@@ -409,13 +435,9 @@ __global__ __launch_bounds__(kBlk) void k_brownian_sum(const BlkItem* __restrict
     const int64_t n = tick_of(tick_dev, tick_arg) / S.stride;
     double zs[kMaxD] = {0.0, 0.0, 0.0, 0.0};
     if (i < S.N) {
-        const uint64_t nf0 = (uint64_t)n * (uint64_t)S.r;
-        for (int m = q; m < S.r; m += LP) {
-            double z[kMaxD];
-            normals(cf.seed, 0u, (uint64_t)i, nf0 + (uint64_t)m, (uint64_t)S.ens, D, z);
-#pragma unroll
-            for (int k = 0; k < D; ++k) zs[k] += z[k];
-        }
+        const uint64_t q0 = (uint64_t)n * (uint64_t)S.r * D;
+        const uint64_t q1 = q0 + (uint64_t)S.r * D;
+        stream_sum<D>(cf.seed, (uint64_t)i, (uint64_t)S.ens, q0, q1, q0 / 4 + q, LP, zs);
     }
 #pragma unroll
     for (int w = LP / 2; w > 0; w >>= 1)

@@ -38,8 +38,10 @@ def candidates(d: int, precision: str):
     return out
 
 
-def measure(workload: dict, precision: str, cand: dict, stream=None, steps: int = 8) -> float:
-    """Average pair-kernel time (ms) of `cand` over `steps` ticks after one warm tick."""
+def measure(workload: dict, precision: str, cand: dict, stream=None, steps: int = 24) -> float:
+    """Average time (ms) per tick of the pair and update kernels of `cand`
+    over `steps` ticks after one warm tick (the tiling sets both: the update
+    kernel combines the pair kernel's partial sums)."""
     kw = dict(precision=precision, stream=stream, targets_per_lane=cand["targets_per_lane"],
               pair_scheme=cand["pair_scheme"])
     with SSM(workload, **kw) as s:
@@ -56,10 +58,10 @@ def measure(workload: dict, precision: str, cand: dict, stream=None, steps: int 
         s.step(n)
         s.sync()
         i = s.info()
-    return i["pair_ms"] / max(1, i["pair_launches"])
+    return (i["pair_ms"] + i["update_ms"]) / max(1, i["pair_launches"])
 
 
-def autotune(workload: dict, precision: str = "fp32_kahan", stream=None, steps: int = 8,
+def autotune(workload: dict, precision: str = "fp32_kahan", stream=None, steps: int = 24,
              use_cache: bool = True, verbose: bool = False) -> dict:
     """Best tiling for `workload`: {"targets_per_lane", "sources_per_item", "pair_scheme"}."""
     key = _key(workload, precision)
@@ -81,7 +83,7 @@ def autotune(workload: dict, precision: str = "fp32_kahan", stream=None, steps: 
         if ms < best_ms:
             best_ms, best = ms, cand
     choice = {"targets_per_lane": best["targets_per_lane"], "sources_per_item": best["sources_per_item"],
-              "pair_scheme": best["pair_scheme"], "pair_ms": best_ms}
+              "pair_scheme": best["pair_scheme"], "tick_ms": best_ms}
     cache[key] = choice
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)

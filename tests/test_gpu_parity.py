@@ -55,16 +55,13 @@ def test_philox_blocks_bitwise(torch_cuda):
             assert np.array_equal(got[q], ref), q
 
 
-@pytest.mark.parametrize("d", [1, 2, 3, 4])
-def test_brownian_increments_match_oracle(torch_cuda, d):
+@pytest.mark.parametrize("d,r", [(1, 3), (1, 16), (2, 1), (3, 1), (3, 5), (4, 2)])
+def test_brownian_increments_match_oracle(torch_cuda, d, r):
     from paper_2105_09688_amd.ssm import brownian
-    N, seed, ens, n0, r, hf = 300, 7, 5, 17, 3, 2.0 ** -10
-    _say(f"brownian d={d}")
+    N, seed, ens, n0, hf = 300, 7, 5, 17, 2.0 ** -10
+    _say(f"brownian d={d} r={r}")
     got = brownian(d, N, seed, ens, n0, r, hf).cpu().numpy()
-    ref = np.zeros((d, N))
-    for i in range(N):
-        zs = sum(oracle.normals4(seed, 0, i, n0 + m, ens) for m in range(r))
-        ref[:, i] = math.sqrt(hf) * zs[:d]
+    ref = np.stack([oracle.brownian(seed, d, i, ens, n0, r, hf) for i in range(N)], axis=1)
     assert np.max(np.abs(got - ref)) <= 1e-13
 
 

@@ -63,6 +63,28 @@ def test_normals_are_standard_gaussian(oracle_mod):
     assert not np.array_equal(oracle_mod.normals4(0, 0, 5, 3, 1), oracle_mod.normals4(0, 0, 5, 3, 2))
 
 
+def test_brownian_stream_packing(oracle_mod):
+    """The Brownian stream of a particle is the concatenation of the four
+    normals of consecutive Philox blocks; fine step m, component k of a d-dim
+    increment is stream normal m d + k, and the increment sums them."""
+    for q in list(range(12)) + [1001, 4095]:
+        assert oracle_mod.stream_normal(5, 3, 2, q) == oracle_mod.normals4(5, 0, 3, q // 4, 2)[q % 4]
+    for d in (1, 2, 3, 4):
+        dW = oracle_mod.brownian(5, d, 3, 2, 7, 6, 2.0 ** -10)
+        for k in range(d):
+            ref = math.sqrt(2.0 ** -10) * math.fsum(oracle_mod.stream_normal(5, 3, 2, (7 + m) * d + k) for m in range(6))
+            assert dW[k] == pytest.approx(ref, rel=1e-14, abs=1e-16)
+    # increments of disjoint fine ranges are independent N(0, r h_fine)
+    r, hf, n = 4, 2.0 ** -8, 4000
+    a = np.array([oracle_mod.brownian(0, 2, i, 0, 0, r, hf) for i in range(n)])
+    b = np.array([oracle_mod.brownian(0, 2, i, 0, r, r, hf) for i in range(n)])
+    v = r * hf
+    for x in (a[:, 0], a[:, 1], b[:, 0]):
+        assert abs(x.var() / v - 1.0) < 5 * math.sqrt(2.0 / n)
+    assert abs(np.corrcoef(a[:, 0], b[:, 0])[0, 1]) < 5 / math.sqrt(n)
+    assert abs(np.corrcoef(a[:, 0], a[:, 1])[0, 1]) < 5 / math.sqrt(n)
+
+
 # --------------------------------------------------------------------------- implicit step (2.3)
 def _cardano(x, a, h):
     """Real root of y + a h y^3 = x (hyperbolic form of Cardano's formula)."""
@@ -220,7 +242,7 @@ def test_full_step_brute_force_small_N(oracle_mod):
         pair = sum((ys[j] - ys[i]) * mp.exp(-(ys[i] - ys[j]) ** 2 / 2) for j in range(N)) / N
         b = ys[i] + pair
         sig = mp.mpf(0.05) + mp.mpf(0.3) * ys[i] + mp.mpf(0.2) * ybar
-        zsum = sum(mp.mpf(oracle_mod.normals4(0, 0, i, n * r + m, e)[0]) for m in range(r))
+        zsum = sum(mp.mpf(oracle_mod.stream_normal(0, i, e, n * r + m)) for m in range(r))
         dW = mp.sqrt(mp.mpf(2.0 ** -8)) * zsum
         xn = ys[i] + b * mp.mpf(h) + sig * dW
         assert abs(mp.mpf(Y[0, i]) - ys[i]) < 1e-15
@@ -248,7 +270,7 @@ def test_ou_mean_recursion_pathwise(oracle_mod):
     r = 4
     for n in range(16):
         X, _ = oracle_mod.step(w, 0, h, n, X)
-        dW = np.array([math.sqrt(2.0 ** -7) * sum(oracle_mod.normals4(0, 0, i, n * r + m, 0)[0] for m in range(r))
+        dW = np.array([math.sqrt(2.0 ** -7) * sum(oracle_mod.stream_normal(0, i, 0, n * r + m) for m in range(r))
                        for i in range(N)])
         mean = (1 + h * lam) / (1 - h * rho) * mean + eta * dW.mean()
         assert X.mean() == pytest.approx(mean, rel=1e-12, abs=1e-13)
