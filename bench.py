@@ -403,7 +403,7 @@ def main():
         },
         "update_kernel_avg_ms": info["update_ms"] / max(1, info["update_launches"]),
         "tiling": {"targets_per_lane": info["targets_per_lane"], "sources_per_item": info["sources_per_item"],
-                   "pair_scheme": info["pair_scheme"], "wavefront_items": info["n_pair_items"],
+                   "pair_scheme": info["pair_scheme"], "pair_work_items": info["n_pair_items"],
                    "autotuned": bool(args.tune)},
     }
     if not args.no_check and args.precision != "fp64":

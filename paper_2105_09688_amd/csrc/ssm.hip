@@ -84,17 +84,41 @@ __global__ void k_implicit_plain(int64_t N, const double* __restrict__ X, double
 // ---------------------------------------------------------------------------
 // kernel dispatch tables (d, R, precision)
 // ---------------------------------------------------------------------------
+// Symmetric scheme: one workgroup per item.
+template <int D>
+static void launch_pair_sym_D(int R, bool kahan, int n, hipStream_t st, const PairItem* items, const SysDev* sys,
+                              const float* Ys, int64_t P, double* Bp, float* Bpj)
+{
+    dim3 grid((unsigned)n), block(64 * kWaves);
+#define SSM_SYM_CASE(RR)                                                                                   \
+    case RR:                                                                                               \
+        if (kahan)                                                                                         \
+            hipLaunchKernelGGL((k_pair_sym<D, RR, true>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj);  \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_pair_sym<D, RR, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj); \
+        break;
+    switch (R) {
+        SSM_SYM_CASE(1)
+        SSM_SYM_CASE(2)
+        SSM_SYM_CASE(4)
+        SSM_SYM_CASE(8)
+        default: break;
+    }
+#undef SSM_SYM_CASE
+}
+
 template <typename T, int D>
 static void launch_pair_T(int R, bool kahan, dim3 grid, hipStream_t st, const PairItem* items,
                           int n, const SysDev* sys, const T* Ys, int64_t P, double* Bp, float* Bpj)
 {
+    (void)Bpj;
     dim3 block(64 * kWaves);
 #define SSM_PAIR_CASE(RR)                                                                      \
     case RR:                                                                                   \
         if (kahan)                                                                             \
-            hipLaunchKernelGGL((k_pair<T, D, RR, true>), grid, block, 0, st, items, n, sys, Ys, P, Bp, Bpj); \
+            hipLaunchKernelGGL((k_pair<T, D, RR, true>), grid, block, 0, st, items, n, sys, Ys, P, Bp); \
         else                                                                                   \
-            hipLaunchKernelGGL((k_pair<T, D, RR, false>), grid, block, 0, st, items, n, sys, Ys, P, Bp, Bpj); \
+            hipLaunchKernelGGL((k_pair<T, D, RR, false>), grid, block, 0, st, items, n, sys, Ys, P, Bp); \
         break;
     switch (R) {
         SSM_PAIR_CASE(1)
@@ -106,10 +130,24 @@ static void launch_pair_T(int R, bool kahan, dim3 grid, hipStream_t st, const Pa
 #undef SSM_PAIR_CASE
 }
 
+// Pair kernel launch: ordered scheme one wavefront per item (kWaves items per
+// workgroup), symmetric scheme (FP32 only) one workgroup per item.
 template <typename T>
 static void launch_pair(int d, int R, bool kahan, dim3 grid, hipStream_t st, const PairItem* items,
-                        int n, const SysDev* sys, const T* Ys, int64_t P, double* Bp, float* Bpj)
+                        int n, const SysDev* sys, const T* Ys, int64_t P, double* Bp, float* Bpj, bool sym = false)
 {
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (sym) {
+            switch (d) {
+                case 1: launch_pair_sym_D<1>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
+                case 2: launch_pair_sym_D<2>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
+                case 3: launch_pair_sym_D<3>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
+                case 4: launch_pair_sym_D<4>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
+                default: break;
+            }
+            return;
+        }
+    }
     switch (d) {
         case 1: launch_pair_T<T, 1>(R, kahan, grid, st, items, n, sys, Ys, P, Bp, Bpj); break;
         case 2: launch_pair_T<T, 2>(R, kahan, grid, st, items, n, sys, Ys, P, Bp, Bpj); break;
@@ -288,10 +326,11 @@ static bool is_int_ratio(double a, double b, int64_t* out)
 // Work items of one system's pair sums.
 //  Ordered-pair scheme: tiles of 64 R targets x source ranges of L sources;
 //    i-side partial q = source range q.
-//  Symmetric scheme (FP32): target blocks of B = 64 R particles; block a has
-//    a diagonal item (its own sources, ordered pairs, partial 0) and items over
-//    the later sources [B (a+1), N) in ranges of L (partial 1, 2, ...), each
-//    also writing j-side partial row a.  Every unordered pair is visited once.
+//  Symmetric scheme (FP32): target groups of G = kWaves x 64 R particles
+//    (one workgroup); group a has a diagonal item (its own sources, ordered
+//    pairs, partial 0) and items over the later sources [G (a+1), N) in ranges
+//    of L (partial 1, 2, ...), each also writing j-side partial row a.  Every
+//    unordered pair is visited once.
 // Each item carries a cost estimate (VALU issue slots) for ordering.
 static int64_t plan_system(int s, int64_t N, int R, bool sym, int64_t L,
                            std::vector<std::pair<int64_t, PairItem>>& out, int64_t* nb_out)
@@ -318,9 +357,12 @@ static int64_t plan_system(int s, int64_t N, int R, bool sym, int64_t L,
         if (nb_out) *nb_out = 0;
         return isplits;
     }
-    for (int64_t a = 0; a < tiles; ++a) {
-        const int64_t t0 = a * tile;
-        const int64_t nt = std::min<int64_t>(tile, N - t0);
+    // symmetric: target groups of kWaves blocks, one workgroup per item
+    const int64_t group = tile * kWaves;
+    const int64_t groups = (N + group - 1) / group;
+    for (int64_t a = 0; a < groups; ++a) {
+        const int64_t t0 = a * group;
+        const int64_t nt = std::min<int64_t>(group, N - t0);
         PairItem dg{};
         dg.sys = s;
         dg.tgt0 = (int32_t)t0;
@@ -330,7 +372,7 @@ static int64_t plan_system(int s, int64_t N, int R, bool sym, int64_t L,
         dg.jrow = -1;
         out.push_back({5 * nt * nt, dg});
         int64_t q = 1;
-        for (int64_t j0 = t0 + tile; j0 < N; j0 += L, ++q) {
+        for (int64_t j0 = t0 + group; j0 < N; j0 += L, ++q) {
             PairItem it{};
             it.sys = s;
             it.tgt0 = (int32_t)t0;
@@ -338,11 +380,11 @@ static int64_t plan_system(int s, int64_t N, int R, bool sym, int64_t L,
             it.nsrc = (int32_t)std::min<int64_t>(L, N - j0);
             it.split = (int32_t)q;
             it.jrow = (int32_t)a;
-            out.push_back({6 * (int64_t)it.nsrc * tile + 64 * tile, it});
+            out.push_back({6 * (int64_t)it.nsrc * group + 64 * group, it});
         }
         isplits = std::max(isplits, q);
     }
-    if (nb_out) *nb_out = tiles;
+    if (nb_out) *nb_out = groups;
     return isplits;
 }
 
@@ -367,16 +409,22 @@ static void build_pair_items(const ssm_ctx* c, const std::vector<int>& systems, 
 // SIMD) over the given sizes; at least 512 (ordered) / 256 (symmetric)
 // sources, a multiple of 64 / 16.  (Measured on MI355X: shorter items beat
 // longer ones down to this size for d = 1..3.)
-static int64_t default_L(const std::vector<int64_t>& Ns, int R, bool sym)
+static int64_t default_L(const std::vector<int64_t>& Ns, int R, bool sym, int d)
 {
     const int64_t tile = 64 * (int64_t)R;
-    double work = 0.0;
-    for (int64_t N : Ns) {
-        const double tiles = (double)((N + tile - 1) / tile);
-        work += sym ? 0.5 * (double)N * (double)N / (double)tile : tiles * (double)N;
+    if (sym) {
+        // ~6144 workgroup items per tick (about 8 per resident workgroup
+        // slot: small enough a tail, few enough i-side partials)
+        const double group = (double)(tile * kWaves);
+        double work = 0.0;
+        for (int64_t N : Ns) work += 0.5 * (double)N * (double)N / group;
+        const int64_t L = (int64_t)std::ceil(work / 6144.0 / 16.0) * 16;
+        (void)d;
+        return std::max<int64_t>(L, 128);
     }
+    double work = 0.0;
+    for (int64_t N : Ns) work += (double)((N + tile - 1) / tile) * (double)N;
     const double per_item = work / 16384.0;
-    if (sym) return std::max<int64_t>((int64_t)std::ceil(per_item / 16.0) * 16, 256);
     return std::max<int64_t>((int64_t)std::ceil(per_item / 64.0) * 64, 512);
 }
 
@@ -431,7 +479,7 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
     const bool run_exact = !surr_on || check || c->surr_fallback;
     const bool run_surr = surr_on && (check || !c->surr_fallback);
     if (c->has_pair && np > 0 && run_exact) {
-        dim3 grid((unsigned)((np + kWaves - 1) / kWaves));
+        dim3 grid((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves));
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->profiling) {
             e0 = take_event(c);
@@ -439,7 +487,7 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
             if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
         }
         launch_pair<T>(d, c->R, c->prec == SSM_FP32_KAHAN, grid, c->stream, c->dpair + c->pair_off[ph],
-                       (int)np, c->dsys, Ys, c->P, c->Bp, c->Bpj);
+                       (int)np, c->dsys, Ys, c->P, c->Bp, c->Bpj, c->sym);
         HIP_TRY(hipGetLastError());
         if (c->profiling) {
             if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
@@ -696,20 +744,34 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     c->R = cfg->targets_per_lane > 0 ? cfg->targets_per_lane : (c->d == 1 ? 4 : 2);
     if (cfg->pair_scheme == 2 && c->prec == SSM_FP64) { free_ctx(c); return fail(SSM_ERR_INVALID, "the symmetric pair scheme is FP32 only"); }
     c->sym = c->prec != SSM_FP64 && cfg->pair_scheme != 1;
-    {
+    if (c->sym && (int64_t)64 * c->R * kWaves * c->d > kSymLDS) {
+        // a target group's j-side sums must fit the kernel's LDS buffer
+        if (cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "symmetric scheme: targets_per_lane too large for this d (64 x R x 4 x d must be <= 2048)"); }
+        c->sym = false;
+    }
+    for (int attempt = 0; attempt < 2; ++attempt) {
         std::vector<int64_t> Ns;
         for (auto& S : c->sys) Ns.push_back(S.N);
-        c->L = cfg->sources_per_item > 0 ? (c->sym ? (cfg->sources_per_item + 15) / 16 * 16 : cfg->sources_per_item)
-                                         : default_L(Ns, c->R, c->sym);
-    }
-    c->max_splits = 1;
-    c->nb_max = 0;
-    for (int s = 0; s < (int)c->sys.size(); ++s) {
-        std::vector<std::pair<int64_t, PairItem>> scratch;
-        int64_t nb = 0;
-        c->sys[s].splits = plan_system(s, c->sys[s].N, c->R, c->sym, c->L, scratch, &nb);
-        c->max_splits = std::max(c->max_splits, c->sys[s].splits);
-        c->nb_max = std::max(c->nb_max, nb);
+        if (cfg->sources_per_item > 0) {
+            c->L = c->sym ? (cfg->sources_per_item + 15) / 16 * 16 : cfg->sources_per_item;
+        } else {
+            c->L = default_L(Ns, c->R, c->sym, c->d);
+        }
+        c->max_splits = 1;
+        c->nb_max = 0;
+        for (int s = 0; s < (int)c->sys.size(); ++s) {
+            std::vector<std::pair<int64_t, PairItem>> scratch;
+            int64_t nb = 0;
+            c->sys[s].splits = plan_system(s, c->sys[s].N, c->R, c->sym, c->L, scratch, &nb);
+            c->max_splits = std::max(c->max_splits, c->sys[s].splits);
+            c->nb_max = std::max(c->nb_max, nb);
+        }
+        // the symmetric scheme's j-side partials take groups x d x P floats; past
+        // 32 GiB the default falls back to ordered pairs
+        const double jbytes = (double)c->nb_max * c->d * (double)c->P * sizeof(float);
+        if (!c->sym || jbytes <= 32.0 * (1ull << 30)) break;
+        if (cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "symmetric scheme needs more than 32 GiB of partial sums; raise targets_per_lane or use ordered pairs"); }
+        c->sym = false;
     }
 
     // stream
@@ -772,7 +834,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
         x.blk0 = (int32_t)S.blk0;
         x.nblk = (int32_t)S.nblk;
         x.splits = (int32_t)S.splits;
-        x.sym_B = c->sym ? 64 * c->R : 0;
+        x.sym_B = c->sym ? 64 * c->R * kWaves : 0;
         x.sym_L = c->sym ? (int32_t)c->L : 0;
         x.h = S.h;
         x.pair_scale = c->has_pair ? cfg->b_g / ((double)S.N * cf.coord_scale) : 0.0;
@@ -783,7 +845,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     ALLOC(c->Y, field);
     ALLOC(c->Ys, field);
     ALLOC(c->Bp, c->has_pair ? (size_t)c->max_splits * c->d * c->P * sizeof(double) : 0);
-    ALLOC(c->Bpj, (c->has_pair && c->sym) ? (size_t)std::max<int64_t>(c->nb_max - 1, 1) * c->d * c->P * sizeof(float) : 0);
+    ALLOC(c->Bpj, (c->has_pair && c->sym) ? (size_t)c->nb_max * c->d * c->P * sizeof(float) : 0);
     ALLOC(c->psumX, 2 * (size_t)(c->d + 1) * c->nblk_tot * sizeof(double));
     ALLOC(c->psumY, 2 * (size_t)c->d * c->nblk_tot * sizeof(double));
     ALLOC(c->dsys, sd.size() * sizeof(SysDev));
@@ -1097,7 +1159,7 @@ static KPlan kernel_plan(int32_t d, int64_t N, int32_t precision)
 {
     KPlan p{};
     p.sym = precision != SSM_FP64;
-    p.L = default_L(std::vector<int64_t>{N}, kernel_R(d), p.sym);
+    p.L = default_L(std::vector<int64_t>{N}, kernel_R(d), p.sym, d);
     std::vector<std::pair<int64_t, PairItem>> tmp;
     p.isplits = plan_system(0, N, kernel_R(d), p.sym, p.L, tmp, &p.nb);
     order_items(tmp, p.items);
@@ -1110,7 +1172,7 @@ static size_t kernel_ws_bytes(int32_t d, int64_t N, int32_t precision, const KPl
 {
     return align256(sizeof(SysDev)) + align256(p.items.size() * sizeof(PairItem)) +
            align256((size_t)d * N * elt(precision)) + align256((size_t)p.isplits * d * N * sizeof(double)) +
-           align256((size_t)std::max<int64_t>(p.nb - 1, 1) * d * N * sizeof(float));
+           align256((size_t)std::max<int64_t>(p.nb, 1) * d * N * sizeof(float));
 }
 
 namespace ssm {
@@ -1152,7 +1214,7 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
     S.r = 1;
     S.nblk = (int32_t)((N + kBlk - 1) / kBlk);
     S.splits = (int32_t)plan.isplits;
-    S.sym_B = plan.sym ? 64 * kernel_R(d) : 0;
+    S.sym_B = plan.sym ? 64 * kernel_R(d) * kWaves : 0;
     S.sym_L = plan.sym ? (int32_t)plan.L : 0;
     char* w = (char*)workspace;
     SysDev* dS = (SysDev*)w; w += align256(sizeof(SysDev));
@@ -1165,13 +1227,13 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
     const double c = std::sqrt(kLog2e / (2.0 * ell * ell));
     const int64_t n = (int64_t)d * N;
     const dim3 g1((unsigned)((n + 255) / 256));
-    const dim3 gp((unsigned)((plan.items.size() + kWaves - 1) / kWaves));
+    const dim3 gp((unsigned)(plan.sym ? plan.items.size() : (plan.items.size() + kWaves - 1) / kWaves));
     if (precision == SSM_FP64) {
         hipLaunchKernelGGL(k_scale_copy<double>, g1, dim3(256), 0, st, (const double*)Y, (double*)dYs, n, c);
         launch_pair<double>(d, kernel_R(d), false, gp, st, dI, (int)plan.items.size(), dS, (const double*)dYs, N, dBp, dBpj);
     } else {
         hipLaunchKernelGGL(k_scale_copy<float>, g1, dim3(256), 0, st, (const float*)Y, (float*)dYs, n, c);
-        launch_pair<float>(d, kernel_R(d), precision == SSM_FP32_KAHAN, gp, st, dI, (int)plan.items.size(), dS, (const float*)dYs, N, dBp, dBpj);
+        launch_pair<float>(d, kernel_R(d), precision == SSM_FP32_KAHAN, gp, st, dI, (int)plan.items.size(), dS, (const float*)dYs, N, dBp, dBpj, plan.sym);
     }
     const dim3 gc((unsigned)((N + 255) / 256));
     SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine_sys<D>), gc, dim3(256), 0, st, dS, dBp, dBpj, N, 1.0 / ((double)N * c), K));
@@ -1327,10 +1389,10 @@ extern "C" ssm_status ssm_surrogate_samples(ssm_ctx* c, int32_t sys, int64_t n, 
     const int64_t np = c->pair_cnt[0], nb = c->blk_cnt[0];
     const int d = c->d;
     if (c->prec == SSM_FP64) {
-        launch_pair<double>(d, c->R, false, dim3((unsigned)((np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const double*)c->Ys, c->P, c->Bp, c->Bpj);
+        launch_pair<double>(d, c->R, false, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const double*)c->Ys, c->P, c->Bp, c->Bpj);
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<double, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const double*)c->Y, c->rff, c->rff_part));
     } else {
-        launch_pair<float>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)((np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const float*)c->Ys, c->P, c->Bp, c->Bpj);
+        launch_pair<float>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const float*)c->Ys, c->P, c->Bp, c->Bpj, c->sym);
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<float, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const float*)c->Y, c->rff, c->rff_part));
     }
     HIP_TRY(hipGetLastError());

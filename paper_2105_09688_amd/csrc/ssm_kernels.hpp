@@ -23,6 +23,7 @@ constexpr int kBlk = 256;      // particles per update block (and system alignme
 constexpr int kWaves = 4;      // wavefronts per pair block
 constexpr int kUnroll = 8;     // sources per inner-loop iteration
 constexpr int kKahanChunk = 128;  // sources summed plainly before a compensated add
+constexpr int kSymLDS = 2048;     // floats of LDS j-side buffer per wavefront (symmetric scheme)
 
 struct SysDev {
     int64_t off;        // first slot of the system in [P]
@@ -110,8 +111,9 @@ __device__ __forceinline__ double combine_splits(const double* __restrict__ Bp, 
 }
 
 // Pair sum of particle i of a system under the symmetric scheme: i-side
-// partials (diagonal block, then the off-diagonal source ranges of i's block)
-// and j-side partials from every earlier target block, in that fixed order.
+// partials (the group's diagonal item, then the later source ranges of i's
+// group) and j-side partials from every earlier group and from i's own group,
+// in that fixed order.
 template <int D>
 __device__ __forceinline__ double combine_sym(const SysDev& S, const double* __restrict__ Bp,
                                               const float* __restrict__ Bpj, int k, int64_t P, int i)
@@ -121,15 +123,16 @@ __device__ __forceinline__ double combine_sym(const SysDev& S, const double* __r
     const int ns = 1 + (rest > 0 ? (rest + S.sym_L - 1) / S.sym_L : 0);
     const int64_t slot = S.off + i;
     double acc = combine_splits<D>(Bp, ns, k, P, slot);
+    const int rows = a + 1;
     int q0 = 0;
-    for (; q0 + 8 <= a; q0 += 8) {
+    for (; q0 + 8 <= rows; q0 += 8) {
         float v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) v[u] = Bpj[((int64_t)(q0 + u) * D + k) * P + slot];
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc += (double)v[u];
     }
-    for (; q0 < a; ++q0) acc += (double)Bpj[((int64_t)q0 * D + k) * P + slot];
+    for (; q0 < rows; ++q0) acc += (double)Bpj[((int64_t)q0 * D + k) * P + slot];
     return acc;
 }
 
@@ -521,7 +524,7 @@ __device__ __forceinline__ void pair_block(const T* __restrict__ src, int64_t P,
 // (p + k) % 16 with DPP row_ror:(16 - k), so no source moves; its q's go to
 // the i-side accumulators and to a per-step j-side accumulator, and after the
 // 16 steps the per-step accumulators are sent to their owners with
-// row_ror:k, summed over the rows and written as the chunk's j-side partial.
+// row_ror:k and summed over the rows.
 // Out-of-range targets and sources sit at +-1e15: their terms are exactly 0.
 // ---------------------------------------------------------------------------
 template <int N>
@@ -530,7 +533,7 @@ __device__ __forceinline__ float dpp_ror(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + N, 0xF, 0xF, false));
 }
 
-template <int D, int R, int K>
+template <int D, int R, int K, bool JSIDE>
 __device__ __forceinline__ void sym_step(const float (&s)[D], const float (&yi)[R][D], float (&acc)[R][D],
                                          float (&accj)[16][D])
 {
@@ -550,7 +553,7 @@ __device__ __forceinline__ void sym_step(const float (&s)[D], const float (&yi)[
 #pragma unroll
         for (int c = 0; c < D; ++c) {
             acc[r][c] = fmaf(z[c], e, acc[r][c]);
-            accj[K][c] = fmaf(z[c], e, accj[K][c]);
+            if constexpr (JSIDE) accj[K][c] = fmaf(z[c], e, accj[K][c]);
         }
     }
 }
@@ -562,10 +565,13 @@ __device__ __forceinline__ void sym_route(const float (&accj)[16][D], float (&to
     for (int c = 0; c < D; ++c) tot[c] += dpp_ror<K>(accj[K][c]);
 }
 
-template <int D, int R>
+// The chunk's j-side sums (before the sign flip) go to out[c * (kSymLDS / D) + j + jshift]
+// for the chunk's valid sources j when write_j holds.  JSIDE = false drops
+// the j-side arithmetic at compile time.
+template <int D, int R, bool JSIDE = true>
 __device__ __forceinline__ void sym_chunk(const float* __restrict__ base, int64_t P, int c0, int c_end,
-                                          const float (&yi)[R][D], float (&acc)[R][D], float* __restrict__ Bpj_row,
-                                          int64_t jslot0)
+                                          const float (&yi)[R][D], float (&acc)[R][D], float* __restrict__ out,
+                                          int64_t jshift, bool write_j = true)
 {
     const int lane = threadIdx.x & 63;
     const int p = lane & 15;
@@ -579,22 +585,23 @@ __device__ __forceinline__ void sym_chunk(const float* __restrict__ base, int64_
     for (int k = 0; k < 16; ++k)
 #pragma unroll
         for (int c = 0; c < D; ++c) accj[k][c] = 0.0f;
-    sym_step<D, R, 0>(s, yi, acc, accj);
-    sym_step<D, R, 1>(s, yi, acc, accj);
-    sym_step<D, R, 2>(s, yi, acc, accj);
-    sym_step<D, R, 3>(s, yi, acc, accj);
-    sym_step<D, R, 4>(s, yi, acc, accj);
-    sym_step<D, R, 5>(s, yi, acc, accj);
-    sym_step<D, R, 6>(s, yi, acc, accj);
-    sym_step<D, R, 7>(s, yi, acc, accj);
-    sym_step<D, R, 8>(s, yi, acc, accj);
-    sym_step<D, R, 9>(s, yi, acc, accj);
-    sym_step<D, R, 10>(s, yi, acc, accj);
-    sym_step<D, R, 11>(s, yi, acc, accj);
-    sym_step<D, R, 12>(s, yi, acc, accj);
-    sym_step<D, R, 13>(s, yi, acc, accj);
-    sym_step<D, R, 14>(s, yi, acc, accj);
-    sym_step<D, R, 15>(s, yi, acc, accj);
+    sym_step<D, R, 0, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 1, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 2, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 3, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 4, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 5, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 6, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 7, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 8, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 9, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 10, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 11, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 12, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 13, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 14, JSIDE>(s, yi, acc, accj);
+    sym_step<D, R, 15, JSIDE>(s, yi, acc, accj);
+    if constexpr (!JSIDE) return;
     float tot[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) tot[c] = accj[0][c];
@@ -618,60 +625,132 @@ __device__ __forceinline__ void sym_chunk(const float* __restrict__ base, int64_
         tot[c] += __shfl_xor(tot[c], 16, 64);
         tot[c] += __shfl_xor(tot[c], 32, 64);
     }
-    if (lane < 16 && vj) {
+    if (write_j && lane < 16 && vj) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) Bpj_row[c * P + jslot0 + j] = -tot[c];
+        for (int c = 0; c < D; ++c) out[c * (kSymLDS / D) + j + jshift] = tot[c];
     }
 }
 
+// One workgroup of kWaves wavefronts per symmetric work item.  The item
+// covers a target group of kWaves blocks of 64 R particles (wavefront w takes
+// block w) and either
+//  - the group itself (jrow < 0, "diagonal"): wavefront w takes the ordered
+//    pairs of its own block (i-side only) and the unordered pairs with the
+//    later blocks of the group; i-side partial 0, and
+//    the j-side sums of the group's particles form row a of the j-side
+//    partials (zero for block 0); or
+//  - a later source range (jrow = a): unordered pairs with every block of
+//    the group; i-side partial `split`, j-side row a.
+// j-side sums pass through LDS (kSymLDS / d sources at a time) and are added
+// over the wavefronts in a fixed order before they are written.
 template <int D, int R, bool KAHAN>
-__device__ __forceinline__ void pair_item_sym(const PairItem& it, const SysDev& S, const float* __restrict__ base,
-                                              int64_t P, double* __restrict__ Bp, float* __restrict__ Bpj)
+__device__ __forceinline__ void kahan_fold(float (&acc)[R][D], float (&hi)[R][D], float (&lo)[R][D])
 {
-    const int lane = threadIdx.x & 63;
-    float yi[R][D];
-    bool valid[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = it.tgt0 + lane + 64 * r;
-        valid[r] = i < S.N;
-#pragma unroll
-        for (int c = 0; c < D; ++c) yi[r][c] = valid[r] ? base[c * P + i] : -1e15f;
-    }
-    float acc[R][D], hi[R][D], lo[R][D];
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int c = 0; c < D; ++c) {
+            const float a = acc[r][c];
+            const float sm = hi[r][c] + a;
+            lo[r][c] += (fabsf(hi[r][c]) >= fabsf(a)) ? (hi[r][c] - sm) + a : (a - sm) + hi[r][c];
+            hi[r][c] = sm;
             acc[r][c] = 0.0f;
-            hi[r][c] = 0.0f;
-            lo[r][c] = 0.0f;
         }
-    float* Bpj_row = Bpj + (int64_t)it.jrow * D * P;
-    const int c_end = it.src0 + it.nsrc;
+}
+
+// Sum the wavefronts' LDS j-side sums for sources [j0, j0 + n) (LDS index
+// j - lds0) and store them, negated, in row `row` of the j-side partials.
+template <int D>
+__device__ __forceinline__ void jside_flush(float (*jred)[kSymLDS], float* __restrict__ Bpj, int64_t row,
+                                            int64_t P, int64_t off, int j0, int n, int lds0)
+{
+    constexpr int stride = kSymLDS / D;
+    float* Bpj_row = Bpj + row * D * P;
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+        for (int jj = threadIdx.x; jj < n; jj += 64 * kWaves) {
+            const int li = c * stride + (j0 + jj - lds0);
+            float v = jred[0][li];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) v += jred[w][li];
+            Bpj_row[c * P + off + j0 + jj] = -v;
+        }
+}
+
+template <int D, int R, bool KAHAN>
+__global__ __launch_bounds__(64 * kWaves) void k_pair_sym(const PairItem* __restrict__ items,
+                                                          const SysDev* __restrict__ sys,
+                                                          const float* __restrict__ Ys, int64_t P,
+                                                          double* __restrict__ Bp, float* __restrict__ Bpj)
+{
+    constexpr int stride = kSymLDS / D;  // LDS j-side capacity (sources) per component
+    __shared__ float jred[kWaves][kSymLDS];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const PairItem it = items[blockIdx.x];
+    const SysDev S = sys[it.sys];
+    const float* __restrict__ base = Ys + S.off;
+    const int blk = 64 * R;
+    const int tb0 = it.tgt0 + wave * blk;  // this wavefront's target block
+
+    float yi[R][D], acc[R][D], hi[R][D], lo[R][D];
+    bool valid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = tb0 + lane + 64 * r;
+        valid[r] = i < S.N;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            yi[r][c] = valid[r] ? base[c * P + i] : -1e15f;
+            acc[r][c] = hi[r][c] = lo[r][c] = 0.0f;
+        }
+    }
+
+    // One loop for both kinds of item (a single inlined copy of the chunk
+    // routine keeps the register count down):
+    //  - group itself: wavefront w sweeps [own block start, group end); the
+    //    chunks of its own block skip the j-side store (a block against
+    //    itself gives each target its full ordered sum; its j-side would
+    //    count the pairs twice); one j-side flush at the end;
+    //  - later range: all wavefronts sweep the range, flushing the j-side
+    //    every `stride` sources (uniform trip counts around the barriers).
+    const bool diag = it.jrow < 0;
+    const int g_end = it.tgt0 + it.nsrc;
+    const int own_end = min(tb0 + blk, g_end);
+    const int start = diag ? tb0 : it.src0;
+    const int end = diag ? g_end : it.src0 + it.nsrc;
+    const int piece = diag ? kSymLDS : stride;  // group x d <= kSymLDS: one piece
+    if (diag) {
+        for (int q = lane; q < kSymLDS; q += 64) jred[wave][q] = 0.0f;
+    }
     int chunks = 0;
-    for (int c0 = it.src0; c0 < c_end; c0 += 16) {
-        sym_chunk<D, R>(base, P, c0, c_end, yi, acc, Bpj_row, S.off);
-        if constexpr (KAHAN) {
-            if (++chunks == kKahanChunk / 16 || c0 + 16 >= c_end) {
-                chunks = 0;
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                    for (int c = 0; c < D; ++c) {
-                        const float a = acc[r][c];
-                        const float sm = hi[r][c] + a;
-                        const float err = (fabsf(hi[r][c]) >= fabsf(a)) ? (hi[r][c] - sm) + a : (a - sm) + hi[r][c];
-                        lo[r][c] += err;
-                        hi[r][c] = sm;
-                        acc[r][c] = 0.0f;
-                    }
+    for (int u0 = start; u0 < end; u0 += piece) {
+        const int u1 = min(u0 + piece, end);
+        const int64_t jshift = diag ? -(int64_t)it.tgt0 : -(int64_t)u0;
+        for (int c0 = u0; c0 < u1; c0 += 16) {
+            const int ce = (diag && c0 < own_end) ? own_end : u1;
+            sym_chunk<D, R>(base, P, c0, ce, yi, acc, &jred[wave][0], jshift, !(diag && c0 < own_end));
+            if constexpr (KAHAN) {
+                if (++chunks == kKahanChunk / 16) {
+                    chunks = 0;
+                    kahan_fold<D, R, KAHAN>(acc, hi, lo);
+                }
             }
         }
+        if (!diag) {
+            __syncthreads();
+            jside_flush<D>(jred, Bpj, (int64_t)it.jrow, P, S.off, u0, u1 - u0, u0);
+            if (u1 < end) __syncthreads();  // the next piece reuses the LDS
+        }
+    }
+    if constexpr (KAHAN) kahan_fold<D, R, KAHAN>(acc, hi, lo);
+    if (diag) {
+        __syncthreads();
+        jside_flush<D>(jred, Bpj, (int64_t)(it.tgt0 / (blk * kWaves)), P, S.off, it.tgt0, it.nsrc, it.tgt0);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int i = it.tgt0 + lane + 64 * r;
+        const int i = tb0 + lane + 64 * r;
         if (!valid[r]) continue;
 #pragma unroll
         for (int c = 0; c < D; ++c) {
@@ -686,7 +765,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair(const PairItem* __restrict
                                                       int n_items,
                                                       const SysDev* __restrict__ sys,
                                                       const T* __restrict__ Ys, int64_t P,
-                                                      double* __restrict__ Bp, float* __restrict__ Bpj)
+                                                      double* __restrict__ Bp)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -695,12 +774,6 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair(const PairItem* __restrict
     const PairItem it = items[idx];
     const SysDev S = sys[it.sys];
     const T* __restrict__ base = Ys + S.off;
-    if constexpr (sizeof(T) == sizeof(float)) {
-        if (it.jrow >= 0) {
-            pair_item_sym<D, R, KAHAN>(it, S, (const float*)base, P, Bp, Bpj);
-            return;
-        }
-    }
 
     T yi[R][D];
     bool valid[R];

@@ -32,7 +32,9 @@ def candidates(d: int, precision: str):
     schemes = ["ordered"] if precision == "fp64" else ["symmetric", "ordered"]
     out = []
     for scheme in schemes:
-        for R in ((2, 4) if d == 1 else (1, 2, 4)):
+        # symmetric: a target group (4 x 64 R particles) times d must fit 2048 LDS floats
+        Rs = {1: (2, 4, 8), 2: (1, 2, 4)}.get(d, (1, 2)) if scheme == "symmetric" else ((2, 4) if d == 1 else (1, 2))
+        for R in Rs:
             for Lmul in (0.5, 1.0, 2.0):
                 out.append({"pair_scheme": scheme, "targets_per_lane": R, "L_factor": Lmul})
     return out
