@@ -242,17 +242,17 @@ def study_surrogate(args, stream):
     ex.close()
     print(f"[surrogate] exact run {dt_ex:.1f} s", file=sys.stderr, flush=True)
     runs = {}
-    for tol in (1e-3, 1e-2, 1e9):
-        def setup(s, tol=tol):
+    for mode, tol in (("gain", 1e-3), ("gain", 1e-2), ("gain", 1e9), ("residual", 1e-3), ("residual", 1e9)):
+        def setup(s, tol=tol, mode=mode):
             s.surrogate_load(master)
-            s.surrogate_enable(check_every=every, tol=tol)
+            s.surrogate_enable(check_every=every, tol=tol, mode=mode)
         su, dt_su, _ = timed_run(SSM, w, prec, stream, setup=setup)
         info = su.info()
         X = su.state(0)
         m, v = su.moments(0)
         su.close()
         D = X - X_ex
-        runs[f"tol={tol:g}"] = {
+        runs[f"{mode} tol={tol:g}"] = {
             "seconds": dt_su, "particle_steps_per_s": N * n / dt_su, "speedup_vs_exact": dt_ex / dt_su,
             "checks": info["surr_checks"], "surrogate_ticks": info["surr_ticks"],
             "fallback_ticks": info["surr_fallback_ticks"], "check_rel_err_last": info["surr_last_err"],
@@ -261,8 +261,8 @@ def study_surrogate(args, stream):
             "pathwise_rms_vs_exact": float(np.sqrt(np.sum(D * D) / N)),
             "mean_diff": [float(x) for x in m - m_ex], "var_diff": [float(x) for x in v - v_ex],
         }
-        print(f"[surrogate] tol {tol:g}: {dt_su:.2f} s, {info['surr_ticks']} surrogate ticks, "
-              f"max err {info['surr_max_err']:.3e}", file=sys.stderr, flush=True)
+        print(f"[surrogate] {mode} tol {tol:g}: {dt_su:.2f} s, {info['surr_ticks']} surrogate ticks, "
+              f"last err {info['surr_last_err']:.3e}, max err {info['surr_max_err']:.3e}", file=sys.stderr, flush=True)
     # strong error at fixed h against a 2^-13 proxy solution on the same paths,
     # at N = min(N, 2^18), the size the network was trained at (the proxy run
     # takes 8192 exact steps)
@@ -272,16 +272,21 @@ def study_surrogate(args, stream):
     ref = SSM(W.with_h(wr, 2.0 ** -13), precision=prec, stream=stream)
     ref.run()
     rm = {}
-    for label, tol in (("exact", None), ("surrogate tol=1e-2", 1e-2), ("surrogate always", 1e9)):
+    variants = (("exact", None, None), ("gain tol=1e-2", "gain", 1e-2), ("gain always", "gain", 1e9),
+                ("residual tol=1e-3", "residual", 1e-3), ("residual always", "residual", 1e9))
+    for label, mode, tol in variants:
         with SSM(wr, precision=prec, stream=stream) as a:
             if tol is not None:
                 a.surrogate_load(master)
-                a.surrogate_enable(check_every=every, tol=tol)
+                a.surrogate_enable(check_every=every, tol=tol, mode=mode)
             a.run()
             rm[label] = math.sqrt(a.sqdiff(0, ref, 0) / Nr)
+            if tol is not None:
+                i = a.info()
+                rm[label + " surrogate ticks"] = i["surr_ticks"]
     ref.close()
-    rm["ratio tol=1e-2 / exact"] = rm["surrogate tol=1e-2"] / rm["exact"]
-    rm["ratio always / exact"] = rm["surrogate always"] / rm["exact"]
+    for label, _m, tol in variants[1:]:
+        rm[f"ratio {label} / exact"] = rm[label] / rm["exact"]
     pair_avg = info_ex["pair_ms"] / 1e3 / max(1, info_ex["pair_launches"])
     return {"study": "surrogate", f"rmse_vs_2^-13_at_N={Nr}": rm, "workload": f"d=2 N={N} T=1 h=2^-9, exact check every {every} steps, {prec}",
             "training": {"pairs": int(U.shape[0]), "from": f"{n_runs} exact runs of other ensembles at N={N_train}",

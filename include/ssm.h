@@ -139,9 +139,9 @@ typedef struct {
     int64_t surr_checks;         /* check ticks: exact pair term computed and compared */
     int64_t surr_ticks;          /* ticks whose update used the surrogate */
     int64_t surr_fallback_ticks; /* non-check ticks that used the exact term after a failed check */
-    double surr_last_err;        /* relative error of the last check (with the fitted gain) */
+    double surr_last_err;        /* relative error of the last check's prediction (see ssm_surrogate_enable) */
     double surr_max_err;         /* largest such error seen */
-    double surr_last_raw_err;    /* relative error of the last check without the gain */
+    double surr_last_raw_err;    /* relative error of the last check's bare network output s - mean s */
     double surr_gain[SSM_MAX_D]; /* per-component gain fitted at the last check */
 } ssm_info_t;
 
@@ -285,19 +285,33 @@ int64_t ssm_mlp_num_params(int32_t d);
  * with a pairwise term.  Synchronizes. */
 ssm_status ssm_surrogate_load(ssm_ctx *ctx, const float *master, int64_t n);
 
+/* Prediction modes of ssm_surrogate_enable. */
+#define SSM_SURR_GAIN 0     /* g_k (s_k - mean s_k) */
+#define SSM_SURR_RESIDUAL 1 /* (s_k - mean s_k) + r_k, r from the last check */
+
 /* Use the loaded surrogate in place of the O(N^2) pairwise sums.  Every
- * check_every-th tick (tick % check_every == 0) the exact sums are computed
+ * check_every-th tick (tick % check_every == 0) the exact sums p are computed
  * as well, the update uses them, and the relative error
- * sqrt(sum_i |s_i - p_i|^2 / sum_i |p_i|^2) over the stepping systems decides
- * whether the following ticks use the surrogate (error <= tol) or the exact
- * sums (until the next check).  The surrogate enters the update as
- * g_k (s_k - mean(s_k)): its mean over the system is removed (the exact term
- * has zero net force) and g_k = sum p_k s_k / sum s_k^2 is the least-squares
- * gain fitted at the last check (1 before the first).  The error compared
- * with tol is that of g (s - mean s) against the exact term p.  Check ticks
- * synchronize the stream.
- * check_every = 0 turns the surrogate off. */
-ssm_status ssm_surrogate_enable(ssm_ctx *ctx, int32_t check_every, double tol);
+ * sqrt(sum_i |q_i - p_i|^2 / sum_i |p_i|^2) of the prediction q over the
+ * stepping systems decides whether the following ticks use the prediction
+ * (error <= tol) or the exact sums (until the next check).  The network
+ * output s enters with its mean over the system removed (the exact term has
+ * zero net force), and
+ *  - mode SSM_SURR_GAIN: q_k = g_k (s_k - mean s_k), where
+ *    g_k = sum p_k s_k / sum s_k^2 is the least-squares gain fitted at the
+ *    last check (1 before the first); the error compared with tol is that of
+ *    the gain fitted at this check;
+ *  - mode SSM_SURR_RESIDUAL: q_k^i = (s_k^i - mean s_k) + r_k^i, where
+ *    r^i = p^i - (s^i - mean s) is particle i's residual stored at the last
+ *    check (one float per particle and component); the error compared with
+ *    tol is that of the residual carried over from the previous check, so it
+ *    measures how far the network's error moved in check_every ticks.  The
+ *    first check has no earlier residual and is compared without one.  Every
+ *    system must step on check ticks: check_every a multiple of the ratio of
+ *    the largest to the smallest step of the context.
+ * Check ticks synchronize the stream.  check_every = 0 turns the surrogate
+ * off.  Enabling (again) forgets the gain and the residuals. */
+ssm_status ssm_surrogate_enable(ssm_ctx *ctx, int32_t check_every, double tol, int32_t mode);
 
 /* Training pairs from the current state of system sys: n draws (with
  * replacement, Philox stream tag 4 under seed) of a particle i, writing its

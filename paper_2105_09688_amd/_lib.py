@@ -96,7 +96,7 @@ def load():
         "ssm_philox_blocks": (st, [u64, u64, u64, u64, u64, u64, i64, vp, vp]),
         "ssm_mlp_num_params": (i64, [i32]),
         "ssm_surrogate_load": (st, [vp, vp, i64]),
-        "ssm_surrogate_enable": (st, [vp, i32, C.c_double]),
+        "ssm_surrogate_enable": (st, [vp, i32, C.c_double, i32]),
         "ssm_surrogate_samples": (st, [vp, i32, i64, u64, vp, vp]),
         "ssm_mlp_forward": (st, [i32, vp, vp, i64, vp, vp]),
         "ssm_mlp_loss_grad": (st, [i32, vp, vp, vp, i64, vp, dp, vp]),

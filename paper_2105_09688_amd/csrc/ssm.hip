@@ -225,6 +225,9 @@ struct ssm_ctx {
     int64_t surr_checks = 0, surr_fallback_ticks = 0, surr_ticks = 0;
     double surr_last_err = 0.0, surr_max_err = 0.0, surr_last_raw_err = 0.0;
     double surr_gain[kMaxD] = {1.0, 1.0, 1.0, 1.0};
+    int32_t surr_mode = SSM_SURR_GAIN;
+    bool surr_res_valid = false;   // residuals stored by a check since enabling
+    float* surr_res = nullptr;     // [d][P] residual p - (s - mean s) of the last check
     MlpPacked* dmlp = nullptr;
     float* surr = nullptr;         // [d][P] surrogate pair term
     double* rff_part = nullptr;    // [nblk_tot][2K]
@@ -500,8 +503,10 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
     }
     if (check && nb > 0) {
         const BlkItem* items = c->dblk + c->blk_off[ph];
+        const bool resid = c->surr_mode == SSM_SURR_RESIDUAL;
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_surr_err<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, items,
-                                             c->dsys, c->P, c->Bp, c->Bpj, c->surr, c->smean, c->err_part));
+                                             c->dsys, c->P, c->Bp, c->Bpj, c->surr, c->smean, c->surr_res,
+                                             (resid && c->surr_res_valid) ? 1 : 0, resid ? 1 : 0, c->err_part));
         HIP_TRY(hipGetLastError());
     }
     const int use_surr = (run_surr && !check) ? 1 : 0;
@@ -529,7 +534,10 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
                                              items, c->dsys, c->coef, c->P, c->tick, tdev, X, Y, Ys, c->Bp, c->surr,
                                              c->smean, use_surr,
                                              make_float4((float)c->surr_gain[0], (float)c->surr_gain[1],
-                                                         (float)c->surr_gain[2], (float)c->surr_gain[3]), c->dW, c->Bpj,
+                                                         (float)c->surr_gain[2], (float)c->surr_gain[3]),
+                                             (use_surr && c->surr_mode == SSM_SURR_RESIDUAL && c->surr_res_valid)
+                                                 ? c->surr_res : nullptr,
+                                             c->dW, c->Bpj,
                                              c->psumX, c->psumY, c->nblk_tot, c->dflags));
         HIP_TRY(hipGetLastError());
         if (!c->fused) {
@@ -552,32 +560,40 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
         if (!check && c->surr_fallback) c->surr_fallback_ticks++;
     }
     if (check && nb > 0) {
-        // Least-squares gain per component from the check's exact and surrogate
-        // terms, then the relative error of the gained surrogate over the
-        // stepping systems; it decides whether the ticks until the next check
-        // use the surrogate (with that gain) or the exact sums.
+        // Gain mode: least-squares gain per component from the check's exact
+        // and surrogate terms, then the relative error of the gained surrogate.
+        // Residual mode: the error of the prediction with the residuals of the
+        // previous check (the kernel has stored this check's residuals).
+        // Over the stepping systems, the error decides whether the ticks until
+        // the next check use the prediction or the exact sums.
         std::vector<double> h(kErrStats * nb);
         HIP_TRY(hipMemcpyAsync(h.data(), c->err_part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
-        double se = 0.0, sb = 0.0, sps[kMaxD] = {0, 0, 0, 0}, sss[kMaxD] = {0, 0, 0, 0};
+        double se = 0.0, sb = 0.0, sr = 0.0, sps[kMaxD] = {0, 0, 0, 0}, sss[kMaxD] = {0, 0, 0, 0};
         for (int64_t q = 0; q < nb; ++q) {
             const double* r = &h[kErrStats * q];
             se += r[0];
             sb += r[1];
+            sr += r[2 + 2 * kMaxD];
             for (int k = 0; k < d; ++k) {
                 sps[k] += r[2 + 2 * k];
                 sss[k] += r[3 + 2 * k];
             }
         }
-        double se_g = sb;  // |g s - p|^2 = g^2 |s|^2 - 2 g s.p + |p|^2, per component
-        for (int k = 0; k < d; ++k) {
-            const double g = sss[k] > 0.0 ? sps[k] / sss[k] : 1.0;
-            c->surr_gain[k] = g;
-            se_g += g * g * sss[k] - 2.0 * g * sps[k];
+        double se_q = se;
+        if (c->surr_mode == SSM_SURR_GAIN) {
+            se_q = sb;  // |g s - p|^2 = g^2 |s|^2 - 2 g s.p + |p|^2, per component
+            for (int k = 0; k < d; ++k) {
+                const double g = sss[k] > 0.0 ? sps[k] / sss[k] : 1.0;
+                c->surr_gain[k] = g;
+                se_q += g * g * sss[k] - 2.0 * g * sps[k];
+            }
+            se_q = std::max(se_q, 0.0);
+        } else {
+            c->surr_res_valid = true;
         }
-        se_g = std::max(se_g, 0.0);
-        const double err = sb > 0.0 ? std::sqrt(se_g / sb) : (se_g > 0.0 ? INFINITY : 0.0);
-        c->surr_last_raw_err = sb > 0.0 ? std::sqrt(se / sb) : 0.0;
+        const double err = sb > 0.0 ? std::sqrt(se_q / sb) : (se_q > 0.0 ? INFINITY : 0.0);
+        c->surr_last_raw_err = sb > 0.0 ? std::sqrt(sr / sb) : 0.0;
         c->surr_last_err = err;
         c->surr_max_err = std::max(c->surr_max_err, err);
         c->surr_checks++;
@@ -1022,6 +1038,7 @@ extern "C" ssm_status ssm_set_state(ssm_ctx* c, int32_t sys, const double* host)
     if (!c || !host) return fail(SSM_ERR_INVALID, "NULL argument");
     if (sys < 0 || sys >= (int32_t)c->sys.size()) return fail(SSM_ERR_INVALID, "sys out of range");
     if (!c->fused) return fail(SSM_ERR_STATE, "set_state needs v independent of mu^X");
+    c->surr_res_valid = false;  // the stored residuals belong to the old state
     const SysHost& S = c->sys[sys];
     HIP_TRY(hipMemcpyAsync(c->dstage, host, (size_t)c->d * S.N * sizeof(double), hipMemcpyHostToDevice, c->stream));
     const unsigned g = (unsigned)((S.N + kBlk - 1) / kBlk);
@@ -1321,6 +1338,7 @@ static ssm_status ensure_surrogate_buffers(ssm_ctx* c)
 #define ALLOC2(ptr, bytes) do { st = dev_alloc(c, (void**)&(ptr), (bytes)); if (st != SSM_OK) return st; } while (0)
     ALLOC2(c->dmlp, sizeof(MlpPacked));
     ALLOC2(c->surr, (size_t)c->d * c->P * sizeof(float));
+    ALLOC2(c->surr_res, (size_t)c->d * c->P * sizeof(float));
     ALLOC2(c->rff_part, (size_t)c->nblk_tot * 2 * kRff * sizeof(double));
     ALLOC2(c->mom, c->sys.size() * 2 * kRff * sizeof(float));
     ALLOC2(c->err_part, (size_t)c->nblk_tot * kErrStats * sizeof(double));
@@ -1366,14 +1384,20 @@ extern "C" ssm_status ssm_surrogate_load(ssm_ctx* c, const float* master_host, i
     return SSM_OK;
 }
 
-extern "C" ssm_status ssm_surrogate_enable(ssm_ctx* c, int32_t check_every, double tol)
+extern "C" ssm_status ssm_surrogate_enable(ssm_ctx* c, int32_t check_every, double tol, int32_t mode)
 {
     if (!c) return fail(SSM_ERR_INVALID, "ctx is NULL");
     if (check_every < 0 || !(tol > 0.0)) return fail(SSM_ERR_INVALID, "check_every >= 0 and tol > 0 required");
+    if (mode != SSM_SURR_GAIN && mode != SSM_SURR_RESIDUAL) return fail(SSM_ERR_INVALID, "unknown surrogate mode");
     if (check_every > 0 && !c->surr_loaded) return fail(SSM_ERR_STATE, "load surrogate weights first");
+    if (check_every > 0 && mode == SSM_SURR_RESIDUAL && check_every % c->max_stride != 0)
+        return fail(SSM_ERR_INVALID, "residual mode: check_every must be a multiple of " +
+                                         std::to_string(c->max_stride) + " (every system steps on check ticks)");
     c->surr_check_every = check_every;
     c->surr_tol = tol;
+    c->surr_mode = mode;
     c->surr_fallback = false;
+    c->surr_res_valid = false;
     for (int k = 0; k < kMaxD; ++k) c->surr_gain[k] = 1.0;
     return SSM_OK;
 }

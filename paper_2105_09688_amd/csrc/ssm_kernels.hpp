@@ -323,7 +323,8 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
                                                  const double* __restrict__ Bp,
                                                  const float* __restrict__ surr,
                                                  const float* __restrict__ surr_mean, int use_surr,
-                                                 float4 surr_gain, const double* __restrict__ dWbuf,
+                                                 float4 surr_gain, const float* __restrict__ surr_res,
+                                                 const double* __restrict__ dWbuf,
                                                  const float* __restrict__ Bpj,
                                                  double* __restrict__ psumX,
                                                  double* __restrict__ psumY, int64_t nblk_tot,
@@ -350,10 +351,12 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
             const double y = (double)Y[k * P + slot];
             double pair = 0.0;
             if (use_surr) {
-                // learned surrogate of the pair term, projected to zero net force and
-                // scaled by the gain fitted at the last check
+                // learned surrogate of the pair term, projected to zero net force,
+                // scaled by the gain fitted at the last check and (residual mode)
+                // corrected by the particle's residual stored at the last check
                 const float gk = k == 0 ? surr_gain.x : k == 1 ? surr_gain.y : k == 2 ? surr_gain.z : surr_gain.w;
                 pair = (double)gk * ((double)surr[k * P + slot] - (double)surr_mean[(int64_t)it.sys * kMaxD + k]);
+                if (surr_res) pair += (double)surr_res[k * P + slot];
             } else if (cf.has_pair) {
                 pair = pair_partials<D>(S, Bp, Bpj, k, P, i) * S.pair_scale;
             }

@@ -178,31 +178,9 @@ __device__ __forceinline__ void d_to_a(const f32x4 v[NT], __bf16* tile, bf16x8 a
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Input features of one sample in A layout: lane (l) holds features
-// k = 32 ks + 8 (l / 16) + 0..7 of sample l % 16:  u = [hi(y), lo(y), m_0..m_{2K-1}, 0...].
-// y: the sample's coordinates (y0..y3), mom: moments in LDS.
-__device__ __forceinline__ void build_input(float y0, float y1, float y2, float y3, const float* mom, int d,
-                                            bf16x8 a[2])
-{
-    const int l = threadIdx.x & 63;
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int k = ks * 32 + 8 * (l >> 4) + i;
-            __bf16 v = (__bf16)0.0f;
-            if (k < 2 * d) {
-                const int c = k < d ? k : k - d;
-                const float yc = (c == 0) ? y0 : (c == 1) ? y1 : (c == 2) ? y2 : y3;
-                v = k < d ? bf_hi(yc) : bf_lo(yc);
-            } else if (k < 2 * d + 2 * kRff) {
-                v = (__bf16)mom[k - 2 * d];
-            }
-            a[ks][i] = v;
-        }
-}
-
-// Same, from a raw row r = [y (d), m (2K)] in global memory (r may be null: zeros).
+// Input features of one sample in A layout (training): lane l holds features
+// k = 32 ks + 8 (l / 16) + 0..7 of sample l % 16:  u = [hi(y), lo(y), m_0..m_{2K-1}, 0...],
+// from a raw row r = [y (d), m (2K)] in global memory (r may be null: zeros).
 __device__ __forceinline__ void build_input_row(const float* r, int d, bf16x8 a[2])
 {
     const int l = threadIdx.x & 63;
@@ -219,6 +197,113 @@ __device__ __forceinline__ void build_input_row(const float* r, int d, bf16x8 a[
             }
             a[ks][i] = v;
         }
+}
+
+// Split-precision activations for inference: every A operand is carried as
+// hi + lo with hi = bf16(v) and lo = bf16(v - hi) (about 16 significant bits),
+// and each product W x runs as W hi + W lo (two MFMAs per K slice).  The
+// weights stay BF16 (the network is trained with them), so the network stays
+// a smooth function of its inputs; plain BF16 activations add rounding noise
+// of order 1e-3 relative that changes from one step to the next.
+template <int NT>
+__device__ __forceinline__ void dense_tiles_split(const __bf16* W, const bf16x8 ah[2], const bf16x8 al[2],
+                                                  f32x4 acc[NT])
+{
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const bf16x8 b = *(const bf16x8*)&W[(nt * 16 + (l & 15)) * kStride + ks * 32 + 8 * (l >> 4)];
+            c = mfma_bf16(al[ks], b, c);
+            c = mfma_bf16(ah[ks], b, c);
+        }
+        acc[nt] = c;
+    }
+}
+
+// d_to_a for split activations: two LDS tiles [16][kStride] (hi, lo).
+template <int NT>
+__device__ __forceinline__ void d_to_a_split(const f32x4 v[NT], __bf16* th, __bf16* tl, bf16x8 ah[2],
+                                             bf16x8 al[2])
+{
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = (4 * (l >> 4) + i) * kStride + nt * 16 + (l & 15);
+            th[q] = bf_hi(v[nt][i]);
+            tl[q] = bf_lo(v[nt][i]);
+        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        ah[ks] = *(const bf16x8*)&th[(l & 15) * kStride + ks * 32 + 8 * (l >> 4)];
+        al[ks] = *(const bf16x8*)&tl[(l & 15) * kStride + ks * 32 + 8 * (l >> 4)];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Input features u = [hi(y), lo(y), m] as hi + lo parts: the coordinate
+// features are BF16 values already (lo part 0); each moment m splits into
+// bf16(m) + bf16(m - bf16(m)).  y0..y3: coordinates; mom: the 2K moments
+// (null: an all-zero row).
+__device__ __forceinline__ void build_input_split(float y0, float y1, float y2, float y3, const float* mom, int d,
+                                                  bf16x8 ah[2], bf16x8 al[2])
+{
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = ks * 32 + 8 * (l >> 4) + i;
+            __bf16 vh = (__bf16)0.0f, vl = (__bf16)0.0f;
+            if (mom && k < 2 * d) {
+                const int c = k < d ? k : k - d;
+                const float yc = (c == 0) ? y0 : (c == 1) ? y1 : (c == 2) ? y2 : y3;
+                vh = k < d ? bf_hi(yc) : bf_lo(yc);
+            } else if (mom && k < 2 * d + 2 * kRff) {
+                const float m = mom[k - 2 * d];
+                vh = bf_hi(m);
+                vl = bf_lo(m);
+            }
+            ah[ks][i] = vh;
+            al[ks][i] = vl;
+        }
+}
+
+// Split-precision forward of the wavefront's 16 samples (inference only):
+// output tile in D layout, columns 0..d-1 valid, bias added.
+__device__ __forceinline__ void mlp_forward16_split(const __bf16* sW1, const __bf16* sW2, const __bf16* sW3,
+                                                    const __bf16* sW4, const float* sb, bf16x8 ah[2], bf16x8 al[2],
+                                                    __bf16* th, __bf16* tl, f32x4& out)
+{
+    const int l = threadIdx.x & 63;
+    const __bf16* Ws[3] = {sW1, sW2, sW3};
+#pragma unroll
+    for (int layer = 0; layer < 3; ++layer) {
+        f32x4 acc[4];
+        dense_tiles_split<4>(Ws[layer], ah, al, acc);
+        f32x4 hv[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const float bias = sb[layer * kHid + nt * 16 + (l & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) hv[nt][i] = silu_f(acc[nt][i] + bias);
+        }
+        d_to_a_split<4>(hv, th, tl, ah, al);
+    }
+    f32x4 o[1];
+    dense_tiles_split<1>(sW4, ah, al, o);
+    const float b4 = sb[3 * kHid + (l & 15)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[i] = o[0][i] + b4;
 }
 
 // Forward pass of the wavefront's 16 samples.  Returns the output tile
@@ -325,7 +410,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const BlkItem* __restrict__ i
     __shared__ __align__(16) __bf16 sW3[kHid * kStride];
     __shared__ __align__(16) __bf16 sW4[kOutPad * kStride];
     __shared__ float sb[3 * kHid + kOutPad];
-    __shared__ __align__(16) __bf16 tiles[4][16 * kStride];
+    __shared__ __align__(16) __bf16 tiles[4][2][16 * kStride];
     __shared__ float smom[2 * kRff];
     load_fwd_weights(W, sW1, sW2, sW3, sW4, sb);
     __syncthreads();
@@ -345,12 +430,10 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const BlkItem* __restrict__ i
             float y[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int k = 0; k < D; ++k) y[k] = (i < S.N) ? (float)Y[k * P + S.off + i] : 0.0f;
-            bf16x8 a[2];
-            build_input(y[0], y[1], y[2], y[3], smom, D, a);
-            f32x4 z[3][4];
-            bf16x8 act[3][2];
+            bf16x8 ah[2], al[2];
+            build_input_split(y[0], y[1], y[2], y[3], smom, D, ah, al);
             f32x4 out;
-            mlp_forward16(sW1, sW2, sW3, sW4, sb, a, tiles[wave], z, out, act);
+            mlp_forward16_split(sW1, sW2, sW3, sW4, sb, ah, al, tiles[wave][0], tiles[wave][1], out);
             // out: rows 4 (l/16) + r (samples), column l % 16 (output component)
             const int comp = l & 15;
             if (comp < D) {
@@ -373,7 +456,7 @@ __global__ __launch_bounds__(256) void k_mlp_apply(const float* __restrict__ U, 
     __shared__ __align__(16) __bf16 sW3[kHid * kStride];
     __shared__ __align__(16) __bf16 sW4[kOutPad * kStride];
     __shared__ float sb[3 * kHid + kOutPad];
-    __shared__ __align__(16) __bf16 tiles[4][16 * kStride];
+    __shared__ __align__(16) __bf16 tiles[4][2][16 * kStride];
     load_fwd_weights(W, sW1, sW2, sW3, sW4, sb);
     __syncthreads();
     const int wave = threadIdx.x >> 6;
@@ -381,12 +464,13 @@ __global__ __launch_bounds__(256) void k_mlp_apply(const float* __restrict__ U, 
     const int in = raw_in(d);
     for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 16; r0 < n; r0 += (int64_t)gridDim.x * 64) {
         const int64_t row = r0 + (l & 15);
-        bf16x8 a[2];
-        build_input_row(row < n ? U + row * in : nullptr, d, a);
-        f32x4 z[3][4];
-        bf16x8 act[3][2];
+        const float* r = row < n ? U + row * in : nullptr;
+        float yv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int k = 0; k < d && r; ++k) yv[k] = r[k];
+        bf16x8 ah[2], al[2];
+        build_input_split(yv[0], yv[1], yv[2], yv[3], r ? r + d : nullptr, d, ah, al);
         f32x4 o;
-        mlp_forward16(sW1, sW2, sW3, sW4, sb, a, tiles[wave], z, o, act);
+        mlp_forward16_split(sW1, sW2, sW3, sW4, sb, ah, al, tiles[wave][0], tiles[wave][1], o);
         const int comp = l & 15;
         if (comp < d) {
 #pragma unroll
@@ -674,10 +758,13 @@ __global__ void k_surr_final(const int32_t* __restrict__ sys_list, const SysDev*
 }
 
 // Check statistics per update block (fixed-order block sums), for the listed
-// blocks, with s = surrogate minus its system mean and p = exact pair term:
-//   [0] sum |s - p|^2, [1] sum |p|^2, then per component k:
-//   [2 + 2k] sum p_k s_k, [3 + 2k] sum s_k^2.
-constexpr int kErrStats = 2 + 2 * kMaxD;
+// blocks, with s = surrogate minus its system mean, p = exact pair term and
+// q = s + r the prediction (r = the stored residual when res_read, else 0):
+//   [0] sum |q - p|^2, [1] sum |p|^2, then per component k:
+//   [2 + 2k] sum p_k s_k, [3 + 2k] sum s_k^2, and [2 + 2 kMaxD] sum |s - p|^2.
+// With res_write the residuals p - s replace the stored ones (each thread
+// reads its own slots before it writes them).
+constexpr int kErrStats = 3 + 2 * kMaxD;
 
 template <typename T, int D>
 __global__ __launch_bounds__(kBlk) void k_surr_err(const BlkItem* __restrict__ items,
@@ -686,21 +773,24 @@ __global__ __launch_bounds__(kBlk) void k_surr_err(const BlkItem* __restrict__ i
                                                    const float* __restrict__ Bpj,
                                                    const float* __restrict__ surr,
                                                    const float* __restrict__ surr_mean,
+                                                   float* res, int res_read, int res_write,
                                                    double* __restrict__ err_part /*[nblk][kErrStats]*/)
 {
     __shared__ double red[kBlk];
     const BlkItem it = items[blockIdx.x];
     const SysDev S = sys[it.sys];
     const int i = it.blk * kBlk + threadIdx.x;
-    double e2 = 0.0, b2 = 0.0, ps[kMaxD] = {0.0, 0.0, 0.0, 0.0}, ss[kMaxD] = {0.0, 0.0, 0.0, 0.0};
+    double e2 = 0.0, b2 = 0.0, r2 = 0.0, ps[kMaxD] = {0.0, 0.0, 0.0, 0.0}, ss[kMaxD] = {0.0, 0.0, 0.0, 0.0};
     if (i < S.N) {
         const int64_t slot = S.off + i;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const double pair = pair_partials<D>(S, Bp, Bpj, k, P, i) * S.pair_scale;
             const double sv = (double)surr[k * P + slot] - (double)surr_mean[(int64_t)it.sys * kMaxD + k];
-            const double df = sv - pair;
-            e2 += df * df;
+            const double q = res_read ? sv + (double)res[k * P + slot] : sv;
+            if (res_write) res[k * P + slot] = (float)(pair - sv);
+            e2 += (q - pair) * (q - pair);
+            r2 += (sv - pair) * (sv - pair);
             b2 += pair * pair;
             ps[k] = pair * sv;
             ss[k] = sv * sv;
@@ -709,9 +799,11 @@ __global__ __launch_bounds__(kBlk) void k_surr_err(const BlkItem* __restrict__ i
     double* out = err_part + (int64_t)blockIdx.x * kErrStats;
     const double t0 = block_sum(e2, red);
     const double t1 = block_sum(b2, red);
+    const double t2 = block_sum(r2, red);
     if (threadIdx.x == 0) {
         out[0] = t0;
         out[1] = t1;
+        out[2 + 2 * kMaxD] = t2;
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) {

@@ -137,8 +137,12 @@ class SSM:
         m = np.ascontiguousarray(np.asarray(master, dtype=np.float32).ravel())
         check(_lib.load().ssm_surrogate_load(self._h, m.ctypes.data, m.size))
 
-    def surrogate_enable(self, check_every: int = 16, tol: float = 1e-3) -> None:
-        check(_lib.load().ssm_surrogate_enable(self._h, int(check_every), float(tol)))
+    def surrogate_enable(self, check_every: int = 16, tol: float = 1e-3, mode: str = "gain") -> None:
+        """mode "gain": g (s - mean s); "residual": (s - mean s) + the residual of the last check."""
+        modes = {"gain": 0, "residual": 1}
+        if mode not in modes:
+            raise ValueError(f"mode must be one of {sorted(modes)}")
+        check(_lib.load().ssm_surrogate_enable(self._h, int(check_every), float(tol), modes[mode]))
 
     def surrogate_samples(self, n: int, seed: int, sys: int = 0):
         """(U [n][d+32], T [n][d]) float32 device tensors from the current state."""
