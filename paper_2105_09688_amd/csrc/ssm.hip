@@ -211,6 +211,7 @@ struct ssm_ctx {
     PairItem* dpair = nullptr;
     BlkItem* dblk = nullptr;
     Flags* dflags = nullptr;
+    int32_t* dnmax = nullptr;      // [nblk_tot][kSlotsPerBlk] largest Newton iteration count
     double* dstage = nullptr;  // staging for state copies / moments
     int64_t bytes = 0;
     // per phase (tick % max_stride) work lists: offsets into dpair / dblk
@@ -305,7 +306,7 @@ static void free_ctx(ssm_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* bufs[] = {c->X, c->Y, c->Ys, c->Bp, c->Bpj, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
                     c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list, c->smean_part, c->smean,
-                    c->dtick, c->dW};
+                    c->dtick, c->dW, c->surr_res, c->dnmax};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     recycle_events(c, c->ev_pair);
@@ -449,7 +450,7 @@ static ssm_status launch_surrogate(ssm_ctx* c, int64_t ph)
     SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, items,
                                          c->dsys, c->P, (const T*)c->Y, c->rff, c->rff_part));
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_rff_final, dim3((unsigned)c->sys_list_cnt[ph]), dim3(64), 0, c->stream,
+    hipLaunchKernelGGL(k_rff_final, dim3((unsigned)c->sys_list_cnt[ph], 2 * kRff), dim3(kBlk), 0, c->stream,
                        c->dsys_list + c->sys_list_off[ph], c->dsys, c->rff_part, c->mom);
     HIP_TRY(hipGetLastError());
     const unsigned grid = (unsigned)std::min<int64_t>(nb, 2048);
@@ -459,8 +460,8 @@ static ssm_status launch_surrogate(ssm_ctx* c, int64_t ph)
     SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_surr_partial<D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, items,
                                          c->dsys, c->P, c->surr, c->smean_part));
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_surr_final, dim3((unsigned)c->sys_list_cnt[ph]), dim3(64), 0, c->stream,
-                       c->dsys_list + c->sys_list_off[ph], c->dsys, d, c->smean_part, c->smean);
+    hipLaunchKernelGGL(k_surr_final, dim3((unsigned)c->sys_list_cnt[ph], d), dim3(kBlk), 0, c->stream,
+                       c->dsys_list + c->sys_list_off[ph], c->dsys, c->smean_part, c->smean);
     HIP_TRY(hipGetLastError());
     return SSM_OK;
 }
@@ -538,12 +539,12 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
                                              (use_surr && c->surr_mode == SSM_SURR_RESIDUAL && c->surr_res_valid)
                                                  ? c->surr_res : nullptr,
                                              c->dW, c->Bpj,
-                                             c->psumX, c->psumY, c->nblk_tot, c->dflags));
+                                             c->psumX, c->psumY, c->nblk_tot, c->dflags, c->dnmax));
         HIP_TRY(hipGetLastError());
         if (!c->fused) {
             SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_newton<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream,
                                                  items, c->dsys, c->coef, c->P, c->tick, tdev, X, Y, Ys,
-                                                 c->psumX, c->psumY, c->nblk_tot, c->dflags));
+                                                 c->psumX, c->psumY, c->nblk_tot, c->dflags, c->dnmax));
             HIP_TRY(hipGetLastError());
         }
         if (c->profiling) {
@@ -662,7 +663,7 @@ static ssm_status launch_init(ssm_ctx* c)
     HIP_TRY(hipGetLastError());
     SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<T, D>), dim3(nb), dim3(kBlk), 0, c->stream, items, c->dsys,
                                             c->coef, c->P, (int64_t)-1, (const int64_t*)nullptr, (const T*)c->X, (T*)c->Y, (T*)c->Ys,
-                                            c->psumX, c->psumY, c->nblk_tot, c->dflags));
+                                            c->psumX, c->psumY, c->nblk_tot, c->dflags, c->dnmax));
     HIP_TRY(hipGetLastError());
     return SSM_OK;
 }
@@ -868,6 +869,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     ALLOC(c->dpair, std::max<size_t>(pairs.size(), 1) * sizeof(PairItem));
     ALLOC(c->dblk, blks.size() * sizeof(BlkItem));
     ALLOC(c->dflags, sizeof(Flags));
+    ALLOC(c->dnmax, (size_t)c->nblk_tot * kSlotsPerBlk * sizeof(int32_t));
     ALLOC(c->dtick, sizeof(int64_t));
     ALLOC(c->dW, (size_t)c->d * c->P * sizeof(double));
     ALLOC(c->dsys_list, sys_lists.size() * sizeof(int32_t));
@@ -880,6 +882,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     if (he == hipSuccess) he = hipMemcpyAsync(c->dblk, blks.data(), blks.size() * sizeof(BlkItem), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipMemcpyAsync(c->dsys_list, sys_lists.data(), sys_lists.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(c->dflags, 0, sizeof(Flags), c->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(c->dnmax, 0, (size_t)c->nblk_tot * kSlotsPerBlk * sizeof(int32_t), c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(c->dtick, 0, sizeof(int64_t), c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);  // host vectors go out of scope
     if (he != hipSuccess) { std::string m = hipGetErrorString(he); free_ctx(c); return fail(SSM_ERR_HIP, "upload: " + m); }
@@ -1059,11 +1062,11 @@ extern "C" ssm_status ssm_set_state(ssm_ctx* c, int32_t sys, const double* host)
         if (c->prec == SSM_FP64) {
             SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<double, D>), dim3((unsigned)items.size()), dim3(kBlk), 0, c->stream,
                                                     ditems, c->dsys, c->coef, c->P, tick_arg, (const int64_t*)nullptr, (const double*)c->X, (double*)c->Y,
-                                                    (double*)c->Ys, c->psumX, c->psumY, c->nblk_tot, c->dflags));
+                                                    (double*)c->Ys, c->psumX, c->psumY, c->nblk_tot, c->dflags, c->dnmax));
         } else {
             SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<float, D>), dim3((unsigned)items.size()), dim3(kBlk), 0, c->stream,
                                                     ditems, c->dsys, c->coef, c->P, tick_arg, (const int64_t*)nullptr, (const float*)c->X, (float*)c->Y,
-                                                    (float*)c->Ys, c->psumX, c->psumY, c->nblk_tot, c->dflags));
+                                                    (float*)c->Ys, c->psumX, c->psumY, c->nblk_tot, c->dflags, c->dnmax));
         }
         he = hipGetLastError();
     }
@@ -1125,7 +1128,9 @@ extern "C" ssm_status ssm_info(ssm_ctx* c, ssm_info_t* out)
     HIP_TRY(hipMemcpy(&f, c->dflags, sizeof(Flags), hipMemcpyDeviceToHost));
     out->tick = c->tick;
     out->ticks_total = c->ticks_total;
-    out->newton_max_seen = f.newton_max;
+    std::vector<int32_t> nmax((size_t)c->nblk_tot * kSlotsPerBlk);
+    HIP_TRY(hipMemcpy(nmax.data(), c->dnmax, nmax.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    out->newton_max_seen = nmax.empty() ? 0 : *std::max_element(nmax.begin(), nmax.end());
     out->newton_failures = f.newton_fail;
     out->nonfinite = f.nonfinite;
     out->n_pair_items = (int32_t)c->pair_cnt[0];
@@ -1420,7 +1425,7 @@ extern "C" ssm_status ssm_surrogate_samples(ssm_ctx* c, int32_t sys, int64_t n, 
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<float, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const float*)c->Y, c->rff, c->rff_part));
     }
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_rff_final, dim3((unsigned)c->sys_list_cnt[0]), dim3(64), 0, c->stream, c->dsys_list + c->sys_list_off[0], c->dsys, c->rff_part, c->mom);
+    hipLaunchKernelGGL(k_rff_final, dim3((unsigned)c->sys_list_cnt[0], 2 * kRff), dim3(kBlk), 0, c->stream, c->dsys_list + c->sys_list_off[0], c->dsys, c->rff_part, c->mom);
     HIP_TRY(hipGetLastError());
     const dim3 g((unsigned)((n + 255) / 256));
     if (c->prec == SSM_FP64) {

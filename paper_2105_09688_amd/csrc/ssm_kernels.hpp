@@ -69,12 +69,17 @@ struct Coef {
     int32_t pad;
 };
 
+// Error counters (atomics: they fire only when something goes wrong).
 struct Flags {
     int32_t newton_fail;
     int32_t nonfinite;
-    int32_t newton_max;
-    int32_t pad;
+    int32_t pad[2];
 };
+
+// Largest Newton iteration count per wavefront slot: slot gb * kSlotsPerBlk + w
+// for global block gb, wavefront w (plain stores by the owning wavefront; a
+// device-wide atomic per wavefront on one address serializes across the XCDs).
+constexpr int kSlotsPerBlk = kBlk / 64;
 
 template <typename T>
 __device__ __forceinline__ T exp2_fast(T x);
@@ -233,7 +238,8 @@ __device__ __forceinline__ void solve_and_store(const SysDev& S, const Coef& cf,
                                                 double m2, int64_t slot, int64_t P,
                                                 T* __restrict__ Y, T* __restrict__ Ys,
                                                 double* __restrict__ psumY_out, int64_t gb,
-                                                int64_t nblk_tot, Flags* flags, double* red)
+                                                int64_t nblk_tot, Flags* flags, int32_t* __restrict__ nmax,
+                                                double* red)
 {
     double w[D], y[D];
 #pragma unroll
@@ -242,11 +248,20 @@ __device__ __forceinline__ void solve_and_store(const SysDev& S, const Coef& cf,
     int it = 0;
     if (valid) {
         it = implicit_radial<D>(w, alpha, S.h * cf.v_a, cf.newton_max_iter, y);
-        if (it < 0) atomicAdd(&flags->newton_fail, 1);
-        else if (it > 0) atomicMax(&flags->newton_max, it);
     } else {
 #pragma unroll
         for (int k = 0; k < D; ++k) y[k] = 0.0;
+    }
+    // failures: one atomic per wavefront that has any; iteration counts: the
+    // wavefront's maximum into its own slot
+    const uint64_t fails = __ballot(it < 0);
+    int itmax = it;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) itmax = max(itmax, __shfl_xor(itmax, off, 64));
+    if ((threadIdx.x & 63) == 0) {
+        if (fails) atomicAdd(&flags->newton_fail, (int)__popcll(fails));
+        int32_t* slot = nmax + gb * kSlotsPerBlk + (threadIdx.x >> 6);
+        if (itmax > *slot) *slot = itmax;
     }
     double ysum[D];
 #pragma unroll
@@ -278,7 +293,7 @@ __global__ __launch_bounds__(kBlk) void k_newton(const BlkItem* __restrict__ ite
                                                  T* __restrict__ Ys,
                                                  const double* __restrict__ psumX,
                                                  double* __restrict__ psumY, int64_t nblk_tot,
-                                                 Flags* flags)
+                                                 Flags* flags, int32_t* __restrict__ nmax)
 {
     __shared__ double red[kBlk];
     const BlkItem it = items[blockIdx.x];
@@ -305,7 +320,7 @@ __global__ __launch_bounds__(kBlk) void k_newton(const BlkItem* __restrict__ ite
         for (int k = 0; k < D; ++k) x[k] = (double)X[k * P + slot];
     }
     solve_and_store<T, D>(S, cf, valid, x, xbar, m2, slot, P, Y, Ys, pY, S.blk0 + it.blk, nblk_tot,
-                          flags, red);
+                          flags, nmax, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -328,7 +343,7 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
                                                  const float* __restrict__ Bpj,
                                                  double* __restrict__ psumX,
                                                  double* __restrict__ psumY, int64_t nblk_tot,
-                                                 Flags* flags)
+                                                 Flags* flags, int32_t* __restrict__ nmax)
 {
     __shared__ double red[kBlk];
     const BlkItem it = items[blockIdx.x];
@@ -380,7 +395,7 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
     if (cf.fused) {
         const double zero[kMaxD] = {0.0, 0.0, 0.0, 0.0};
         solve_and_store<T, D>(S, cf, valid, xn, zero, 0.0, slot, P, Y, Ys,
-                              psumY + (int64_t)par_out * D * nblk_tot, gb, nblk_tot, flags, red);
+                              psumY + (int64_t)par_out * D * nblk_tot, gb, nblk_tot, flags, nmax, red);
     } else {
         double* pX = psumX + (int64_t)par_out * (D + 1) * nblk_tot;
 #pragma unroll

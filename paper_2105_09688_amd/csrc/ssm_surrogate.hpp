@@ -381,17 +381,28 @@ __global__ __launch_bounds__(kBlk) void k_rff_partial(const BlkItem* __restrict_
     }
 }
 
-// one block per listed system: mom[sys][q] = (1/N) sum of its block partials
-__global__ void k_rff_final(const int32_t* __restrict__ sys_list, const SysDev* __restrict__ sys,
-                            const double* __restrict__ part, float* __restrict__ mom)
+// Sum over a system's block partials part[(blk0 + b) * stride + q], b < nblk:
+// thread t adds b = t, t + kBlk, ... in order, then a fixed-order tree over
+// the block.  All threads of the block must call it.
+__device__ __forceinline__ double sum_block_partials(const double* __restrict__ part, int64_t blk0, int64_t nblk,
+                                                     int stride, int q, double* red)
 {
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < nblk; b += kBlk) acc += part[(blk0 + b) * stride + q];
+    return block_sum(acc, red);
+}
+
+// grid (listed systems, 2K), kBlk threads: mom[sys][q] = (1/N) sum of its block partials
+__global__ __launch_bounds__(kBlk) void k_rff_final(const int32_t* __restrict__ sys_list,
+                                                    const SysDev* __restrict__ sys,
+                                                    const double* __restrict__ part, float* __restrict__ mom)
+{
+    __shared__ double red[kBlk];
     const int s = sys_list[blockIdx.x];
     const SysDev S = sys[s];
-    const int q = threadIdx.x;
-    if (q >= 2 * kRff) return;
-    double acc = 0.0;
-    for (int b = 0; b < S.nblk; ++b) acc += part[(int64_t)(S.blk0 + b) * (2 * kRff) + q];
-    mom[(int64_t)s * (2 * kRff) + q] = (float)(acc / (double)S.N);
+    const int q = blockIdx.y;
+    const double t = sum_block_partials(part, S.blk0, S.nblk, 2 * kRff, q, red);
+    if (threadIdx.x == 0) mom[(int64_t)s * (2 * kRff) + q] = (float)(t / (double)S.N);
 }
 
 // ---------------------------------------------------------------------------
@@ -745,16 +756,18 @@ __global__ __launch_bounds__(kBlk) void k_surr_partial(const BlkItem* __restrict
     }
 }
 
-__global__ void k_surr_final(const int32_t* __restrict__ sys_list, const SysDev* __restrict__ sys, int d,
-                             const double* __restrict__ part, float* __restrict__ mean /*[n_sys][kMaxD]*/)
+// grid (listed systems, d), kBlk threads
+__global__ __launch_bounds__(kBlk) void k_surr_final(const int32_t* __restrict__ sys_list,
+                                                     const SysDev* __restrict__ sys,
+                                                     const double* __restrict__ part,
+                                                     float* __restrict__ mean /*[n_sys][kMaxD]*/)
 {
+    __shared__ double red[kBlk];
     const int s = sys_list[blockIdx.x];
     const SysDev S = sys[s];
-    const int k = threadIdx.x;
-    if (k >= d) return;
-    double acc = 0.0;
-    for (int b = 0; b < S.nblk; ++b) acc += part[(int64_t)(S.blk0 + b) * kMaxD + k];
-    mean[(int64_t)s * kMaxD + k] = (float)(acc / (double)S.N);
+    const int k = blockIdx.y;
+    const double t = sum_block_partials(part, S.blk0, S.nblk, kMaxD, k, red);
+    if (threadIdx.x == 0) mean[(int64_t)s * kMaxD + k] = (float)(t / (double)S.N);
 }
 
 // Check statistics per update block (fixed-order block sums), for the listed
