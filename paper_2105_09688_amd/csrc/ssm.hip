@@ -203,6 +203,7 @@ struct ssm_ctx {
     void* Ys = nullptr;
     double* Bp = nullptr;
     float* Bpj = nullptr;      // symmetric scheme: j-side partials [nb_max][d][P]
+    double* pairsum = nullptr; // [d][P] scaled pair term of the last exact tick (k_combine)
     bool sym = false;          // symmetric pair scheme (FP32 modes)
     int64_t nb_max = 0;
     double* psumX = nullptr;
@@ -304,7 +305,7 @@ static void free_ctx(ssm_ctx* c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    void* bufs[] = {c->X, c->Y, c->Ys, c->Bp, c->Bpj, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
+    void* bufs[] = {c->X, c->Y, c->Ys, c->Bp, c->Bpj, c->pairsum, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
                     c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list, c->smean_part, c->smean,
                     c->dtick, c->dW, c->surr_res, c->dnmax};
     for (void* b : bufs)
@@ -502,14 +503,6 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
         ssm_status st = launch_surrogate<T>(c, ph);
         if (st != SSM_OK) return st;
     }
-    if (check && nb > 0) {
-        const BlkItem* items = c->dblk + c->blk_off[ph];
-        const bool resid = c->surr_mode == SSM_SURR_RESIDUAL;
-        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_surr_err<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, items,
-                                             c->dsys, c->P, c->Bp, c->Bpj, c->surr, c->smean, c->surr_res,
-                                             (resid && c->surr_res_valid) ? 1 : 0, resid ? 1 : 0, c->err_part));
-        HIP_TRY(hipGetLastError());
-    }
     const int use_surr = (run_surr && !check) ? 1 : 0;
     if (nb > 0) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -519,6 +512,11 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
             if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
         }
         const BlkItem* items = c->dblk + c->blk_off[ph];
+        if (c->has_pair && run_exact) {
+            SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<D>), dim3((unsigned)(nb * 4)), dim3(64 * kCombineWaves), 0,
+                                                 c->stream, items, c->dsys, c->P, c->Bp, c->Bpj, c->pairsum));
+            HIP_TRY(hipGetLastError());
+        }
         const unsigned gb = (unsigned)(nb * c->bm_lanes);
 #define SSM_BM(LPV) SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_brownian_sum<D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, \
                                                          items, c->dsys, c->coef, c->P, c->tick, tdev, c->dW))
@@ -532,13 +530,13 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
 #undef SSM_BM
         HIP_TRY(hipGetLastError());
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_update<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream,
-                                             items, c->dsys, c->coef, c->P, c->tick, tdev, X, Y, Ys, c->Bp, c->surr,
+                                             items, c->dsys, c->coef, c->P, c->tick, tdev, X, Y, Ys, c->pairsum, c->surr,
                                              c->smean, use_surr,
                                              make_float4((float)c->surr_gain[0], (float)c->surr_gain[1],
                                                          (float)c->surr_gain[2], (float)c->surr_gain[3]),
                                              (use_surr && c->surr_mode == SSM_SURR_RESIDUAL && c->surr_res_valid)
                                                  ? c->surr_res : nullptr,
-                                             c->dW, c->Bpj,
+                                             c->dW,
                                              c->psumX, c->psumY, c->nblk_tot, c->dflags, c->dnmax));
         HIP_TRY(hipGetLastError());
         if (!c->fused) {
@@ -551,6 +549,16 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
             if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
             c->ev_update.push_back({e0, e1});
         }
+    }
+    if (check && nb > 0) {
+        // check statistics (and, in residual mode, the new residuals) from this
+        // tick's exact term and surrogate; k_update of this tick used the exact term
+        const BlkItem* items = c->dblk + c->blk_off[ph];
+        const bool resid = c->surr_mode == SSM_SURR_RESIDUAL;
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_surr_err<T, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, items,
+                                             c->dsys, c->P, c->pairsum, c->surr, c->smean, c->surr_res,
+                                             (resid && c->surr_res_valid) ? 1 : 0, resid ? 1 : 0, c->err_part));
+        HIP_TRY(hipGetLastError());
     }
     if (capture) {
         hipLaunchKernelGGL(k_tick_advance, dim3(1), dim3(64), 0, c->stream, c->dtick);
@@ -862,6 +870,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     ALLOC(c->Y, field);
     ALLOC(c->Ys, field);
     ALLOC(c->Bp, c->has_pair ? (size_t)c->max_splits * c->d * c->P * sizeof(double) : 0);
+    ALLOC(c->pairsum, c->has_pair ? (size_t)c->d * c->P * sizeof(double) : 0);
     ALLOC(c->Bpj, (c->has_pair && c->sym) ? (size_t)c->nb_max * c->d * c->P * sizeof(float) : 0);
     ALLOC(c->psumX, 2 * (size_t)(c->d + 1) * c->nblk_tot * sizeof(double));
     ALLOC(c->psumY, 2 * (size_t)c->d * c->nblk_tot * sizeof(double));
@@ -1197,19 +1206,6 @@ static size_t kernel_ws_bytes(int32_t d, int64_t N, int32_t precision, const KPl
            align256((size_t)std::max<int64_t>(p.nb, 1) * d * N * sizeof(float));
 }
 
-namespace ssm {
-template <int D>
-__global__ void k_combine_sys(const SysDev* __restrict__ sys, const double* __restrict__ Bp,
-                              const float* __restrict__ Bpj, int64_t P, double scale, double* __restrict__ K)
-{
-    const SysDev S = sys[0];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S.N) return;
-#pragma unroll
-    for (int k = 0; k < D; ++k) K[(int64_t)k * S.N + i] = pair_partials<D>(S, Bp, Bpj, k, P, i) * scale;
-}
-}  // namespace ssm
-
 extern "C" size_t ssm_pair_workspace_bytes(int32_t d, int64_t N, int32_t precision)
 {
     if (d < 1 || d > SSM_MAX_D || N < 1 || N > 0x7fffffff - 1024) return 0;
@@ -1238,6 +1234,8 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
     S.splits = (int32_t)plan.isplits;
     S.sym_B = plan.sym ? 64 * kernel_R(d) * kWaves : 0;
     S.sym_L = plan.sym ? (int32_t)plan.L : 0;
+    const double c = std::sqrt(kLog2e / (2.0 * ell * ell));
+    S.pair_scale = 1.0 / ((double)N * c);  // unscaled sums of the scaled coordinates -> (1/N) sum
     char* w = (char*)workspace;
     SysDev* dS = (SysDev*)w; w += align256(sizeof(SysDev));
     PairItem* dI = (PairItem*)w; w += align256(plan.items.size() * sizeof(PairItem));
@@ -1246,7 +1244,6 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
     float* dBpj = (float*)w;
     HIP_TRY(hipMemcpyAsync(dS, &S, sizeof(S), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dI, plan.items.data(), plan.items.size() * sizeof(PairItem), hipMemcpyHostToDevice, st));
-    const double c = std::sqrt(kLog2e / (2.0 * ell * ell));
     const int64_t n = (int64_t)d * N;
     const dim3 g1((unsigned)((n + 255) / 256));
     const dim3 gp((unsigned)(plan.sym ? plan.items.size() : (plan.items.size() + kWaves - 1) / kWaves));
@@ -1257,8 +1254,9 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
         hipLaunchKernelGGL(k_scale_copy<float>, g1, dim3(256), 0, st, (const float*)Y, (float*)dYs, n, c);
         launch_pair<float>(d, kernel_R(d), precision == SSM_FP32_KAHAN, gp, st, dI, (int)plan.items.size(), dS, (const float*)dYs, N, dBp, dBpj, plan.sym);
     }
-    const dim3 gc((unsigned)((N + 255) / 256));
-    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine_sys<D>), gc, dim3(256), 0, st, dS, dBp, dBpj, N, 1.0 / ((double)N * c), K));
+    const dim3 gc((unsigned)(4 * ((N + kBlk - 1) / kBlk)));
+    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<D>), gc, dim3(64 * kCombineWaves), 0, st, (const BlkItem*)nullptr, dS,
+                                         N, dBp, dBpj, K));
     HIP_TRY(hipGetLastError());
     // the host-side plan must outlive the asynchronous copies
     HIP_TRY(hipStreamSynchronize(st));
@@ -1425,13 +1423,16 @@ extern "C" ssm_status ssm_surrogate_samples(ssm_ctx* c, int32_t sys, int64_t n, 
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<float, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const float*)c->Y, c->rff, c->rff_part));
     }
     HIP_TRY(hipGetLastError());
+    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<D>), dim3((unsigned)(nb * 4)), dim3(64 * kCombineWaves), 0, c->stream,
+                                         c->dblk + c->blk_off[0], c->dsys, c->P, c->Bp, c->Bpj, c->pairsum));
+    HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_rff_final, dim3((unsigned)c->sys_list_cnt[0], 2 * kRff), dim3(kBlk), 0, c->stream, c->dsys_list + c->sys_list_off[0], c->dsys, c->rff_part, c->mom);
     HIP_TRY(hipGetLastError());
     const dim3 g((unsigned)((n + 255) / 256));
     if (c->prec == SSM_FP64) {
-        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_gather_samples<double, D>), g, dim3(256), 0, c->stream, c->dsys, sys, c->P, (const double*)c->Y, c->Bp, c->Bpj, c->mom, n, seed, U, Tt));
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_gather_samples<double, D>), g, dim3(256), 0, c->stream, c->dsys, sys, c->P, (const double*)c->Y, c->pairsum, c->mom, n, seed, U, Tt));
     } else {
-        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_gather_samples<float, D>), g, dim3(256), 0, c->stream, c->dsys, sys, c->P, (const float*)c->Y, c->Bp, c->Bpj, c->mom, n, seed, U, Tt));
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_gather_samples<float, D>), g, dim3(256), 0, c->stream, c->dsys, sys, c->P, (const float*)c->Y, c->pairsum, c->mom, n, seed, U, Tt));
     }
     HIP_TRY(hipGetLastError());
     return ssm_sync(c);

@@ -96,57 +96,89 @@ __device__ __forceinline__ double exp2_fast<double>(double x)
     return exp2(x);
 }
 
-// sum_{q < splits} Bp[(q D + k) P + slot] in ascending q, with the loads
-// issued eight at a time (same rounding as the plain loop).
-template <int D>
-__device__ __forceinline__ double combine_splits(const double* __restrict__ Bp, int splits, int k, int64_t P,
-                                                 int64_t slot)
-{
-    double acc = 0.0;
-    int q0 = 0;
-    for (; q0 + 8 <= splits; q0 += 8) {
-        double v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = Bp[((int64_t)(q0 + u) * D + k) * P + slot];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc += v[u];
-    }
-    for (; q0 < splits; ++q0) acc += Bp[((int64_t)q0 * D + k) * P + slot];
-    return acc;
-}
+// The partial-sum rows of particle i of system S, in their fixed order:
+// ni i-side rows (doubles, Bp[q][k][P]: the target tile's or group's work
+// items) then, in the symmetric scheme, nj j-side rows (floats, Bpj[a][k][P]:
+// every earlier group and the particle's own group).
+struct PairRows {
+    int ni, nj;
+};
 
-// Pair sum of particle i of a system under the symmetric scheme: i-side
-// partials (the group's diagonal item, then the later source ranges of i's
-// group) and j-side partials from every earlier group and from i's own group,
-// in that fixed order.
-template <int D>
-__device__ __forceinline__ double combine_sym(const SysDev& S, const double* __restrict__ Bp,
-                                              const float* __restrict__ Bpj, int k, int64_t P, int i)
+__device__ __forceinline__ PairRows pair_rows(const SysDev& S, int i)
 {
+    if (!S.sym_B) return PairRows{S.splits, 0};
     const int a = i / S.sym_B;
     const int rest = S.N - S.sym_B * (a + 1);
-    const int ns = 1 + (rest > 0 ? (rest + S.sym_L - 1) / S.sym_L : 0);
-    const int64_t slot = S.off + i;
-    double acc = combine_splits<D>(Bp, ns, k, P, slot);
-    const int rows = a + 1;
-    int q0 = 0;
-    for (; q0 + 8 <= rows; q0 += 8) {
-        float v[8];
+    return PairRows{1 + (rest > 0 ? (rest + S.sym_L - 1) / S.sym_L : 0), a + 1};
+}
+
+// Sum, in ascending order, of the rows r = w, w + W, w + 2W, ... (r < ni + nj)
+// of component k at slot; loads are issued four at a time.
+template <int D, int W>
+__device__ __forceinline__ double sum_rows(const double* __restrict__ Bp, const float* __restrict__ Bpj,
+                                           PairRows pr, int k, int64_t P, int64_t slot, int w)
+{
+    double acc = 0.0;
+    int r = w;
+    for (; r + 3 * W < pr.ni; r += 4 * W) {
+        double v[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = Bpj[((int64_t)(q0 + u) * D + k) * P + slot];
+        for (int u = 0; u < 4; ++u) v[u] = Bp[((int64_t)(r + u * W) * D + k) * P + slot];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += (double)v[u];
+        for (int u = 0; u < 4; ++u) acc += v[u];
     }
-    for (; q0 < rows; ++q0) acc += (double)Bpj[((int64_t)q0 * D + k) * P + slot];
+    for (; r < pr.ni; r += W) acc += Bp[((int64_t)r * D + k) * P + slot];
+    int q = r - pr.ni;
+    for (; q + 3 * W < pr.nj; q += 4 * W) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = Bpj[((int64_t)(q + u * W) * D + k) * P + slot];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += (double)v[u];
+    }
+    for (; q < pr.nj; q += W) acc += (double)Bpj[((int64_t)q * D + k) * P + slot];
     return acc;
 }
 
-// Combined (unscaled) pair sum of particle i of system S, component k.
+// ---------------------------------------------------------------------------
+// k_combine: the scaled pair term of every particle of the listed blocks,
+// out[k][slot] = pair_scale * (sum of the particle's partial rows).  Four
+// blocks of 64 particles per 256-particle block item (items
+// null: system 0, block blockIdx.x / 4); wavefront w of a block adds the rows
+// w, w + 4, ... and the four sums are added in wavefront order, so the result
+// does not depend on the launch.
+// ---------------------------------------------------------------------------
+constexpr int kCombineWaves = 4;
+
 template <int D>
-__device__ __forceinline__ double pair_partials(const SysDev& S, const double* __restrict__ Bp,
-                                                const float* __restrict__ Bpj, int k, int64_t P, int i)
+__global__ __launch_bounds__(64 * kCombineWaves) void k_combine(const BlkItem* __restrict__ items,
+                                                               const SysDev* __restrict__ sys, int64_t P,
+                                                               const double* __restrict__ Bp,
+                                                               const float* __restrict__ Bpj,
+                                                               double* __restrict__ out)
 {
-    return S.sym_B ? combine_sym<D>(S, Bp, Bpj, k, P, i) : combine_splits<D>(Bp, S.splits, k, P, S.off + i);
+    __shared__ double part[kCombineWaves][D][64];
+    const int q4 = blockIdx.x & 3;
+    const BlkItem it = items ? items[blockIdx.x >> 2] : BlkItem{0, (int32_t)(blockIdx.x >> 2)};
+    const SysDev S = sys[it.sys];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int i = it.blk * kBlk + q4 * 64 + lane;
+    const bool valid = i < S.N;
+    const int64_t slot = S.off + i;
+    const PairRows pr = valid ? pair_rows(S, i) : PairRows{0, 0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) part[wave][k][lane] = sum_rows<D, kCombineWaves>(Bp, Bpj, pr, k, P, slot, wave);
+    __syncthreads();
+    if (wave == 0 && valid) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            double t = part[0][k][lane];
+#pragma unroll
+            for (int w = 1; w < kCombineWaves; ++w) t += part[w][k][lane];
+            out[k * P + slot] = t * S.pair_scale;
+        }
+    }
 }
 
 // The tick a per-tick kernel works on: the context's device counter when
@@ -335,12 +367,11 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
                                                  const int64_t* __restrict__ tick_dev,
                                                  T* __restrict__ X,
                                                  T* __restrict__ Y, T* __restrict__ Ys,
-                                                 const double* __restrict__ Bp,
+                                                 const double* __restrict__ pairsum,
                                                  const float* __restrict__ surr,
                                                  const float* __restrict__ surr_mean, int use_surr,
                                                  float4 surr_gain, const float* __restrict__ surr_res,
                                                  const double* __restrict__ dWbuf,
-                                                 const float* __restrict__ Bpj,
                                                  double* __restrict__ psumX,
                                                  double* __restrict__ psumY, int64_t nblk_tot,
                                                  Flags* flags, int32_t* __restrict__ nmax)
@@ -373,7 +404,7 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
                 pair = (double)gk * ((double)surr[k * P + slot] - (double)surr_mean[(int64_t)it.sys * kMaxD + k]);
                 if (surr_res) pair += (double)surr_res[k * P + slot];
             } else if (cf.has_pair) {
-                pair = pair_partials<D>(S, Bp, Bpj, k, P, i) * S.pair_scale;
+                pair = pairsum[k * P + slot];
             }
             const double b = cf.b_c0 * y + cf.b_lam * ybar[k] + pair;
             const double sig = cf.s0[k] + cf.s1[k] * y + cf.s2[k] * ybar[k];
@@ -640,6 +671,8 @@ __device__ __forceinline__ void sym_chunk(const float* __restrict__ base, int64_
     sym_route<D, 15>(accj, tot);
 #pragma unroll
     for (int c = 0; c < D; ++c) {
+        // across the rows through the LDS crossbar (ds_bpermute runs beside the
+        // VALU work; the gfx950 row-swap instructions measured slower here)
         tot[c] += __shfl_xor(tot[c], 16, 64);
         tot[c] += __shfl_xor(tot[c], 32, 64);
     }

@@ -497,8 +497,7 @@ __global__ __launch_bounds__(256) void k_mlp_apply(const float* __restrict__ U, 
 // at particle i, for n draws of i (Philox tag 4, counter (q, 0, 1)).
 template <typename T, int D>
 __global__ void k_gather_samples(const SysDev* __restrict__ sys, int s, int64_t P, const T* __restrict__ Y,
-                                 const double* __restrict__ Bp, const float* __restrict__ Bpj,
-                                 const float* __restrict__ mom, int64_t n,
+                                 const double* __restrict__ pairsum, const float* __restrict__ mom, int64_t n,
                                  uint64_t seed, float* __restrict__ U, float* __restrict__ Tt)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -511,7 +510,7 @@ __global__ void k_gather_samples(const SysDev* __restrict__ sys, int s, int64_t 
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         U[q * in + k] = (float)Y[k * P + slot];
-        Tt[q * D + k] = (float)(pair_partials<D>(S, Bp, Bpj, k, P, (int)i) * S.pair_scale);
+        Tt[q * D + k] = (float)pairsum[k * P + slot];
     }
     for (int m = 0; m < 2 * kRff; ++m) U[q * in + D + m] = mom[(int64_t)s * (2 * kRff) + m];
 }
@@ -782,8 +781,7 @@ constexpr int kErrStats = 3 + 2 * kMaxD;
 template <typename T, int D>
 __global__ __launch_bounds__(kBlk) void k_surr_err(const BlkItem* __restrict__ items,
                                                    const SysDev* __restrict__ sys, int64_t P,
-                                                   const double* __restrict__ Bp,
-                                                   const float* __restrict__ Bpj,
+                                                   const double* __restrict__ pairsum,
                                                    const float* __restrict__ surr,
                                                    const float* __restrict__ surr_mean,
                                                    float* res, int res_read, int res_write,
@@ -798,7 +796,7 @@ __global__ __launch_bounds__(kBlk) void k_surr_err(const BlkItem* __restrict__ i
         const int64_t slot = S.off + i;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const double pair = pair_partials<D>(S, Bp, Bpj, k, P, i) * S.pair_scale;
+            const double pair = pairsum[k * P + slot];
             const double sv = (double)surr[k * P + slot] - (double)surr_mean[(int64_t)it.sys * kMaxD + k];
             const double q = res_read ? sv + (double)res[k * P + slot] : sv;
             if (res_write) res[k * P + slot] = (float)(pair - sv);
