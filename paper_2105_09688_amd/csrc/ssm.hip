@@ -87,7 +87,7 @@ __global__ void k_implicit_plain(int64_t N, const double* __restrict__ X, double
 // Symmetric scheme: one workgroup per item.
 template <int D>
 static void launch_pair_sym_D(int R, bool kahan, int n, hipStream_t st, const PairItem* items, const SysDev* sys,
-                              const float* Ys, int64_t P, double* Bp, float* Bpj)
+                              const float* Ys, int64_t P, float* Bp, float* Bpj)
 {
     dim3 grid((unsigned)n), block(64 * kWaves);
 #define SSM_SYM_CASE(RR)                                                                                   \
@@ -109,7 +109,7 @@ static void launch_pair_sym_D(int R, bool kahan, int n, hipStream_t st, const Pa
 
 template <typename T, int D>
 static void launch_pair_T(int R, bool kahan, dim3 grid, hipStream_t st, const PairItem* items,
-                          int n, const SysDev* sys, const T* Ys, int64_t P, double* Bp, float* Bpj)
+                          int n, const SysDev* sys, const T* Ys, int64_t P, T* Bp, float* Bpj)
 {
     (void)Bpj;
     dim3 block(64 * kWaves);
@@ -134,7 +134,7 @@ static void launch_pair_T(int R, bool kahan, dim3 grid, hipStream_t st, const Pa
 // workgroup), symmetric scheme (FP32 only) one workgroup per item.
 template <typename T>
 static void launch_pair(int d, int R, bool kahan, dim3 grid, hipStream_t st, const PairItem* items,
-                        int n, const SysDev* sys, const T* Ys, int64_t P, double* Bp, float* Bpj, bool sym = false)
+                        int n, const SysDev* sys, const T* Ys, int64_t P, T* Bp, float* Bpj, bool sym = false)
 {
     if constexpr (sizeof(T) == sizeof(float)) {
         if (sym) {
@@ -201,7 +201,7 @@ struct ssm_ctx {
     void* X = nullptr;
     void* Y = nullptr;
     void* Ys = nullptr;
-    double* Bp = nullptr;
+    void* Bp = nullptr;        // i-side partials [max_splits][d][P] in the storage precision
     float* Bpj = nullptr;      // symmetric scheme: j-side partials [nb_max][d][P]
     double* pairsum = nullptr; // [d][P] scaled pair term of the last exact tick (k_combine)
     bool sym = false;          // symmetric pair scheme (FP32 modes)
@@ -492,7 +492,7 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
             if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
         }
         launch_pair<T>(d, c->R, c->prec == SSM_FP32_KAHAN, grid, c->stream, c->dpair + c->pair_off[ph],
-                       (int)np, c->dsys, Ys, c->P, c->Bp, c->Bpj, c->sym);
+                       (int)np, c->dsys, Ys, c->P, (T*)c->Bp, c->Bpj, c->sym);
         HIP_TRY(hipGetLastError());
         if (c->profiling) {
             if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
@@ -513,8 +513,8 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
         }
         const BlkItem* items = c->dblk + c->blk_off[ph];
         if (c->has_pair && run_exact) {
-            SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<D>), dim3((unsigned)(nb * 4)), dim3(64 * kCombineWaves), 0,
-                                                 c->stream, items, c->dsys, c->P, c->Bp, c->Bpj, c->pairsum));
+            SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<T, D>), dim3((unsigned)(nb * 4)), dim3(64 * kCombineWaves), 0,
+                                                 c->stream, items, c->dsys, c->P, (const T*)c->Bp, c->Bpj, c->pairsum));
             HIP_TRY(hipGetLastError());
         }
         const unsigned gb = (unsigned)(nb * c->bm_lanes);
@@ -869,7 +869,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     ALLOC(c->X, field);
     ALLOC(c->Y, field);
     ALLOC(c->Ys, field);
-    ALLOC(c->Bp, c->has_pair ? (size_t)c->max_splits * c->d * c->P * sizeof(double) : 0);
+    ALLOC(c->Bp, c->has_pair ? (size_t)c->max_splits * c->d * c->P * elt(c->prec) : 0);
     ALLOC(c->pairsum, c->has_pair ? (size_t)c->d * c->P * sizeof(double) : 0);
     ALLOC(c->Bpj, (c->has_pair && c->sym) ? (size_t)c->nb_max * c->d * c->P * sizeof(float) : 0);
     ALLOC(c->psumX, 2 * (size_t)(c->d + 1) * c->nblk_tot * sizeof(double));
@@ -1202,7 +1202,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static size_t kernel_ws_bytes(int32_t d, int64_t N, int32_t precision, const KPlan& p)
 {
     return align256(sizeof(SysDev)) + align256(p.items.size() * sizeof(PairItem)) +
-           align256((size_t)d * N * elt(precision)) + align256((size_t)p.isplits * d * N * sizeof(double)) +
+           align256((size_t)d * N * elt(precision)) + align256((size_t)p.isplits * d * N * elt(precision)) +
            align256((size_t)std::max<int64_t>(p.nb, 1) * d * N * sizeof(float));
 }
 
@@ -1240,7 +1240,7 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
     SysDev* dS = (SysDev*)w; w += align256(sizeof(SysDev));
     PairItem* dI = (PairItem*)w; w += align256(plan.items.size() * sizeof(PairItem));
     void* dYs = (void*)w; w += align256((size_t)d * N * elt(precision));
-    double* dBp = (double*)w; w += align256((size_t)plan.isplits * d * N * sizeof(double));
+    void* dBp = (void*)w; w += align256((size_t)plan.isplits * d * N * elt(precision));
     float* dBpj = (float*)w;
     HIP_TRY(hipMemcpyAsync(dS, &S, sizeof(S), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dI, plan.items.data(), plan.items.size() * sizeof(PairItem), hipMemcpyHostToDevice, st));
@@ -1249,14 +1249,19 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
     const dim3 gp((unsigned)(plan.sym ? plan.items.size() : (plan.items.size() + kWaves - 1) / kWaves));
     if (precision == SSM_FP64) {
         hipLaunchKernelGGL(k_scale_copy<double>, g1, dim3(256), 0, st, (const double*)Y, (double*)dYs, n, c);
-        launch_pair<double>(d, kernel_R(d), false, gp, st, dI, (int)plan.items.size(), dS, (const double*)dYs, N, dBp, dBpj);
+        launch_pair<double>(d, kernel_R(d), false, gp, st, dI, (int)plan.items.size(), dS, (const double*)dYs, N, (double*)dBp, dBpj);
     } else {
         hipLaunchKernelGGL(k_scale_copy<float>, g1, dim3(256), 0, st, (const float*)Y, (float*)dYs, n, c);
-        launch_pair<float>(d, kernel_R(d), precision == SSM_FP32_KAHAN, gp, st, dI, (int)plan.items.size(), dS, (const float*)dYs, N, dBp, dBpj, plan.sym);
+        launch_pair<float>(d, kernel_R(d), precision == SSM_FP32_KAHAN, gp, st, dI, (int)plan.items.size(), dS, (const float*)dYs, N, (float*)dBp, dBpj, plan.sym);
     }
     const dim3 gc((unsigned)(4 * ((N + kBlk - 1) / kBlk)));
-    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<D>), gc, dim3(64 * kCombineWaves), 0, st, (const BlkItem*)nullptr, dS,
-                                         N, dBp, dBpj, K));
+    if (precision == SSM_FP64) {
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<double, D>), gc, dim3(64 * kCombineWaves), 0, st,
+                                             (const BlkItem*)nullptr, dS, N, (const double*)dBp, dBpj, K));
+    } else {
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<float, D>), gc, dim3(64 * kCombineWaves), 0, st,
+                                             (const BlkItem*)nullptr, dS, N, (const float*)dBp, dBpj, K));
+    }
     HIP_TRY(hipGetLastError());
     // the host-side plan must outlive the asynchronous copies
     HIP_TRY(hipStreamSynchronize(st));
@@ -1416,15 +1421,22 @@ extern "C" ssm_status ssm_surrogate_samples(ssm_ctx* c, int32_t sys, int64_t n, 
     const int64_t np = c->pair_cnt[0], nb = c->blk_cnt[0];
     const int d = c->d;
     if (c->prec == SSM_FP64) {
-        launch_pair<double>(d, c->R, false, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const double*)c->Ys, c->P, c->Bp, c->Bpj);
+        launch_pair<double>(d, c->R, false, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const double*)c->Ys, c->P, (double*)c->Bp, c->Bpj);
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<double, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const double*)c->Y, c->rff, c->rff_part));
     } else {
-        launch_pair<float>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const float*)c->Ys, c->P, c->Bp, c->Bpj, c->sym);
+        launch_pair<float>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const float*)c->Ys, c->P, (float*)c->Bp, c->Bpj, c->sym);
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<float, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const float*)c->Y, c->rff, c->rff_part));
     }
     HIP_TRY(hipGetLastError());
-    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<D>), dim3((unsigned)(nb * 4)), dim3(64 * kCombineWaves), 0, c->stream,
-                                         c->dblk + c->blk_off[0], c->dsys, c->P, c->Bp, c->Bpj, c->pairsum));
+    if (c->prec == SSM_FP64) {
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<double, D>), dim3((unsigned)(nb * 4)), dim3(64 * kCombineWaves), 0,
+                                             c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const double*)c->Bp,
+                                             c->Bpj, c->pairsum));
+    } else {
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<float, D>), dim3((unsigned)(nb * 4)), dim3(64 * kCombineWaves), 0,
+                                             c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const float*)c->Bp,
+                                             c->Bpj, c->pairsum));
+    }
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_rff_final, dim3((unsigned)c->sys_list_cnt[0], 2 * kRff), dim3(kBlk), 0, c->stream, c->dsys_list + c->sys_list_off[0], c->dsys, c->rff_part, c->mom);
     HIP_TRY(hipGetLastError());

@@ -97,7 +97,7 @@ __device__ __forceinline__ double exp2_fast<double>(double x)
 }
 
 // The partial-sum rows of particle i of system S, in their fixed order:
-// ni i-side rows (doubles, Bp[q][k][P]: the target tile's or group's work
+// ni i-side rows (Bp[q][k][P] in the storage precision: the target tile's or group's work
 // items) then, in the symmetric scheme, nj j-side rows (floats, Bpj[a][k][P]:
 // every earlier group and the particle's own group).
 struct PairRows {
@@ -114,20 +114,20 @@ __device__ __forceinline__ PairRows pair_rows(const SysDev& S, int i)
 
 // Sum, in ascending order, of the rows r = w, w + W, w + 2W, ... (r < ni + nj)
 // of component k at slot; loads are issued four at a time.
-template <int D, int W>
-__device__ __forceinline__ double sum_rows(const double* __restrict__ Bp, const float* __restrict__ Bpj,
+template <int D, int W, typename PT>
+__device__ __forceinline__ double sum_rows(const PT* __restrict__ Bp, const float* __restrict__ Bpj,
                                            PairRows pr, int k, int64_t P, int64_t slot, int w)
 {
     double acc = 0.0;
     int r = w;
     for (; r + 3 * W < pr.ni; r += 4 * W) {
-        double v[4];
+        PT v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) v[u] = Bp[((int64_t)(r + u * W) * D + k) * P + slot];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc += v[u];
+        for (int u = 0; u < 4; ++u) acc += (double)v[u];
     }
-    for (; r < pr.ni; r += W) acc += Bp[((int64_t)r * D + k) * P + slot];
+    for (; r < pr.ni; r += W) acc += (double)Bp[((int64_t)r * D + k) * P + slot];
     int q = r - pr.ni;
     for (; q + 3 * W < pr.nj; q += 4 * W) {
         float v[4];
@@ -150,10 +150,10 @@ __device__ __forceinline__ double sum_rows(const double* __restrict__ Bp, const 
 // ---------------------------------------------------------------------------
 constexpr int kCombineWaves = 4;
 
-template <int D>
+template <typename PT, int D>
 __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(const BlkItem* __restrict__ items,
                                                                const SysDev* __restrict__ sys, int64_t P,
-                                                               const double* __restrict__ Bp,
+                                                               const PT* __restrict__ Bp,
                                                                const float* __restrict__ Bpj,
                                                                double* __restrict__ out)
 {
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(const BlkItem* _
     const int64_t slot = S.off + i;
     const PairRows pr = valid ? pair_rows(S, i) : PairRows{0, 0};
 #pragma unroll
-    for (int k = 0; k < D; ++k) part[wave][k][lane] = sum_rows<D, kCombineWaves>(Bp, Bpj, pr, k, P, slot, wave);
+    for (int k = 0; k < D; ++k) part[wave][k][lane] = sum_rows<D, kCombineWaves, PT>(Bp, Bpj, pr, k, P, slot, wave);
     __syncthreads();
     if (wave == 0 && valid) {
 #pragma unroll
@@ -514,7 +514,7 @@ __global__ void k_tick_advance(int64_t* tick_dev)
 //   acc_k(i) += (Ys_k^j - Ys_k^i) * exp2(-|Ys^j - Ys^i|^2)
 // in T.  KAHAN: plain sums over chunks of kKahanChunk sources, each chunk
 // total added into a (hi, lo) pair with Neumaier's compensated summation.
-// Writes Bp[split][k][slot] (double).
+// Writes Bp[split][k][slot] (in T).
 // ---------------------------------------------------------------------------
 template <typename T, int D, int R>
 __device__ __forceinline__ void pair_block(const T* __restrict__ src, int64_t P, int j0, int j1,
@@ -732,7 +732,7 @@ template <int D, int R, bool KAHAN>
 __global__ __launch_bounds__(64 * kWaves) void k_pair_sym(const PairItem* __restrict__ items,
                                                           const SysDev* __restrict__ sys,
                                                           const float* __restrict__ Ys, int64_t P,
-                                                          double* __restrict__ Bp, float* __restrict__ Bpj)
+                                                          float* __restrict__ Bp, float* __restrict__ Bpj)
 {
     constexpr int stride = kSymLDS / D;  // LDS j-side capacity (sources) per component
     __shared__ float jred[kWaves][kSymLDS];
@@ -805,7 +805,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sym(const PairItem* __rest
         if (!valid[r]) continue;
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            const double v = KAHAN ? (double)hi[r][c] + (double)lo[r][c] : (double)acc[r][c];
+            // the compensated sum hi + lo, rounded once
+            const float v = KAHAN ? (float)((double)hi[r][c] + (double)lo[r][c]) : acc[r][c];
             Bp[((int64_t)it.split * D + c) * P + S.off + i] = v;
         }
     }
@@ -816,7 +817,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair(const PairItem* __restrict
                                                       int n_items,
                                                       const SysDev* __restrict__ sys,
                                                       const T* __restrict__ Ys, int64_t P,
-                                                      double* __restrict__ Bp)
+                                                      T* __restrict__ Bp)
 {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -877,14 +878,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair(const PairItem* __restrict
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int k = 0; k < D; ++k) acc[r][k] = hi[r][k];
-        // the compensation is added in double at the store below
+        // hi + lo is added in double and rounded once to T at the store below
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = it.tgt0 + lane + 64 * r;
             if (!valid[r]) continue;
 #pragma unroll
             for (int k = 0; k < D; ++k)
-                Bp[((int64_t)it.split * D + k) * P + S.off + i] = (double)hi[r][k] + (double)lo[r][k];
+                Bp[((int64_t)it.split * D + k) * P + S.off + i] = (T)((double)hi[r][k] + (double)lo[r][k]);
         }
         return;
     }
@@ -893,7 +894,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair(const PairItem* __restrict
         const int i = it.tgt0 + lane + 64 * r;
         if (!valid[r]) continue;
 #pragma unroll
-        for (int k = 0; k < D; ++k) Bp[((int64_t)it.split * D + k) * P + S.off + i] = (double)acc[r][k];
+        for (int k = 0; k < D; ++k) Bp[((int64_t)it.split * D + k) * P + S.off + i] = acc[r][k];
     }
 }
 
