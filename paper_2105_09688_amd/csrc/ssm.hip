@@ -512,14 +512,20 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
             if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
         }
         const BlkItem* items = c->dblk + c->blk_off[ph];
-        if (c->has_pair && run_exact) {
-            SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<T, D>), dim3((unsigned)(nb * 4)), dim3(64 * kCombineWaves), 0,
-                                                 c->stream, items, c->dsys, c->P, (const T*)c->Bp, c->Bpj, c->pairsum));
-            HIP_TRY(hipGetLastError());
-        }
-        const unsigned gb = (unsigned)(nb * c->bm_lanes);
-#define SSM_BM(LPV) SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_brownian_sum<D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, \
-                                                         items, c->dsys, c->coef, c->P, c->tick, tdev, c->dW))
+        // Brownian sums of the step, and on exact ticks the combine of the pair
+        // partials in the same launch (k_prep)
+        const bool comb = c->has_pair && run_exact;
+        const int ncb = comb ? (int)(nb * 4) : 0;
+        const unsigned gb = (unsigned)(ncb + nb * c->bm_lanes);
+#define SSM_BM(LPV)                                                                                                   \
+    if (comb) {                                                                                                       \
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_prep<T, D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, ncb, items,     \
+                                             c->dsys, c->coef, c->P, (const T*)c->Bp, c->Bpj, c->pairsum, c->tick,   \
+                                             tdev, c->dW));                                                           \
+    } else {                                                                                                          \
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_brownian_sum<D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, items,    \
+                                             c->dsys, c->coef, c->P, c->tick, tdev, c->dW));                          \
+    }
         switch (c->bm_lanes) {
             case 16: SSM_BM(16); break;
             case 8: SSM_BM(8); break;

@@ -151,15 +151,13 @@ __device__ __forceinline__ double sum_rows(const PT* __restrict__ Bp, const floa
 constexpr int kCombineWaves = 4;
 
 template <typename PT, int D>
-__global__ __launch_bounds__(64 * kCombineWaves) void k_combine(const BlkItem* __restrict__ items,
-                                                               const SysDev* __restrict__ sys, int64_t P,
-                                                               const PT* __restrict__ Bp,
-                                                               const float* __restrict__ Bpj,
-                                                               double* __restrict__ out)
+__device__ __forceinline__ void combine_block(int vb, const BlkItem* __restrict__ items,
+                                              const SysDev* __restrict__ sys, int64_t P, const PT* __restrict__ Bp,
+                                              const float* __restrict__ Bpj, double* __restrict__ out,
+                                              double (*part)[D][64])
 {
-    __shared__ double part[kCombineWaves][D][64];
-    const int q4 = blockIdx.x & 3;
-    const BlkItem it = items ? items[blockIdx.x >> 2] : BlkItem{0, (int32_t)(blockIdx.x >> 2)};
+    const int q4 = vb & 3;
+    const BlkItem it = items ? items[vb >> 2] : BlkItem{0, (int32_t)(vb >> 2)};
     const SysDev S = sys[it.sys];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -179,6 +177,17 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(const BlkItem* _
             out[k * P + slot] = t * S.pair_scale;
         }
     }
+}
+
+template <typename PT, int D>
+__global__ __launch_bounds__(64 * kCombineWaves) void k_combine(const BlkItem* __restrict__ items,
+                                                               const SysDev* __restrict__ sys, int64_t P,
+                                                               const PT* __restrict__ Bp,
+                                                               const float* __restrict__ Bpj,
+                                                               double* __restrict__ out)
+{
+    __shared__ double part[kCombineWaves][D][64];
+    combine_block<PT, D>(blockIdx.x, items, sys, P, Bp, Bpj, out, part);
 }
 
 // The tick a per-tick kernel works on: the context's device counter when
@@ -473,14 +482,13 @@ __device__ __forceinline__ void stream_sum(uint64_t seed, uint64_t i, uint64_t e
 // their partial sums are combined by a fixed butterfly.  Block g of the grid
 // handles sub-block g % LP of item g / LP (256 / LP particles).
 template <int D, int LP>
-__global__ __launch_bounds__(kBlk) void k_brownian_sum(const BlkItem* __restrict__ items,
-                                                       const SysDev* __restrict__ sys, Coef cf,
-                                                       int64_t P, int64_t tick_arg,
-                                                       const int64_t* __restrict__ tick_dev,
-                                                       double* __restrict__ dW)
+__device__ __forceinline__ void brownian_block(int vb, const BlkItem* __restrict__ items,
+                                               const SysDev* __restrict__ sys, const Coef& cf, int64_t P,
+                                               int64_t tick_arg, const int64_t* __restrict__ tick_dev,
+                                               double* __restrict__ dW)
 {
-    const BlkItem it = items[blockIdx.x / LP];
-    const int sub = blockIdx.x % LP;
+    const BlkItem it = items[vb / LP];
+    const int sub = vb % LP;
     const SysDev S = sys[it.sys];
     const int q = threadIdx.x % LP;
     const int i = it.blk * kBlk + sub * (kBlk / LP) + threadIdx.x / LP;
@@ -499,6 +507,34 @@ __global__ __launch_bounds__(kBlk) void k_brownian_sum(const BlkItem* __restrict
 #pragma unroll
         for (int k = 0; k < D; ++k) dW[k * P + S.off + i] = cf.sqrt_hf * zs[k];
     }
+}
+
+template <int D, int LP>
+__global__ __launch_bounds__(kBlk) void k_brownian_sum(const BlkItem* __restrict__ items,
+                                                       const SysDev* __restrict__ sys, Coef cf,
+                                                       int64_t P, int64_t tick_arg,
+                                                       const int64_t* __restrict__ tick_dev,
+                                                       double* __restrict__ dW)
+{
+    brownian_block<D, LP>(blockIdx.x, items, sys, cf, P, tick_arg, tick_dev, dW);
+}
+
+// k_prep: the combine (first n_combine blocks) and the Brownian sums (the
+// rest) of an exact tick in one launch; the two are independent, so the
+// HBM-bound combine runs beside the FP64-bound Philox/Box-Muller work.
+template <typename PT, int D, int LP>
+__global__ __launch_bounds__(kBlk) void k_prep(int n_combine, const BlkItem* __restrict__ items,
+                                               const SysDev* __restrict__ sys, Coef cf, int64_t P,
+                                               const PT* __restrict__ Bp, const float* __restrict__ Bpj,
+                                               double* __restrict__ pairsum, int64_t tick_arg,
+                                               const int64_t* __restrict__ tick_dev, double* __restrict__ dW)
+{
+    static_assert(64 * kCombineWaves == kBlk, "one block shape for both parts");
+    __shared__ double part[kCombineWaves][D][64];
+    if ((int)blockIdx.x < n_combine)
+        combine_block<PT, D>(blockIdx.x, items, sys, P, Bp, Bpj, pairsum, part);
+    else
+        brownian_block<D, LP>(blockIdx.x - n_combine, items, sys, cf, P, tick_arg, tick_dev, dW);
 }
 
 // Advance the context's device tick counter (last launch of every tick).
