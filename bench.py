@@ -23,6 +23,9 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published)
 PEAK_FP64_TFLOPS = 78.6
 
 
+PROFILE_EVERY = 8  # ticks between timed pair launches in the headline run
+
+
 def flops_per_pair(d: int) -> int:
     """Algorithmic work of one interaction pair: d subtractions, d squares and
     d-1 adds, one scale, one exp, d multiplies and d accumulates."""
@@ -355,7 +358,9 @@ def main():
         s.sync()
     s = SSM(w, precision=args.precision, stream=stream, **tiling)
     s.sync()
-    s.profile(True)
+    # HIP events around the pair and update launches of every PROFILE_EVERY-th
+    # tick of the timed run (an event pair on every tick costs ~4 % of the step)
+    s.profile(True, every=PROFILE_EVERY)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
@@ -405,6 +410,7 @@ def main():
             "pairs_per_launch": pairs,
             "avg_launch_ms": pair_avg_s * 1e3,
             "launches": info["pair_launches"],
+            "launches_timed_every": PROFILE_EVERY,
         },
         "update_kernel_avg_ms": info["update_ms"] / max(1, info["update_launches"]),
         "tiling": {"targets_per_lane": info["targets_per_lane"], "sources_per_item": info["sources_per_item"],

@@ -130,7 +130,7 @@ typedef struct {
     int32_t pad;
     int64_t device_bytes;    /* device memory the context holds */
     /* Kernel timing (ssm_profile enabled): HIP events recorded on the context's
-     * stream around each launch since the last ssm_profile(ctx, 1). */
+     * stream around the launches of the sampled ticks since the last ssm_profile. */
     int64_t pair_launches;   /* launches of the pairwise kernel */
     double pair_ms;          /* their summed duration, milliseconds */
     int64_t update_launches; /* launches of the per-particle update (+ implicit solve) kernels */
@@ -205,10 +205,13 @@ ssm_status ssm_rmse(ssm_ctx *a, ssm_ctx *b, double *per_sys, double *rmse);
  * both contexts. */
 ssm_status ssm_sqdiff(ssm_ctx *a, int32_t sys_a, ssm_ctx *b, int32_t sys_b, double *out);
 
-/* Enable (nonzero) or disable per-kernel timing with HIP events on the
- * context's stream; enabling resets the accumulated times.  Timing adds one
- * event record before and after each kernel launch. */
-ssm_status ssm_profile(ssm_ctx *ctx, int32_t enable);
+/* Per-kernel timing with HIP events on the context's stream: every = 0
+ * disables it; every = k >= 1 records one event before and one after the
+ * pairwise launch and the update launches of each tick with tick % k == 0
+ * (k = 1: every tick).  Enabling resets the accumulated times.  Each event
+ * pair costs a few microseconds of stream time, so a stride k > 1 keeps a
+ * timed run close to an untimed one while still averaging over the whole run. */
+ssm_status ssm_profile(ssm_ctx *ctx, int32_t every);
 
 /* Counters, tiling and (if enabled) kernel times of a context.  Synchronizes. */
 ssm_status ssm_info(ssm_ctx *ctx, ssm_info_t *out);

@@ -251,6 +251,7 @@ struct ssm_ctx {
     std::vector<hipGraphExec_t> phase_graph;
     // kernel timing: event pairs recorded around launches while profiling
     bool profiling = false;
+    int32_t profile_every = 1;     // bracket the launches of ticks with tick % profile_every == 0
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pair, ev_update;
     std::vector<hipEvent_t> ev_pool;
 };
@@ -483,10 +484,11 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
     const bool check = surr_on && (c->tick % c->surr_check_every == 0);
     const bool run_exact = !surr_on || check || c->surr_fallback;
     const bool run_surr = surr_on && (check || !c->surr_fallback);
+    const bool prof = c->profiling && c->tick % c->profile_every == 0;
     if (c->has_pair && np > 0 && run_exact) {
         dim3 grid((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves));
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (c->profiling) {
+        if (prof) {
             e0 = take_event(c);
             e1 = take_event(c);
             if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
@@ -494,7 +496,7 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
         launch_pair<T>(d, c->R, c->prec == SSM_FP32_KAHAN, grid, c->stream, c->dpair + c->pair_off[ph],
                        (int)np, c->dsys, Ys, c->P, (T*)c->Bp, c->Bpj, c->sym);
         HIP_TRY(hipGetLastError());
-        if (c->profiling) {
+        if (prof) {
             if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
             c->ev_pair.push_back({e0, e1});
         }
@@ -506,7 +508,7 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
     const int use_surr = (run_surr && !check) ? 1 : 0;
     if (nb > 0) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (c->profiling) {
+        if (prof) {
             e0 = take_event(c);
             e1 = take_event(c);
             if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
@@ -551,7 +553,7 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
                                                  c->psumX, c->psumY, c->nblk_tot, c->dflags, c->dnmax));
             HIP_TRY(hipGetLastError());
         }
-        if (c->profiling) {
+        if (prof) {
             if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
             c->ev_update.push_back({e0, e1});
         }
@@ -1167,13 +1169,15 @@ extern "C" ssm_status ssm_info(ssm_ctx* c, ssm_info_t* out)
     return SSM_OK;
 }
 
-extern "C" ssm_status ssm_profile(ssm_ctx* c, int32_t enable)
+extern "C" ssm_status ssm_profile(ssm_ctx* c, int32_t every)
 {
     if (!c) return fail(SSM_ERR_INVALID, "ctx is NULL");
+    if (every < 0) return fail(SSM_ERR_INVALID, "every must be >= 0");
     HIP_TRY(hipStreamSynchronize(c->stream));
     recycle_events(c, c->ev_pair);
     recycle_events(c, c->ev_update);
-    c->profiling = enable != 0;
+    c->profiling = every > 0;
+    c->profile_every = every > 0 ? every : 1;
     return SSM_OK;
 }
 

@@ -152,8 +152,9 @@ class SSM:
         check(_lib.load().ssm_surrogate_samples(self._h, sys, n, seed, U.data_ptr(), T.data_ptr()))
         return U, T
 
-    def profile(self, enable: bool = True) -> None:
-        check(_lib.load().ssm_profile(self._h, 1 if enable else 0))
+    def profile(self, enable: bool = True, every: int = 1) -> None:
+        """Time the pair and update launches of every `every`-th tick with HIP events."""
+        check(_lib.load().ssm_profile(self._h, int(every) if enable else 0))
 
     def info(self) -> dict:
         i = _lib.Info()

@@ -413,3 +413,23 @@ def test_autotuner_choice_is_valid_and_cached(torch_cuda, tmp_path, monkeypatch)
               sources_per_item=choice["sources_per_item"], pair_scheme=choice["pair_scheme"]) as s:
         s.step(8)
         assert _err(s.state(0), ref) <= FP32_TOL
+
+
+def test_profile_stride_times_the_sampled_ticks_only(torch_cuda):
+    """ssm_profile(every = k): events around the launches of ticks with
+    tick % k == 0; every = 0 switches timing off; the run itself is unchanged."""
+    from paper_2105_09688_amd import SSMError
+    w = W.small_parity(n_ens=1, N=700)
+    with _ssm(w, "fp32_kahan") as a, _ssm(w, "fp32_kahan") as b:
+        a.profile(True, every=4)
+        a.step(16)
+        b.step(16)
+        ia = a.info()
+        assert ia["pair_launches"] == 4 and ia["update_launches"] == 4
+        assert ia["pair_ms"] > 0.0
+        assert np.array_equal(a.state(0), b.state(0))
+        a.profile(False)
+        a.step(4)
+        assert a.info()["pair_launches"] == 0
+        with pytest.raises(SSMError):
+            a.profile(True, every=-1)
