@@ -415,6 +415,26 @@ static void build_pair_items(const ssm_ctx* c, const std::vector<int>& systems, 
 // SIMD) over the given sizes; at least 512 (ordered) / 256 (symmetric)
 // sources, a multiple of 64 / 16.  (Measured on MI355X: shorter items beat
 // longer ones down to this size for d = 1..3.)
+// Default targets per lane: 4 for d = 1, 2 for d >= 2 (measured fastest at
+// full size), halved while the largest work item (a symmetric group's
+// diagonal item, (256 R)^2 / 2 pair evaluations; an ordered item, 64 R x 512)
+// exceeds the average work of a resident workgroup slot (about 1024 of them),
+// so that small runs spread over the chip instead of a few long items.
+static int default_R(int d, const std::vector<int64_t>& Ns, bool sym)
+{
+    int R = d == 1 ? 4 : 2;
+    double total = 0.0;
+    for (int64_t N : Ns) total += (double)N * (double)N;
+    const double per_slot = (sym ? 0.5 : 1.0) * total / 1024.0;
+    while (R > 1) {
+        const double g = sym ? 256.0 * R : 64.0 * R;
+        const double item = sym ? 0.5 * g * g : g * 512.0;
+        if (item <= per_slot) break;
+        R /= 2;
+    }
+    return R;
+}
+
 static int64_t default_L(const std::vector<int64_t>& Ns, int R, bool sym, int d)
 {
     const int64_t tile = 64 * (int64_t)R;
@@ -772,11 +792,13 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     is_int_ratio(cfg->T, h_min, &c->ticks_total);
 
     // pair tiling: R targets per lane, L sources per item, scheme
-    // default: 4 targets per lane for d = 1, 2 for d >= 2 (fewer live registers
-    // per pair, measured faster on MI355X for both schemes)
-    c->R = cfg->targets_per_lane > 0 ? cfg->targets_per_lane : (c->d == 1 ? 4 : 2);
     if (cfg->pair_scheme == 2 && c->prec == SSM_FP64) { free_ctx(c); return fail(SSM_ERR_INVALID, "the symmetric pair scheme is FP32 only"); }
     c->sym = c->prec != SSM_FP64 && cfg->pair_scheme != 1;
+    {
+        std::vector<int64_t> Ns;
+        for (auto& S : c->sys) Ns.push_back(S.N);
+        c->R = cfg->targets_per_lane > 0 ? cfg->targets_per_lane : default_R(c->d, Ns, c->sym);
+    }
     if (c->sym && (int64_t)64 * c->R * kWaves * c->d > kSymLDS) {
         // a target group's j-side sums must fit the kernel's LDS buffer
         if (cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "symmetric scheme: targets_per_lane too large for this d (64 x R x 4 x d must be <= 2048)"); }
@@ -1186,12 +1208,11 @@ extern "C" void ssm_destroy(ssm_ctx* c) { free_ctx(c); }
 // ---------------------------------------------------------------------------
 // kernel-level entry points
 // ---------------------------------------------------------------------------
-// Targets per lane of the kernel-level pair sum (the context default).
-static int kernel_R(int32_t d) { return d == 1 ? 4 : 2; }
 
 // Plan of the kernel-level pair sum over one system of N particles.
 struct KPlan {
     bool sym;
+    int R;
     int64_t L, isplits, nb;
     std::vector<PairItem> items;
 };
@@ -1200,9 +1221,11 @@ static KPlan kernel_plan(int32_t d, int64_t N, int32_t precision)
 {
     KPlan p{};
     p.sym = precision != SSM_FP64;
-    p.L = default_L(std::vector<int64_t>{N}, kernel_R(d), p.sym, d);
+    p.R = default_R(d, std::vector<int64_t>{N}, p.sym);
+    if (p.sym && (int64_t)64 * p.R * kWaves * d > kSymLDS) p.sym = false;
+    p.L = default_L(std::vector<int64_t>{N}, p.R, p.sym, d);
     std::vector<std::pair<int64_t, PairItem>> tmp;
-    p.isplits = plan_system(0, N, kernel_R(d), p.sym, p.L, tmp, &p.nb);
+    p.isplits = plan_system(0, N, p.R, p.sym, p.L, tmp, &p.nb);
     order_items(tmp, p.items);
     return p;
 }
@@ -1242,7 +1265,7 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
     S.r = 1;
     S.nblk = (int32_t)((N + kBlk - 1) / kBlk);
     S.splits = (int32_t)plan.isplits;
-    S.sym_B = plan.sym ? 64 * kernel_R(d) * kWaves : 0;
+    S.sym_B = plan.sym ? 64 * plan.R * kWaves : 0;
     S.sym_L = plan.sym ? (int32_t)plan.L : 0;
     const double c = std::sqrt(kLog2e / (2.0 * ell * ell));
     S.pair_scale = 1.0 / ((double)N * c);  // unscaled sums of the scaled coordinates -> (1/N) sum
@@ -1259,10 +1282,10 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
     const dim3 gp((unsigned)(plan.sym ? plan.items.size() : (plan.items.size() + kWaves - 1) / kWaves));
     if (precision == SSM_FP64) {
         hipLaunchKernelGGL(k_scale_copy<double>, g1, dim3(256), 0, st, (const double*)Y, (double*)dYs, n, c);
-        launch_pair<double>(d, kernel_R(d), false, gp, st, dI, (int)plan.items.size(), dS, (const double*)dYs, N, (double*)dBp, dBpj);
+        launch_pair<double>(d, plan.R, false, gp, st, dI, (int)plan.items.size(), dS, (const double*)dYs, N, (double*)dBp, dBpj);
     } else {
         hipLaunchKernelGGL(k_scale_copy<float>, g1, dim3(256), 0, st, (const float*)Y, (float*)dYs, n, c);
-        launch_pair<float>(d, kernel_R(d), precision == SSM_FP32_KAHAN, gp, st, dI, (int)plan.items.size(), dS, (const float*)dYs, N, (float*)dBp, dBpj, plan.sym);
+        launch_pair<float>(d, plan.R, precision == SSM_FP32_KAHAN, gp, st, dI, (int)plan.items.size(), dS, (const float*)dYs, N, (float*)dBp, dBpj, plan.sym);
     }
     const dim3 gc((unsigned)(4 * ((N + kBlk - 1) / kBlk)));
     if (precision == SSM_FP64) {
