@@ -319,8 +319,12 @@ def strong_error(X: np.ndarray, X_ref: np.ndarray) -> float:
 
 
 def weak_error(X: np.ndarray, X_ref: np.ndarray) -> float:
-    """epsilon_1 of Section 3: |(1/N) sum_j (X^j - X_ref^j)|_2."""
-    D = np.atleast_2d(X) - np.atleast_2d(X_ref)
+    """epsilon_1 of Section 3: |(1/N) sum_j (X^j - X_ref^j)|_2; arrays [d][N] or
+    lists of them (the mean then runs over the particles of all systems)."""
+    if isinstance(X, (list, tuple)):
+        D = np.concatenate([np.atleast_2d(a) - np.atleast_2d(b) for a, b in zip(X, X_ref)], axis=1)
+    else:
+        D = np.atleast_2d(X) - np.atleast_2d(X_ref)
     return float(np.linalg.norm(D.mean(axis=1)))
 
 

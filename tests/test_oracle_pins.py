@@ -276,6 +276,32 @@ def test_ou_mean_recursion_pathwise(oracle_mod):
         assert X.mean() == pytest.approx(mean, rel=1e-12, abs=1e-13)
 
 
+def test_weak_error_over_ensembles_follows_the_ou_mean_recursion(oracle_mod):
+    """epsilon_1 (Section 3) of runs at h and at a finer h_ref on the same paths,
+    over several ensembles: with v = rho x, b = lam E[X], sigma = eta the
+    particle mean follows mean_{n+1} = (1 + h lam)/(1 - h rho) mean_n + eta mean_i dW_i
+    exactly, so the weak error is |average over ensembles of the two mean
+    paths' difference| (equal N), computed here from the recursion alone."""
+    rho, lam, eta, N, n_ens, T = -0.8, 0.6, 0.4, 32, 3, 2.0 ** -3
+    hf = 2.0 ** -7
+    base = W.ou(rho=rho, lam=lam, eta=eta, x0=1.0, x0_std=0.3, N=N, h=2.0 ** -4, T=T, n_ens=n_ens, h_fine=hf)
+
+    def mean_path(h, e):
+        r = int(round(h / hf))
+        mean = oracle_mod.init_state(base, e, N).mean()
+        for n in range(int(round(T / h))):
+            dW = [math.sqrt(hf) * sum(oracle_mod.stream_normal(0, i, e, n * r + m) for m in range(r)) for i in range(N)]
+            mean = (1 + h * lam) / (1 - h * rho) * mean + eta * float(np.mean(dW))
+        return mean
+
+    X = oracle_mod.run(base)
+    X_ref = oracle_mod.run(W.with_h(base, hf))
+    expect = abs(np.mean([mean_path(2.0 ** -4, e) - mean_path(hf, e) for e in range(n_ens)]))
+    assert oracle_mod.weak_error(X, X_ref) == pytest.approx(expect, rel=1e-9, abs=1e-14)
+    assert oracle_mod.weak_error(X[0], X_ref[0]) == pytest.approx(abs(mean_path(2.0 ** -4, 0) - mean_path(hf, 0)),
+                                                                  rel=1e-9, abs=1e-14)
+
+
 def test_ou_moments_closed_form(oracle_mod):
     """E[X_t] = x0 e^{(rho+lam)t},  E[X_t^2] = x0^2 e^{2(rho+lam)t} + eta^2/(2 rho)(e^{2 rho t} - 1)
     (Section 3.4.1), deterministic x0; tolerance O(h) plus 5 standard errors."""
