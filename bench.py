@@ -54,6 +54,18 @@ def recorded_traffic(key: str):
     return rec["hbm_bytes_per_launch"]
 
 
+def oracle_time_runs(ws, particle_steps_total):
+    """CPU baseline of a study: the FP64 oracle timed on whole runs of the same
+    workloads on this host's cores (results unused)."""
+    import oracle
+    t0 = time.perf_counter()
+    for w in ws:
+        oracle.run(w)
+    dt = time.perf_counter() - t0
+    return {"seconds": dt, "value": particle_steps_total / dt, "unit": "particle-steps/s",
+            "cores": oracle.num_threads(), "kind": "oracle"}
+
+
 def cpu_baseline(w, budget_s: float):
     """The FP64 oracle on this host's cores, on a bounded sample of the same
     workload: whole time steps of the same system, as many as fit in the budget."""
@@ -156,6 +168,70 @@ def study_small(args, stream):
             s.close()
             out[f"{prec} {'graphs' if graphs else 'eager'}"] = {
                 "seconds": dt, "particle_steps_per_s": 10 * 1000 * n / dt, "us_per_step": dt / n * 1e6}
+    return out
+
+
+def _rmse(X, X_ref):
+    """Strong error of Section 3 over the particles of all listed systems."""
+    import numpy as np
+    num = sum(float(np.sum((a - b) ** 2)) for a, b in zip(X, X_ref))
+    return math.sqrt(num / sum(a.shape[-1] for a in X))
+
+
+def _weak(X, X_ref):
+    """Weak error of Section 3: norm of the mean difference over all particles."""
+    import numpy as np
+    D = np.concatenate([a - b for a, b in zip(X, X_ref)], axis=1)
+    return float(np.linalg.norm(D.mean(axis=1)))
+
+
+def _slope(hs, errs):
+    import numpy as np
+    return float(np.polyfit(np.log2(hs), np.log2(errs), 1)[0])
+
+
+def study_families(args, stream):
+    """The paper's own coefficient families (Section 3): stochastic
+    Ginzburg-Landau in both SSM splittings (Section 3.1) and polynomial drift
+    (Section 3.3), N = 1000 x 10 ensembles, h = 2^-4 .. 2^-10 in one context,
+    against a 2^-14 proxy on the same paths: strong and weak errors and their
+    rates, and the GPU time; the oracle's time for the same runs is the CPU
+    baseline.  (Parity of these runs with the oracle: tests/test_gpu_families.py.)"""
+    from paper_2105_09688_amd import workloads as W
+    from paper_2105_09688_amd.ssm import SSM
+    prec = args.precision
+    levels = (4, 5, 6, 7, 8, 9, 10)
+    n_ens, N, hf = 10, 1000, 2.0 ** -14
+    fams = {"ginzburg_landau_v1": lambda **k: W.ginzburg_landau(1, **k),
+            "ginzburg_landau_v2": lambda **k: W.ginzburg_landau(2, **k),
+            "polynomial_drift": lambda **k: W.polynomial_drift(**k)}
+    out = {"study": "families", "workload": f"N={N} x {n_ens} ensembles, h=2^-4..2^-10, proxy 2^-14, T=1, {prec}"}
+    for name, mk in fams.items():
+        w = mk(n_ens=n_ens, N=N, h_fine=hf, levels=levels)
+        ref_w = mk(n_ens=n_ens, N=N, h=hf, h_fine=hf)
+        s, dt, n = timed_run(SSM, w, prec, stream, profile=False)
+        r, dt_ref, n_ref = timed_run(SSM, ref_w, prec, stream, profile=False)
+        g, g_ref = s.states(), r.states()
+        s.close()
+        r.close()
+        res = {"levels": {}}
+        hs, st, wk = [], [], []
+        for li, l in enumerate(levels):
+            sel = [g[e * len(levels) + li] for e in range(n_ens)]
+            sg, wg = _rmse(sel, g_ref), _weak(sel, g_ref)
+            res["levels"][f"2^-{l}"] = {"rmse": sg, "weak": wg}
+            hs.append(2.0 ** -l)
+            st.append(sg)
+            wk.append(wg)
+        res["strong_slope"] = _slope(hs, st)
+        res["weak_slope"] = _slope(hs, wk)
+        ps = particle_steps(w, n) + particle_steps(ref_w, n_ref)
+        res["gpu_seconds"] = dt + dt_ref
+        res["gpu_particle_steps_per_s"] = ps / (dt + dt_ref)
+        res["cpu_baseline"] = oracle_time_runs([w, ref_w], ps)
+        out[name] = res
+        print(f"[families] {name}: strong slope {res['strong_slope']:.3f}, weak slope {res['weak_slope']:.3f}, "
+              f"gpu {dt + dt_ref:.2f} s, oracle {res['cpu_baseline']['seconds']:.2f} s", file=sys.stderr, flush=True)
     return out
 
 
@@ -324,7 +400,7 @@ def main():
     ap.add_argument("--precision", default="fp32_kahan", choices=["fp64", "fp32", "fp32_kahan"])
     ap.add_argument("--N", type=int, default=0)
     ap.add_argument("--train-steps", type=int, default=32000)
-    ap.add_argument("--study", choices=["none", "precision", "batched", "surrogate", "small"], default="none",
+    ap.add_argument("--study", choices=["none", "precision", "batched", "surrogate", "small", "families"], default="none",
                     help="run a study of another workload instead of the throughput line")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -350,7 +426,7 @@ def main():
     if args.study != "none":
         stream = torch.cuda.Stream()
         fn = {"precision": study_precision, "batched": study_batched, "surrogate": study_surrogate,
-              "small": study_small}[args.study]
+              "small": study_small, "families": study_families}[args.study]
         print(json.dumps(fn(args, stream)), flush=True)
         return
     w = W.single_gpu_d1(N=args.N or 2 ** 16)

@@ -115,6 +115,44 @@ def ou(rho: float = -1.0, lam: float = 0.5, eta: float = 0.3, x0: float = 1.0, x
     )
 
 
+def ginzburg_landau(version: int = 1, n_ens: int = 10, N: int = 1000, h: float = 2.0 ** -8,
+                    h_fine: float = 2.0 ** -12, sigma_p: float = 1.5, c: float = 0.5, x0: float = 1.0,
+                    levels=None) -> dict:
+    """Stochastic Ginzburg-Landau MV-SDE of Section 3.1,
+    dX = ((s'^2 / 2) X - X^3 + c E[X]) dt + s' X dW, X_0 = x0, with s' = 1.5,
+    c = 0.5, x0 = 1, T = 1, N = 1000.  SSM version 1 puts c E[X] in b (at
+    mu_Y), version 2 in v (at mu_X, the implicit step's measure).  With
+    `levels`, one system per (ensemble, step 2^-l) on the fine grid."""
+    if version not in (1, 2):
+        raise ValueError("version is 1 or 2")
+    systems = ([(N, e, h) for e in range(n_ens)] if levels is None
+               else [(N, e, 2.0 ** -l) for e in range(n_ens) for l in levels])
+    return dict(
+        d=1, T=1.0, seed=0, h_fine=h_fine, systems=systems,
+        v=dict(rho=0.0, a=1.0, kappa=0.0, lam=c if version == 2 else 0.0),
+        b=dict(c0=sigma_p ** 2 / 2, lam=c if version == 1 else 0.0, g=0.0, ell=1.0),
+        sigma=dict(s0=[0.0], s1=[sigma_p], s2=[0.0]),
+        x0_mean=[x0], x0_std=[0.0],
+    )
+
+
+def polynomial_drift(gamma: float = -1.0, n_ens: int = 10, N: int = 1000, h: float = 2.0 ** -8,
+                     h_fine: float = 2.0 ** -12, x0: float = 1.0, T: float = 1.0, levels=None) -> dict:
+    """Polynomial-drift MV-SDE of Section 3.3,
+    dX = (gamma X + E[X] - X E[|X|^2]) dt + X dW, with v = gamma x - x E|X|^2
+    (at mu_X), b = E[X] (at mu_Y), sigma = x; gamma = -1, N = 1000.  The paper
+    gives T = 1 and T = 2 in two places and no x0: T = 1 and x0 = 1 here."""
+    systems = ([(N, e, h) for e in range(n_ens)] if levels is None
+               else [(N, e, 2.0 ** -l) for e in range(n_ens) for l in levels])
+    return dict(
+        d=1, T=T, seed=0, h_fine=h_fine, systems=systems,
+        v=dict(rho=gamma, a=0.0, kappa=1.0, lam=0.0),
+        b=dict(c0=0.0, lam=1.0, g=0.0, ell=1.0),
+        sigma=dict(s0=[0.0], s1=[1.0], s2=[0.0]),
+        x0_mean=[x0], x0_std=[0.0],
+    )
+
+
 def with_systems(w: dict, systems) -> dict:
     w = copy.deepcopy(w)
     w["systems"] = [tuple(s) for s in systems]
