@@ -171,6 +171,26 @@ def study_small(args, stream):
     return out
 
 
+def stability_beta(h, L_v, L_b, L_bt, L_s, L_st=0.0, L_vt=0.0):
+    """beta of Theorem 2.9: sup_i E|X_n - Z_n|^2 <= (1 + beta h)^n sup_i E|X_0 - Z_0|^2,
+    from the one-sided Lipschitz constant L_v of v, L_vt of its measure part,
+    and the squared-Lipschitz constants of b and sigma in x (L_b, L_s) and in
+    the measure (L_bt, L_st)."""
+    den = 1.0 - h * (2.0 * L_v + 1.0)
+    if not den > 0.0:
+        raise ValueError("Theorem 2.9 needs 1 - h (2 L_v + 1) > 0")
+    A = 2.0 * math.sqrt(L_b) + 2.0 * math.sqrt(L_bt) + L_s + L_st
+    B = L_b + L_bt
+    num = (2.0 * L_v + A + 1.0 + L_vt) + h * (L_vt * A + B) + h * h * B * L_vt
+    return num / den
+
+
+def gl_stability_beta(gamma, h):
+    """beta of the Section 3.4.2 example: L_v = -5/2 - gamma, L_bt = L_s = 1,
+    L_b = gamma^2, L_vt = L_st = 0."""
+    return stability_beta(h, L_v=-2.5 - gamma, L_b=gamma * gamma, L_bt=1.0, L_s=1.0)
+
+
 def _rmse(X, X_ref):
     """Strong error of Section 3 over the particles of all listed systems."""
     import numpy as np
@@ -232,6 +252,79 @@ def study_families(args, stream):
         out[name] = res
         print(f"[families] {name}: strong slope {res['strong_slope']:.3f}, weak slope {res['weak_slope']:.3f}, "
               f"gpu {dt + dt_ref:.2f} s, oracle {res['cpu_baseline']['seconds']:.2f} s", file=sys.stderr, flush=True)
+    return out
+
+
+def _series(SSM, w, prec, stream, times, wz=None):
+    """E|X_t|^2 (and E|X_t - Z_t|^2 with a second context on the same paths)
+    at the sampled times, averaged over particles and systems."""
+    h = w["systems"][0][2]
+    N = sum(sy[0] for sy in w["systems"])
+    out = {"t": [], "m2": [], "msd": []}
+    with SSM(w, precision=prec, stream=stream) as a:
+        b = SSM(wz, precision=prec, stream=stream) if wz is not None else None
+        try:
+            tick = 0
+            for t in times:
+                n = int(round(t / h))
+                if n > tick:
+                    a.step(n - tick)
+                    if b is not None:
+                        b.step(n - tick)
+                    tick = n
+                m2 = 0.0
+                for k, sy in enumerate(w["systems"]):
+                    mean, var = a.moments(k)
+                    m2 += sy[0] * float(sum(var) + sum(x * x for x in mean))
+                out["t"].append(t)
+                out["m2"].append(m2 / N)
+                if b is not None:
+                    out["msd"].append(sum(a.sqdiff(k, b, k) for k in range(len(w["systems"]))) / N)
+        finally:
+            if b is not None:
+                b.close()
+    if wz is None:
+        del out["msd"]
+    return out
+
+
+def study_stability(args, stream):
+    """Mean-square stability of the SSM (Theorem 2.9) on the example of
+    Section 3.4.2, N = 1000 x 10 ensembles, FP64: (a) E|X_t|^2 for
+    h = 1e-2, 1e-3, 1e-4 (gamma = 0, T = 3); (b) E|X_t - Z_t|^2 for X_0 = 1,
+    Z_0 = 5, 10, 100 on the same paths (h = 1e-2) beside the bound
+    (1 + beta h)^n |X_0 - Z_0|^2; (c) E|X_t|^2 for gamma = -12, 0, 12 at
+    h = 0.1 to T = 15; (d) 1 + beta(gamma) h and E|X_T|^2 over gamma in
+    [-12, 12] at h = 0.1, T = 3."""
+    from paper_2105_09688_amd import workloads as W
+    from paper_2105_09688_amd.ssm import SSM
+    prec = "fp64" if args.precision == "fp32_kahan" else args.precision
+    t0 = time.perf_counter()
+    out = {"study": "stability", "workload": "Section 3.4.2 example, N=1000 x 10 ensembles, " + prec}
+    ts3 = [0.25 * k for k in range(13)]
+    out["a_h_sweep"] = {f"h={h:g}": _series(SSM, W.gl_stability(h=h), prec, stream, ts3)
+                        for h in (1e-2, 1e-3, 1e-4)}
+    h = 1e-2
+    beta = gl_stability_beta(0.0, h)
+    out["b_contraction"] = {"beta": beta, "one_plus_beta_h": 1 + beta * h}
+    for z0 in (5.0, 10.0, 100.0):
+        ser = _series(SSM, W.gl_stability(h=h), prec, stream, ts3, wz=W.gl_stability(h=h, x0=z0))
+        ser["bound"] = [(1 + beta * h) ** int(round(t / h)) * (z0 - 1.0) ** 2 for t in ts3]
+        out["b_contraction"][f"Z0={z0:g}"] = ser
+    ts15 = [1.0 * k for k in range(16)]
+    out["c_gamma_long"] = {f"gamma={g:g}": _series(SSM, W.gl_stability(gamma=g, h=0.1, T=15.0, allow_unstable_h=True),
+                                                   prec, stream, ts15) for g in (-12.0, 0.0, 12.0)}
+    d = {"gamma": [], "one_plus_beta_h": [], "m2_T": []}
+    for g in range(-12, 13):
+        ser = _series(SSM, W.gl_stability(gamma=float(g), h=0.1, allow_unstable_h=True), prec, stream, [3.0])
+        d["gamma"].append(g)
+        try:
+            d["one_plus_beta_h"].append(1 + gl_stability_beta(float(g), 0.1) * 0.1)
+        except ValueError:  # outside the step condition: no guarantee
+            d["one_plus_beta_h"].append(None)
+        d["m2_T"].append(ser["m2"][-1])
+    out["d_gamma_sweep"] = d
+    out["seconds"] = time.perf_counter() - t0
     return out
 
 
@@ -400,7 +493,8 @@ def main():
     ap.add_argument("--precision", default="fp32_kahan", choices=["fp64", "fp32", "fp32_kahan"])
     ap.add_argument("--N", type=int, default=0)
     ap.add_argument("--train-steps", type=int, default=32000)
-    ap.add_argument("--study", choices=["none", "precision", "batched", "surrogate", "small", "families"], default="none",
+    ap.add_argument("--study", choices=["none", "precision", "batched", "surrogate", "small", "families", "stability"],
+                    default="none",
                     help="run a study of another workload instead of the throughput line")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -426,7 +520,7 @@ def main():
     if args.study != "none":
         stream = torch.cuda.Stream()
         fn = {"precision": study_precision, "batched": study_batched, "surrogate": study_surrogate,
-              "small": study_small, "families": study_families}[args.study]
+              "small": study_small, "families": study_families, "stability": study_stability}[args.study]
         print(json.dumps(fn(args, stream)), flush=True)
         return
     w = W.single_gpu_d1(N=args.N or 2 ** 16)

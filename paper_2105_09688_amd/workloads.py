@@ -153,6 +153,24 @@ def polynomial_drift(gamma: float = -1.0, n_ens: int = 10, N: int = 1000, h: flo
     )
 
 
+def gl_stability(gamma: float = 0.0, x0: float = 1.0, h: float = 1e-2, T: float = 3.0, N: int = 1000,
+                 n_ens: int = 10, allow_unstable_h: bool = False) -> dict:
+    """Stability example of Section 3.4.2: dX = (-5/2 X - 1/4 X^3 + E[X]) dt + X dW,
+    X_0 = x0, split as v = -5/2 x - 1/4 x^3 - gamma x, b = E[X] + gamma x,
+    sigma = x (gamma moves slope between v and b); N = 1000.  The Brownian
+    increments are drawn at the step itself (h_fine = h).  allow_unstable_h
+    lifts the step-size condition of Theorem 2.6 for steps the study takes on
+    purpose (the implicit step stays uniquely solvable: 1 - h rho > 0)."""
+    return dict(
+        d=1, T=T, seed=0, h_fine=h, systems=[(N, e, h) for e in range(n_ens)],
+        v=dict(rho=-2.5 - gamma, a=0.25, kappa=0.0, lam=0.0),
+        b=dict(c0=gamma, lam=1.0, g=0.0, ell=1.0),
+        sigma=dict(s0=[0.0], s1=[1.0], s2=[0.0]),
+        x0_mean=[x0], x0_std=[0.0],
+        allow_unstable_h=allow_unstable_h,
+    )
+
+
 def with_systems(w: dict, systems) -> dict:
     w = copy.deepcopy(w)
     w["systems"] = [tuple(s) for s in systems]

@@ -85,3 +85,40 @@ def test_family_rates_match_oracle(torch_cuda, name):
     slope = oracle.ols_slope(hs, strong)
     _say(f"{name}: strong slope {slope:.3f}")
     assert 0.4 <= slope <= 0.85
+
+
+@pytest.mark.parametrize("gamma", [0.0, 12.0, -12.0])
+def test_stability_example_pathwise_parity(torch_cuda, gamma):
+    """The Section 3.4.2 example at h = 0.1, T = 3 (gamma = -12 lifts the step
+    condition of Theorem 2.6 on purpose), FP64 against the oracle."""
+    w = W.gl_stability(gamma=gamma, h=0.1, T=3.0, N=1000, n_ens=2, allow_unstable_h=True)
+    _say(f"stability gamma={gamma}")
+    ref = oracle.run(w)
+    got = _run(w, "fp64")
+    err = max(float(np.max(np.abs(g - r) / np.maximum(1.0, np.abs(r)))) for g, r in zip(got, ref))
+    _say(f"stability gamma={gamma}: max rel err {err:.3e}")
+    assert err <= 1e-10
+
+
+def test_mean_square_contraction_within_theorem_2_9_bound(torch_cuda):
+    """Theorem 2.9 on the Section 3.4.2 example (gamma = 0, h = 0.01): two runs
+    from X_0 = 1 and Z_0 = 5 on the same Brownian paths satisfy
+    E|X_n - Z_n|^2 <= (1 + beta h)^n |X_0 - Z_0|^2 (particle and ensemble
+    average), and the difference contracts."""
+    import bench
+    from paper_2105_09688_amd.ssm import SSM
+    h = 1e-2
+    beta = bench.gl_stability_beta(0.0, h)
+    assert beta < 0
+    wx, wz = W.gl_stability(h=h, n_ens=4), W.gl_stability(h=h, n_ens=4, x0=5.0)
+    msd = []
+    with SSM(wx, precision="fp64") as a, SSM(wz, precision="fp64") as b:
+        for n in range(30, 301, 30):
+            a.step(30)
+            b.step(30)
+            m = sum(a.sqdiff(k, b, k) for k in range(4)) / (4 * 1000)
+            bound = (1 + beta * h) ** n * 16.0
+            _say(f"n={n}: E|X-Z|^2 {m:.3e} bound {bound:.3e}")
+            assert m <= bound
+            msd.append(m)
+    assert all(x > y for x, y in zip(msd, msd[1:]))
