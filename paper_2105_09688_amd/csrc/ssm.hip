@@ -439,12 +439,13 @@ static int64_t default_L(const std::vector<int64_t>& Ns, int R, bool sym, int d)
 {
     const int64_t tile = 64 * (int64_t)R;
     if (sym) {
-        // ~6144 workgroup items per tick (about 8 per resident workgroup
-        // slot: small enough a tail, few enough i-side partials)
+        // ~6600 workgroup items per tick (about 8.6 per resident workgroup
+        // slot at R = 4: small enough a tail, few enough i-side partials;
+        // measured best at d = 1, N = 2^16 among 4000..16000 items)
         const double group = (double)(tile * kWaves);
         double work = 0.0;
         for (int64_t N : Ns) work += 0.5 * (double)N * (double)N / group;
-        const int64_t L = (int64_t)std::ceil(work / 6144.0 / 16.0) * 16;
+        const int64_t L = (int64_t)std::ceil(work / 6600.0 / 16.0) * 16;
         (void)d;
         return std::max<int64_t>(L, 128);
     }
