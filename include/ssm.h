@@ -106,8 +106,13 @@ typedef struct {
     void *stream;              /* hipStream_t the context launches on; NULL -> a stream it owns */
     /* Tiling of the pairwise kernel; 0 = library default.  Results do not
      * depend on these beyond floating-point summation order. */
-    int32_t targets_per_lane;  /* 1, 2, 4 or 8 (a target block is 64 x this) */
-    int32_t sources_per_item;  /* sources one wavefront sweeps per work item (>= 64) */
+    int32_t targets_per_lane;  /* 1, 2, 4 or 8 (a target block is 64 x this; the symmetric scheme
+                                  takes groups of 4 blocks).  0: 4 for d = 1, 2 for d >= 2, halved
+                                  while one work item would exceed the average work of a resident
+                                  workgroup (small runs) */
+    int32_t sources_per_item;  /* sources per work item: one wavefront's source range (ordered
+                                  scheme, >= 64) or a range against a 4-block target group
+                                  (symmetric, rounded up to a multiple of 16) */
     int32_t pair_scheme;       /* 0: default (symmetric for the FP32 modes, ordered pairs for FP64);
                                   1: every ordered pair (i, j) evaluated; 2: symmetric: each unordered
                                   pair evaluated once, +q to i and -q to j (the kernel is odd),
@@ -123,7 +128,8 @@ typedef struct {
     int32_t newton_max_seen; /* largest Newton iteration count seen so far */
     int32_t newton_failures; /* particles whose implicit solve failed (sticky) */
     int32_t nonfinite;       /* particles that became non-finite (sticky) */
-    int32_t n_pair_items;    /* wavefront work items of the pairwise kernel per tick (phase 0) */
+    int32_t n_pair_items;    /* work items of the pairwise kernel per tick (phase 0): wavefronts in
+                                the ordered scheme, workgroups in the symmetric scheme */
     int32_t targets_per_lane;
     int32_t sources_per_item;
     int32_t symmetric;       /* 1: symmetric pair scheme, 0: ordered pairs */
@@ -233,7 +239,8 @@ const char *ssm_last_error(void);
  * j over all N particles.  Y: device [d][N], double for SSM_FP64 and float for
  * the FP32 modes.  K: device [d][N] double.  workspace: device buffer of at
  * least ssm_pair_workspace_bytes(d, N, precision) bytes (scratch for partial
- * sums; contents on entry ignored).  Asynchronous on stream. */
+ * sums; contents on entry ignored).  Synchronizes stream (the work list is
+ * uploaded from host memory). */
 ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, const void *Y, double ell,
                         double *K, void *workspace, size_t workspace_bytes, void *stream);
 
