@@ -316,3 +316,58 @@ def test_surrogate_run_rmse_within_5_percent_of_oracle(torch_cuda):
          f"{info['surr_max_err']:.3e}")
     assert info["surr_ticks"] >= 60  # of 120 non-check ticks
     assert abs(r_gpu - r_oracle) <= 0.05 * r_oracle
+
+
+def test_trained_surrogate_gains_over_the_exact_method(torch_cuda):
+    """What the network buys: at d = 2, N = 2^16 (64 steps of h = 2^-9, exact
+    check every 16), a network trained on other ensembles runs the step at
+    least twice as fast as the exact O(N^2) method, with most ticks on the
+    network and the path within 1e-3 (RMS) of the exact one."""
+    torch = torch_cuda
+    from paper_2105_09688_amd.ssm import SSM, mlp_init, mlp_train
+    h = 2.0 ** -9
+    w = W.surrogate_d2(N=2 ** 16, h=h, h_fine=h)
+    w["T"] = 64 * h
+    Us, Ts = [], []
+    for e in (1, 2):
+        with SSM(W.with_systems(w, [(2 ** 14, e, h)]), precision="fp32_kahan") as s:
+            for t in range(16):
+                U, T = s.surrogate_samples(4096, seed=300 * e + t)
+                Us.append(U)
+                Ts.append(T)
+                s.step(4)
+    p = torch.tensor(mlp_init(D, seed=0), device="cuda")
+    mlp_train(D, p, torch.cat(Us), torch.cat(Ts), steps=4000, batch=2048, lr=1e-3, seed=1)
+    mlp_train(D, p, torch.cat(Us), torch.cat(Ts), steps=2000, batch=2048, lr=2e-4, seed=2)
+    master = p.cpu().numpy()
+
+    def timed(setup=None):
+        s = SSM(w, precision="fp32_kahan")
+        if setup:
+            setup(s)
+        s.sync()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.run()
+        e1.record()
+        torch.cuda.synchronize()
+        info, X = s.info(), s.state(0)
+        s.close()
+        return e0.elapsed_time(e1), info, X
+
+    timed()  # warm-up of both paths' kernels
+    t_ex, _, X_ex = timed()
+
+    def enable(s):
+        s.surrogate_load(master)
+        s.surrogate_enable(check_every=16, tol=1e-2, mode="residual")
+
+    timed(enable)
+    t_su, info, X_su = timed(enable)
+    rms = float(np.sqrt(np.mean(np.sum((X_su - X_ex) ** 2, axis=0))))
+    _say(f"exact {t_ex:.2f} ms, surrogate {t_su:.2f} ms ({t_ex / t_su:.1f}x), surrogate ticks "
+         f"{info['surr_ticks']}, last check err {info['surr_last_err']:.3e}, rms vs exact {rms:.2e}")
+    assert info["surr_ticks"] >= 40  # of 60 non-check ticks
+    assert t_ex / t_su >= 2.0
+    assert rms < 1e-3
