@@ -1,15 +1,21 @@
 // ssm_kernels.hpp -- the kernels of one SSM time step on gfx950.
 //
-// A tick runs, for the systems that step on it:
-//   k_pair   : the O(N^2) interaction sums at mu^Y (eq. (2.4) drift), one
-//              wavefront per (target tile, source range) work item, partial
-//              sums per source range written to a scratch buffer;
-//   k_update : per particle, combines the partial sums in a fixed order,
-//              evaluates b and sigma at mu^Y, draws dW and applies (2.4);
-//              then (when v does not depend on mu^X) solves the implicit step
-//              (2.3) of the next step in the same thread;
+// An exact tick runs, for the systems that step on it:
+//   k_pair_sym / k_pair : the O(N^2) interaction sums at mu^Y (eq. (2.4)
+//              drift).  FP32: each unordered pair once (the kernel is odd),
+//              one workgroup per (target group, source range) item, i-side
+//              and j-side partial sums to scratch.  FP64 (or on request):
+//              every ordered pair, one wavefront per (target tile, source
+//              range) item, i-side partials only;
+//   k_prep   : the partial sums combined in a fixed order into the scaled
+//              pair term, and (same launch) the step's Brownian increments;
+//   k_update : per particle, b and sigma at mu^Y and the update (2.4); then
+//              (when v does not depend on mu^X) the implicit step (2.3) of
+//              the next step in the same thread;
 //   k_newton : the implicit step on its own (first step, and every step when
 //              v depends on mu^X, whose moments need the whole new cloud).
+// A surrogate tick replaces the first two by the network's kernels
+// (ssm_surrogate.hpp) and k_brownian_sum.
 // Layout: component-major [d][P] arrays over all systems, each system starting
 // at a multiple of kBlk particles (padding slots are zero and never read as
 // sources).
