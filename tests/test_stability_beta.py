@@ -64,3 +64,17 @@ def test_section_3_4_2_statements():
         assert L_v < -(1 + A) / 2
         assert bench.gl_stability_beta(g, 1e-9) == pytest.approx(2 * L_v + A + 1, rel=1e-6)
         assert bench.gl_stability_beta(g, 1e-3) < 0
+
+
+def test_study_error_helpers_match_the_oracle_definitions(oracle_mod):
+    """The studies compute strong and weak errors and slopes with their own
+    numpy helpers (a study may not call the oracle); they agree with the
+    oracle's definitions (Section 3) on random lists of systems."""
+    rng = np.random.default_rng(9)
+    X = [rng.normal(size=(2, n)) for n in (5, 17, 64)]
+    Y = [x + 0.1 * rng.normal(size=x.shape) + 0.01 for x in X]
+    assert bench._rmse(X, Y) == pytest.approx(oracle_mod.strong_error(X, Y), rel=1e-12)
+    assert bench._weak(X, Y) == pytest.approx(oracle_mod.weak_error(X, Y), rel=1e-12)
+    hs = [2.0 ** -l for l in range(4, 9)]
+    errs = [0.3 * h ** 0.5 * (1 + 0.05 * math.sin(l)) for l, h in enumerate(hs)]
+    assert bench._slope(hs, errs) == pytest.approx(oracle_mod.ols_slope(hs, errs), rel=1e-10)
