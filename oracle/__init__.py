@@ -41,6 +41,8 @@ class _Cfg(C.Structure):
         ("s0", C.c_double * MAX_D), ("s1", C.c_double * MAX_D), ("s2", C.c_double * MAX_D),
         ("x0_mean", C.c_double * MAX_D), ("x0_std", C.c_double * MAX_D),
         ("newton_max_iter", C.c_int32), ("allow_unstable_h", C.c_int32),
+        ("v_componentwise", C.c_int32), ("pad", C.c_int32),
+        ("v_ak", C.c_double * MAX_D), ("b_const", C.c_double * MAX_D), ("b_mat", C.c_double * (MAX_D * MAX_D)),
     ]
 
 
@@ -203,6 +205,14 @@ def _cfg(w: dict, keep: list):
         c.x0_mean[k] = float(w["x0_mean"][k]); c.x0_std[k] = float(w["x0_std"][k])
     c.newton_max_iter = int(w.get("newton_max_iter", 64))
     c.allow_unstable_h = int(bool(w.get("allow_unstable_h", False)))
+    # extensions: component-wise cubic in v, b += b_const + b_mat y
+    c.v_componentwise = int(bool(v.get("componentwise", False)))
+    ak, bc, bm = v.get("a_k"), b.get("const"), b.get("mat")
+    for k in range(d):
+        c.v_ak[k] = float(ak[k]) if ak is not None else 0.0
+        c.b_const[k] = float(bc[k]) if bc is not None else 0.0
+        for l in range(d):
+            c.b_mat[k * MAX_D + l] = float(bm[k][l]) if bm is not None else 0.0
     return c
 
 

@@ -280,8 +280,16 @@ int ssmo_step(const ssmo_cfg *cfg, int32_t ens, int64_t N, double h, int64_t n,
     for (int64_t i = 0; i < N; ++i) {
         double xi[SSMO_MAX_D], yi[SSMO_MAX_D];
         for (int k = 0; k < d; ++k) xi[k] = X[(int64_t)k * N + i];
-        int it = ssmo_implicit(d, xi, h, cfg->v_rho, cfg->v_a, cfg->v_kappa, cfg->v_lam,
+        int it = 0;
+        if (cfg->v_componentwise) {
+            /* v_k = (rho - kappa m2) y_k - a_k y_k^3 + lam xbar_k: one scalar cubic per component */
+            for (int k = 0; k < d && it >= 0; ++k)
+                it = ssmo_implicit(1, &xi[k], h, cfg->v_rho, cfg->v_ak[k], cfg->v_kappa, cfg->v_lam,
+                                   &xbar[k], m2, cfg->newton_max_iter, &yi[k]);
+        } else {
+            it = ssmo_implicit(d, xi, h, cfg->v_rho, cfg->v_a, cfg->v_kappa, cfg->v_lam,
                                xbar, m2, cfg->newton_max_iter, yi);
+        }
         if (it < 0) {
 #pragma omp critical
             status = it;
@@ -302,8 +310,12 @@ int ssmo_step(const ssmo_cfg *cfg, int32_t ens, int64_t N, double h, int64_t n,
         ssmo_brownian(cfg->seed, d, (uint64_t)i, (uint64_t)ens, (uint64_t)(n * r), r, cfg->h_fine, dW);
         for (int k = 0; k < d; ++k) {
             int64_t q = (int64_t)k * N + i;
+            double b = B[q];
+            /* the linear extension b_const + b_mat y, terms in ascending l */
+            b += cfg->b_const[k];
+            for (int l = 0; l < d; ++l) b += cfg->b_mat[k * SSMO_MAX_D + l] * Y[(int64_t)l * N + i];
             double sig = cfg->s0[k] + cfg->s1[k] * Y[q] + cfg->s2[k] * ybar[k];
-            X[q] = (Y[q] + h * B[q]) + sig * dW[k];
+            X[q] = (Y[q] + h * b) + sig * dW[k];
         }
     }
     for (int64_t q = 0; q < (int64_t)d * N; ++q)
@@ -329,6 +341,8 @@ static int check_cfg(const ssmo_cfg *cfg)
     if (cfg->d < 1 || cfg->d > SSMO_MAX_D || cfg->n_sys < 1) return SSMO_ERR_INVALID;
     if (!(cfg->T > 0.0) || !(cfg->h_fine > 0.0) || !(cfg->v_a >= 0.0) || !(cfg->v_kappa >= 0.0))
         return SSMO_ERR_INVALID;
+    for (int k = 0; k < cfg->d; ++k)
+        if (!(cfg->v_ak[k] >= 0.0)) return SSMO_ERR_INVALID;
     if (cfg->b_g != 0.0 && !(cfg->b_ell > 0.0)) return SSMO_ERR_INVALID;
     for (int s = 0; s < cfg->n_sys; ++s) {
         double h = cfg->h[s];

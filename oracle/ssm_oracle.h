@@ -49,6 +49,16 @@ typedef struct {
     double x0_mean[SSMO_MAX_D], x0_std[SSMO_MAX_D];
     int32_t newton_max_iter;   /* 0 -> 64 */
     int32_t allow_unstable_h;  /* skip the Theorem 2.6 step-size check (stability studies) */
+    /* Extensions for coefficient sets outside the radial/isotropic family
+     * (the two-dimensional Cucker-Smale model of Section 3.4.3):
+     *   v_componentwise: the cubic part of v is -v_ak[k] y_k^3 per component
+     *                    (v_a unused), so (2.3) is d scalar cubics;
+     *   b += b_const + b_mat y  (b_mat row-major [k][l]). */
+    int32_t v_componentwise;
+    int32_t pad;
+    double v_ak[SSMO_MAX_D];
+    double b_const[SSMO_MAX_D];
+    double b_mat[SSMO_MAX_D * SSMO_MAX_D];
 } ssmo_cfg;
 
 /* Status codes */

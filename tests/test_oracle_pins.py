@@ -249,6 +249,51 @@ def test_full_step_brute_force_small_N(oracle_mod):
         assert abs(mp.mpf(Xn[0, i]) - xn) < 2e-15 * (1 + abs(xn)), (i, float(xn), Xn[0, i])
 
 
+def test_full_step_brute_force_extended_coefficients(oracle_mod):
+    """The extensions for the two-dimensional Cucker-Smale model (Section
+    3.4.3) in a general d = 2 step at N = 5, 50-digit arithmetic: v with a
+    component-wise cubic -a_k y_k^3 plus (rho - kappa m2) y + lam xbar (each
+    component's root of (2.3) by mpmath findroot), b = c0 y + lam ybar +
+    b_const + b_mat y + g * pair term, sigma_k = s0 + s1 y_k + s2 ybar_k."""
+    N, e, h, n = 5, 0, 2.0 ** -5, 2
+    r = 2
+    w = dict(d=2, T=1.0, seed=0, h_fine=h / r, systems=[(N, e, h)],
+             v=dict(rho=-0.4, a=0.0, kappa=0.3, lam=0.25, componentwise=True, a_k=[1.0, 0.5]),
+             b=dict(c0=0.2, lam=-0.3, g=0.8, ell=0.9, const=[1.0, -0.5], mat=[[-2.0, 0.4], [1.0, 0.0]]),
+             sigma=dict(s0=[0.1, 0.0], s1=[-0.6, 0.2], s2=[0.6, 0.1]), x0_mean=[0.0, 0.0], x0_std=[1.0, 1.0])
+    X = W.random_cloud(2, N, seed=31, loc=0.3)
+    Xn, Y = oracle_mod.step(w, e, h, n, X)
+    mp.mp.dps = 50
+    hm = mp.mpf(h)
+    xm = [[mp.mpf(X[k, i]) for i in range(N)] for k in range(2)]
+    xbar = [sum(xm[k]) / N for k in range(2)]
+    m2 = sum(xm[0][i] ** 2 + xm[1][i] ** 2 for i in range(N)) / N
+    ys = [[None] * N for _ in range(2)]
+    for k, ak in enumerate((mp.mpf(1.0), mp.mpf(0.5))):
+        for i in range(N):
+            f = lambda y, k=k, i=i, ak=ak: y - hm * ((mp.mpf(-0.4) - mp.mpf(0.3) * m2) * y - ak * y ** 3
+                                                        + mp.mpf(0.25) * xbar[k]) - xm[k][i]
+            ys[k][i] = mp.findroot(f, xm[k][i])
+    ybar = [sum(ys[k]) / N for k in range(2)]
+    ell2 = mp.mpf(0.9) ** 2
+    for i in range(N):
+        dW = [mp.mpf(0), mp.mpf(0)]
+        for m in range(r):
+            for k in range(2):
+                dW[k] += mp.mpf(oracle_mod.stream_normal(0, i, e, (n * r + m) * 2 + k))
+        for k in range(2):
+            dW[k] *= mp.sqrt(mp.mpf(h / r))
+            d2 = [(ys[0][j] - ys[0][i]) ** 2 + (ys[1][j] - ys[1][i]) ** 2 for j in range(N)]
+            pair = sum((ys[k][j] - ys[k][i]) * mp.exp(-d2[j] / (2 * ell2)) for j in range(N)) / N
+            lin = [mp.mpf(1.0), mp.mpf(-0.5)][k] + sum(mp.mpf([[-2.0, 0.4], [1.0, 0.0]][k][l]) * ys[l][i]
+                                                       for l in range(2))
+            b = mp.mpf(0.2) * ys[k][i] + mp.mpf(-0.3) * ybar[k] + lin + mp.mpf(0.8) * pair
+            sig = mp.mpf([0.1, 0.0][k]) + mp.mpf([-0.6, 0.2][k]) * ys[k][i] + mp.mpf([0.6, 0.1][k]) * ybar[k]
+            xn = ys[k][i] + b * hm + sig * dW[k]
+            assert abs(mp.mpf(Y[k, i]) - ys[k][i]) < 1e-15 * (1 + abs(ys[k][i]))
+            assert abs(mp.mpf(Xn[k, i]) - xn) < 4e-15 * (1 + abs(xn)), (k, i, float(xn), Xn[k, i])
+
+
 def test_initial_state_and_moments(oracle_mod):
     w = W.small_parity(n_ens=1, N=4000)
     X = oracle_mod.init_state(w, 0, 4000)
