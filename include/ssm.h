@@ -59,11 +59,15 @@ typedef enum {
  * Coefficients (the split v + b of Section 2; Remark 2.7 moves a linear term
  * between them through v_rho and b_c0):
  *   v(y, mu_X) = (v_rho - v_kappa m2(mu_X)) y - v_a |y|^2 y + v_lam mean(mu_X)
- *   b(y, mu_Y) = b_c0 y + b_lam mean(mu_Y)
+ *                (v_componentwise: -v_ak[k] y_k^3 in component k in place of
+ *                -v_a |y|^2 y, so (2.3) is d scalar cubics)
+ *   b(y, mu_Y) = b_c0 y + b_lam mean(mu_Y) + b_const + b_mat y + b_mean o mean(mu_Y)
  *                + b_g (1/N) sum_j (Y^j - y) exp(-|y - Y^j|^2 / (2 b_ell^2))
  *   sigma(y, mu_Y) = diag_k(s0[k] + s1[k] y_k + s2[k] mean_k(mu_Y))  (one Brownian
  *                    motion per component)
- * with m2(mu) = (1/N) sum_j |X^j|^2.  Requirements: v_a >= 0, v_kappa >= 0,
+ * with m2(mu) = (1/N) sum_j |X^j|^2 (b_mat row-major [k][l], b_mean per component; the two-dimensional
+ * Cucker-Smale model of Section 3.4.3 needs the component-wise cubic, the
+ * constant and the coupling b_X = V).  Requirements: v_a >= 0, v_ak >= 0, v_kappa >= 0,
  * b_ell > 0 if b_g != 0, and for every system 1 - h v_rho > 0 (Lemma 4.1:
  * unique implicit root) and, unless allow_unstable_h, 1 - h (2 v_rho + 1) > 0
  * (the step-size condition of Theorem 2.6, L_v = v_rho).
@@ -120,6 +124,13 @@ typedef struct {
     int32_t graphs;            /* nonzero: each tick replays a HIP graph captured once per tick
                                   phase (tick % (h_max/h_min)); not used while profiling or with
                                   the surrogate enabled */
+    /* Coefficient extensions (zero: off), see "Coefficients" above. */
+    int32_t v_componentwise;   /* nonzero: component-wise cubic -v_ak[k] y_k^3 (v_a unused) */
+    int32_t pad2;
+    double v_ak[SSM_MAX_D];
+    double b_const[SSM_MAX_D];
+    double b_mat[SSM_MAX_D * SSM_MAX_D];
+    double b_mean[SSM_MAX_D];
 } ssm_config;
 
 typedef struct {

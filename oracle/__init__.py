@@ -43,6 +43,7 @@ class _Cfg(C.Structure):
         ("newton_max_iter", C.c_int32), ("allow_unstable_h", C.c_int32),
         ("v_componentwise", C.c_int32), ("pad", C.c_int32),
         ("v_ak", C.c_double * MAX_D), ("b_const", C.c_double * MAX_D), ("b_mat", C.c_double * (MAX_D * MAX_D)),
+        ("b_mean", C.c_double * MAX_D),
     ]
 
 
@@ -205,12 +206,13 @@ def _cfg(w: dict, keep: list):
         c.x0_mean[k] = float(w["x0_mean"][k]); c.x0_std[k] = float(w["x0_std"][k])
     c.newton_max_iter = int(w.get("newton_max_iter", 64))
     c.allow_unstable_h = int(bool(w.get("allow_unstable_h", False)))
-    # extensions: component-wise cubic in v, b += b_const + b_mat y
+    # extensions: component-wise cubic in v, b += b_const + b_mat y + b_mean o ybar
     c.v_componentwise = int(bool(v.get("componentwise", False)))
-    ak, bc, bm = v.get("a_k"), b.get("const"), b.get("mat")
+    ak, bc, bm, bmean = v.get("a_k"), b.get("const"), b.get("mat"), b.get("mean")
     for k in range(d):
         c.v_ak[k] = float(ak[k]) if ak is not None else 0.0
         c.b_const[k] = float(bc[k]) if bc is not None else 0.0
+        c.b_mean[k] = float(bmean[k]) if bmean is not None else 0.0
         for l in range(d):
             c.b_mat[k * MAX_D + l] = float(bm[k][l]) if bm is not None else 0.0
     return c

@@ -311,9 +311,10 @@ int ssmo_step(const ssmo_cfg *cfg, int32_t ens, int64_t N, double h, int64_t n,
         for (int k = 0; k < d; ++k) {
             int64_t q = (int64_t)k * N + i;
             double b = B[q];
-            /* the linear extension b_const + b_mat y, terms in ascending l */
+            /* the linear extension b_const + b_mat y + b_mean o ybar, terms in ascending l */
             b += cfg->b_const[k];
             for (int l = 0; l < d; ++l) b += cfg->b_mat[k * SSMO_MAX_D + l] * Y[(int64_t)l * N + i];
+            b += cfg->b_mean[k] * ybar[k];
             double sig = cfg->s0[k] + cfg->s1[k] * Y[q] + cfg->s2[k] * ybar[k];
             X[q] = (Y[q] + h * b) + sig * dW[k];
         }

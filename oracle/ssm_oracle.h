@@ -53,12 +53,13 @@ typedef struct {
      * (the two-dimensional Cucker-Smale model of Section 3.4.3):
      *   v_componentwise: the cubic part of v is -v_ak[k] y_k^3 per component
      *                    (v_a unused), so (2.3) is d scalar cubics;
-     *   b += b_const + b_mat y  (b_mat row-major [k][l]). */
+     *   b += b_const + b_mat y + b_mean o mean(mu_Y)  (b_mat row-major [k][l]). */
     int32_t v_componentwise;
     int32_t pad;
     double v_ak[SSMO_MAX_D];
     double b_const[SSMO_MAX_D];
     double b_mat[SSMO_MAX_D * SSMO_MAX_D];
+    double b_mean[SSMO_MAX_D];
 } ssmo_cfg;
 
 /* Status codes */

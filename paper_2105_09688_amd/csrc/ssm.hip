@@ -715,6 +715,8 @@ static ssm_status validate(const ssm_config* cfg)
     if (!(cfg->h_fine > 0.0)) return fail(SSM_ERR_INVALID, "h_fine must be > 0");
     if (!(cfg->v_a >= 0.0)) return fail(SSM_ERR_INVALID, "v_a must be >= 0 (one-sided Lipschitz v)");
     if (!(cfg->v_kappa >= 0.0)) return fail(SSM_ERR_INVALID, "v_kappa must be >= 0");
+    for (int k = 0; k < cfg->d; ++k)
+        if (!(cfg->v_ak[k] >= 0.0)) return fail(SSM_ERR_INVALID, "v_ak must be >= 0 (one-sided Lipschitz v)");
     if (cfg->b_g != 0.0 && !(cfg->b_ell > 0.0)) return fail(SSM_ERR_INVALID, "b_ell must be > 0");
     if (cfg->targets_per_lane != 0 && cfg->targets_per_lane != 1 && cfg->targets_per_lane != 2 &&
         cfg->targets_per_lane != 4 && cfg->targets_per_lane != 8)
@@ -765,6 +767,20 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     cf.newton_max_iter = cfg->newton_max_iter > 0 ? cfg->newton_max_iter : 64;
     cf.has_pair = c->has_pair ? 1 : 0;
     cf.fused = c->fused ? 1 : 0;
+    cf.v_cw = cfg->v_componentwise ? 1 : 0;
+    cf.has_lin = 0;
+    for (int k = 0; k < kMaxD; ++k) {
+        const bool in = k < cfg->d;
+        cf.v_ak[k] = in ? cfg->v_ak[k] : 0.0;
+        cf.b_const[k] = in ? cfg->b_const[k] : 0.0;
+        cf.b_mean[k] = in ? cfg->b_mean[k] : 0.0;
+        if (cf.b_mean[k] != 0.0) cf.has_lin = 1;
+        for (int l = 0; l < kMaxD; ++l) {
+            cf.b_mat[k * kMaxD + l] = (in && l < cfg->d) ? cfg->b_mat[k * SSM_MAX_D + l] : 0.0;
+            if (cf.b_mat[k * kMaxD + l] != 0.0) cf.has_lin = 1;
+        }
+        if (cf.b_const[k] != 0.0) cf.has_lin = 1;
+    }
 
     // systems, strides, padding
     double h_min = cfg->h[0];

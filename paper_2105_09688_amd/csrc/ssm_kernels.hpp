@@ -72,7 +72,13 @@ struct Coef {
     int32_t newton_max_iter;
     int32_t has_pair;    // b_g != 0
     int32_t fused;       // v independent of mu^X: the implicit solve runs inside k_update
+    int32_t v_cw;        // component-wise cubic -v_ak[k] y_k^3 (else radial -v_a |y|^2 y)
+    int32_t has_lin;     // b += b_const + b_mat y + b_mean o ybar
     int32_t pad;
+    double v_ak[kMaxD];
+    double b_const[kMaxD];
+    double b_mat[kMaxD * kMaxD];  // row-major [k][l]
+    double b_mean[kMaxD];         // b_k += b_mean[k] mean_k(mu_Y)
 };
 
 // Error counters (atomics: they fire only when something goes wrong).
@@ -294,7 +300,16 @@ __device__ __forceinline__ void solve_and_store(const SysDev& S, const Coef& cf,
     const double alpha = 1.0 - S.h * (cf.v_rho - cf.v_kappa * m2);
     int it = 0;
     if (valid) {
-        it = implicit_radial<D>(w, alpha, S.h * cf.v_a, cf.newton_max_iter, y);
+        if (cf.v_cw) {
+            // one scalar cubic per component: alpha y_k + h a_k y_k^3 = w_k
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int ik = implicit_radial<1>(&w[k], alpha, S.h * cf.v_ak[k], cf.newton_max_iter, &y[k]);
+                it = (it < 0 || ik < 0) ? -1 : max(it, ik);
+            }
+        } else {
+            it = implicit_radial<D>(w, alpha, S.h * cf.v_a, cf.newton_max_iter, y);
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < D; ++k) y[k] = 0.0;
@@ -407,9 +422,12 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
     double xn[kMaxD] = {0.0, 0.0, 0.0, 0.0};
     if (valid) {
         bool bad = false;
+        double yv[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) yv[k] = (double)Y[k * P + slot];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const double y = (double)Y[k * P + slot];
+            const double y = yv[k];
             double pair = 0.0;
             if (use_surr) {
                 // learned surrogate of the pair term, projected to zero net force,
@@ -421,7 +439,14 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
             } else if (cf.has_pair) {
                 pair = pairsum[k * P + slot];
             }
-            const double b = cf.b_c0 * y + cf.b_lam * ybar[k] + pair;
+            double b = cf.b_c0 * y + cf.b_lam * ybar[k] + pair;
+            if (cf.has_lin) {
+                // the linear extension b_const + b_mat y + b_mean o ybar, terms in ascending l
+                b += cf.b_const[k];
+#pragma unroll
+                for (int l = 0; l < D; ++l) b += cf.b_mat[k * kMaxD + l] * yv[l];
+                b += cf.b_mean[k] * ybar[k];
+            }
             const double sig = cf.s0[k] + cf.s1[k] * y + cf.s2[k] * ybar[k];
             const double dW = dWbuf[k * P + slot];
             xn[k] = (y + S.h * b) + sig * dW;

@@ -63,6 +63,15 @@ class SSM:
         c.sources_per_item = int(sources_per_item)
         c.graphs = 1 if graphs else 0
         c.pair_scheme = {"default": 0, "ordered": 1, "symmetric": 2}[pair_scheme]
+        # coefficient extensions: component-wise cubic in v, b += b_const + b_mat y + b_mean o ybar
+        c.v_componentwise = int(bool(v.get("componentwise", False)))
+        ak, bc, bm, bmean = v.get("a_k"), b.get("const"), b.get("mat"), b.get("mean")
+        for k in range(d):
+            c.v_ak[k] = float(ak[k]) if ak is not None else 0.0
+            c.b_const[k] = float(bc[k]) if bc is not None else 0.0
+            c.b_mean[k] = float(bmean[k]) if bmean is not None else 0.0
+            for l in range(d):
+                c.b_mat[k * _lib.MAX_D + l] = float(bm[k][l]) if bm is not None else 0.0
         self._cfg = c
         h = C.c_void_p()
         check(lib.ssm_init(C.byref(c), C.byref(h)))

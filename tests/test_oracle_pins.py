@@ -254,12 +254,13 @@ def test_full_step_brute_force_extended_coefficients(oracle_mod):
     3.4.3) in a general d = 2 step at N = 5, 50-digit arithmetic: v with a
     component-wise cubic -a_k y_k^3 plus (rho - kappa m2) y + lam xbar (each
     component's root of (2.3) by mpmath findroot), b = c0 y + lam ybar +
-    b_const + b_mat y + g * pair term, sigma_k = s0 + s1 y_k + s2 ybar_k."""
+    b_const + b_mat y + b_mean o ybar + g * pair term, sigma_k = s0 + s1 y_k + s2 ybar_k."""
     N, e, h, n = 5, 0, 2.0 ** -5, 2
     r = 2
     w = dict(d=2, T=1.0, seed=0, h_fine=h / r, systems=[(N, e, h)],
              v=dict(rho=-0.4, a=0.0, kappa=0.3, lam=0.25, componentwise=True, a_k=[1.0, 0.5]),
-             b=dict(c0=0.2, lam=-0.3, g=0.8, ell=0.9, const=[1.0, -0.5], mat=[[-2.0, 0.4], [1.0, 0.0]]),
+             b=dict(c0=0.2, lam=-0.3, g=0.8, ell=0.9, const=[1.0, -0.5], mat=[[-2.0, 0.4], [1.0, 0.0]],
+                    mean=[2.0, 0.0]),
              sigma=dict(s0=[0.1, 0.0], s1=[-0.6, 0.2], s2=[0.6, 0.1]), x0_mean=[0.0, 0.0], x0_std=[1.0, 1.0])
     X = W.random_cloud(2, N, seed=31, loc=0.3)
     Xn, Y = oracle_mod.step(w, e, h, n, X)
@@ -287,6 +288,7 @@ def test_full_step_brute_force_extended_coefficients(oracle_mod):
             pair = sum((ys[k][j] - ys[k][i]) * mp.exp(-d2[j] / (2 * ell2)) for j in range(N)) / N
             lin = [mp.mpf(1.0), mp.mpf(-0.5)][k] + sum(mp.mpf([[-2.0, 0.4], [1.0, 0.0]][k][l]) * ys[l][i]
                                                        for l in range(2))
+            lin += mp.mpf([2.0, 0.0][k]) * ybar[k]
             b = mp.mpf(0.2) * ys[k][i] + mp.mpf(-0.3) * ybar[k] + lin + mp.mpf(0.8) * pair
             sig = mp.mpf([0.1, 0.0][k]) + mp.mpf([-0.6, 0.2][k]) * ys[k][i] + mp.mpf([0.6, 0.1][k]) * ybar[k]
             xn = ys[k][i] + b * hm + sig * dW[k]
