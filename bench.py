@@ -213,8 +213,9 @@ def _slope(hs, errs):
 
 def study_families(args, stream):
     """The paper's own coefficient families (Section 3): stochastic
-    Ginzburg-Landau in both SSM splittings (Section 3.1) and polynomial drift
-    (Section 3.3), N = 1000 x 10 ensembles, h = 2^-4 .. 2^-10 in one context,
+    Ginzburg-Landau in both SSM splittings (Section 3.1), polynomial drift
+    (Section 3.3) and Cucker-Smale (Section 3.4.3, T = 2; also the mean and
+    spread of V at T), N = 1000 x 10 ensembles, h = 2^-4 .. 2^-10 in one context,
     against a 2^-14 proxy on the same paths: strong and weak errors and their
     rates, and the GPU time; the oracle's time for the same runs is the CPU
     baseline.  (Parity of these runs with the oracle: tests/test_gpu_families.py.)"""
@@ -225,7 +226,8 @@ def study_families(args, stream):
     n_ens, N, hf = 10, 1000, 2.0 ** -14
     fams = {"ginzburg_landau_v1": lambda **k: W.ginzburg_landau(1, **k),
             "ginzburg_landau_v2": lambda **k: W.ginzburg_landau(2, **k),
-            "polynomial_drift": lambda **k: W.polynomial_drift(**k)}
+            "polynomial_drift": lambda **k: W.polynomial_drift(**k),
+            "cucker_smale": lambda **k: W.cucker_smale(**k)}
     out = {"study": "families", "workload": f"N={N} x {n_ens} ensembles, h=2^-4..2^-10, proxy 2^-14, T=1, {prec}"}
     for name, mk in fams.items():
         w = mk(n_ens=n_ens, N=N, h_fine=hf, levels=levels)
@@ -244,6 +246,10 @@ def study_families(args, stream):
             hs.append(2.0 ** -l)
             st.append(sg)
             wk.append(wg)
+        if name == "cucker_smale":
+            import numpy as np
+            V = np.concatenate([x[0] for x in g_ref])
+            res["V_at_T"] = {"mean": float(V.mean()), "std": float(V.std())}
         res["strong_slope"] = _slope(hs, st)
         res["weak_slope"] = _slope(hs, wk)
         ps = particle_steps(w, n) + particle_steps(ref_w, n_ref)

@@ -153,6 +153,29 @@ def polynomial_drift(gamma: float = -1.0, n_ens: int = 10, N: int = 1000, h: flo
     )
 
 
+def cucker_smale(lam: float = 2.0, sigma_p: float = 4.0, n_ens: int = 10, N: int = 1000, h: float = 2.0 ** -8,
+                 h_fine: float = 2.0 ** -12, T: float = 2.0, levels=None) -> dict:
+    """Two-dimensional Cucker-Smale flocking model of Section 3.4.3, state
+    (V, X): dV = (1 - V^3 + lam (mean V - V)) dt + sigma' (mean V - V) dW,
+    dX = V dt, with lam = 2, sigma' = 4, T = 2, N = 1000.  Split as
+    v = (-V^3, 0) (component-wise cubic), b = (1 + lam (mean V - V), V),
+    sigma = (sigma' (mean V - V), 0).  The paper's coefficient line writes the
+    mean terms as int (V - z) dmu(z) and its particle dynamics as
+    (1/N) sum_j (V^j - V^i); the particle form (the one whose V converges to
+    1, as the paper states) is used.  V_0 ~ N(1, 2) read as variance 2;
+    X_0 = 0 (not given)."""
+    systems = ([(N, e, h) for e in range(n_ens)] if levels is None
+               else [(N, e, 2.0 ** -l) for e in range(n_ens) for l in levels])
+    return dict(
+        d=2, T=T, seed=0, h_fine=h_fine, systems=systems,
+        v=dict(rho=0.0, a=0.0, kappa=0.0, lam=0.0, componentwise=True, a_k=[1.0, 0.0]),
+        b=dict(c0=0.0, lam=0.0, g=0.0, ell=1.0, const=[1.0, 0.0], mat=[[-lam, 0.0], [1.0, 0.0]],
+               mean=[lam, 0.0]),
+        sigma=dict(s0=[0.0, 0.0], s1=[-sigma_p, 0.0], s2=[sigma_p, 0.0]),
+        x0_mean=[1.0, 0.0], x0_std=[2.0 ** 0.5, 0.0],
+    )
+
+
 def gl_stability(gamma: float = 0.0, x0: float = 1.0, h: float = 1e-2, T: float = 3.0, N: int = 1000,
                  n_ens: int = 10, allow_unstable_h: bool = False) -> dict:
     """Stability example of Section 3.4.2: dX = (-5/2 X - 1/4 X^3 + E[X]) dt + X dW,

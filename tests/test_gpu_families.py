@@ -1,8 +1,10 @@
 """The paper's own coefficient families on the library (Section 3): the
 stochastic Ginzburg-Landau equation in both SSM splittings (Section 3.1;
-version 2 puts c E[X] in v, so the implicit step (2.3) sees mu_X) and the
+version 2 puts c E[X] in v, so the implicit step (2.3) sees mu_X), the
 polynomial-drift model (Section 3.3, measure-dependent v: the unfused
-update path), against the oracle."""
+update path) and the two-dimensional Cucker-Smale model (Section 3.4.3:
+component-wise cubic, constant and coupled linear drift, degenerate
+sigma), against the oracle."""
 import math
 import sys
 
@@ -18,6 +20,7 @@ FAMILIES = {
     "gl_v1": lambda **k: W.ginzburg_landau(1, **k),
     "gl_v2": lambda **k: W.ginzburg_landau(2, **k),
     "poly": lambda **k: W.polynomial_drift(**k),
+    "cucker_smale": lambda **k: W.cucker_smale(**k),
 }
 
 
