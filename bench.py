@@ -513,7 +513,7 @@ def main():
                     help="after the run, one plain device copy of this many MiB (calibrates byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the per-step all-gather of Y* across GPUs is a design note, not code).", file=sys.stderr)
         sys.exit(2)
 
