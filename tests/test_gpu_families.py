@@ -11,6 +11,7 @@ import sys
 import numpy as np
 import pytest
 
+import errstats
 import oracle
 from paper_2105_09688_amd import workloads as W
 
@@ -77,15 +78,15 @@ def test_family_rates_match_oracle(torch_cuda, name):
         idx = [e * len(levels) + li for e in range(10)]
         assert all(w["systems"][k][2] == 2.0 ** -l for k in idx)
         s_o = oracle.strong_error([o[k] for k in idx], o_ref)
-        s_g = oracle.strong_error([g[k] for k in idx], g_ref)
+        s_g = errstats.strong_error([g[k] for k in idx], g_ref)
         w_o = oracle.weak_error([o[k] for k in idx], o_ref)
-        w_g = oracle.weak_error([g[k] for k in idx], g_ref)
+        w_g = errstats.weak_error([g[k] for k in idx], g_ref)
         _say(f"{name} h=2^-{l}: rmse gpu {s_g:.5e} oracle {s_o:.5e}; weak gpu {w_g:.4e} oracle {w_o:.4e}")
         assert abs(s_g - s_o) <= 0.05 * s_o
         assert abs(w_g - w_o) <= 0.05 * w_o + 1e-6
         hs.append(2.0 ** -l)
         strong.append(s_g)
-    slope = oracle.ols_slope(hs, strong)
+    slope = errstats.ols_slope(hs, strong)
     _say(f"{name}: strong slope {slope:.3f}")
     assert 0.4 <= slope <= 0.85
 

@@ -9,6 +9,7 @@ import sys
 import numpy as np
 import pytest
 
+import errstats
 import oracle
 from paper_2105_09688_amd import workloads as W
 
@@ -102,9 +103,9 @@ def test_pair_sum_matches_oracle(torch_cuda, d, ell, N):
     assert _err(got, ref) <= 1e-12
     for prec in ("fp32", "fp32_kahan"):
         _say(f"pair_sum {prec} d={d} N={N}")
-        Yf = torch.tensor(Y, device="cuda", dtype=torch.float32)
-        got = pair_sum(Yf, ell, prec).cpu().numpy()
-        ref32 = oracle.pair_sum(Yf.cpu().numpy().astype(np.float64), ell)  # same rounded inputs
+        Y32 = np.asarray(Y, dtype=np.float32)  # the same rounded inputs on both sides
+        got = pair_sum(torch.tensor(Y32, device="cuda"), ell, prec).cpu().numpy()
+        ref32 = oracle.pair_sum(Y32.astype(np.float64), ell)
         assert _err(got, ref32) <= 2e-6, prec
 
 
@@ -121,13 +122,38 @@ def test_pair_sum_full_size_sampled_and_zero_net_force(torch_cuda):
         ref = oracle.pair_sum_at(Y, ell, idx)
         for prec, tol in (("fp64", 1e-12), ("fp32_kahan", 2e-6), ("fp32", 2e-6)):
             _say(f"pair_sum full size d={d} N={N} {prec}")
-            dt = torch.float64 if prec == "fp64" else torch.float32
-            Yd = torch.tensor(Y, device="cuda", dtype=dt)
-            K = pair_sum(Yd, ell, prec).cpu().numpy()
-            r = ref if prec == "fp64" else oracle.pair_sum_at(Yd.cpu().numpy().astype(np.float64), ell, idx)
+            Yh = np.asarray(Y, dtype=np.float64 if prec == "fp64" else np.float32)
+            K = pair_sum(torch.tensor(Yh, device="cuda"), ell, prec).cpu().numpy()
+            r = ref if prec == "fp64" else oracle.pair_sum_at(Yh.astype(np.float64), ell, idx)
             assert _err(K[:, idx], r) <= tol, prec
             net = np.abs(K.sum(axis=1))
             assert np.all(net <= (1e-9 if prec == "fp64" else 1e-3) * np.abs(K).sum(axis=1)), (prec, net)
+
+
+def test_full_size_single_gpu_steps_match_oracle(torch_cuda):
+    """The single-GPU d = 1 workload at full size (N = 2^16, h = 2^-10) in the
+    tiling the benchmark times (library default: symmetric scheme, 4 targets
+    per lane, 320 sources per item): the first two steps against the oracle's
+    own steps from its X_0, pathwise, in FP32-compensated and FP64."""
+    w = W.single_gpu_d1()
+    N, ens, h = w["systems"][0]
+    X = oracle.init_state(w, ens, N)
+    refs = []
+    for n in range(2):
+        _say(f"oracle full-size step {n}")
+        X, _ = oracle.step(w, ens, h, n, X)
+        refs.append(X)
+    for prec, tol in (("fp32_kahan", FP32_TOL), ("fp64", FP64_TOL)):
+        with _ssm(w, prec) as s:
+            info = s.info()
+            if prec == "fp32_kahan":
+                assert (info["pair_scheme"], info["targets_per_lane"], info["sources_per_item"]) == ("symmetric", 4, 320)
+            for n in range(2):
+                _say(f"gpu full-size step {n} {prec}")
+                s.step(1)
+                err = _err(s.state(0), refs[n])
+                _say(f"  max rel err {err:.3e}")
+                assert err <= tol, (prec, n, err)
 
 
 # --------------------------------------------------------------------------- whole runs
@@ -166,8 +192,8 @@ def test_run_small_parity_fp32(torch_cuda, c0_oracle, precision):
 
 
 def test_stepwise_parity_and_implicit_state(torch_cuda):
-    """Step by step on one system: X_n and Y*_n = F_h(X_n) against oracle steps
-    from the GPU's own X_n (isolates one step's error)."""
+    """Step by step on one system: X_n and the implicit state Y*_n = F_h(X_n)
+    against the oracle's own step-by-step run from its X_0."""
     w = W.small_parity(n_ens=1, N=777, h=2.0 ** -6, h_fine=2.0 ** -8)
     h = 2.0 ** -6
     with _ssm(w, "fp64") as s:
@@ -175,12 +201,11 @@ def test_stepwise_parity_and_implicit_state(torch_cuda):
         assert _err(s.state(0, "x"), X) <= 1e-15
         for n in range(8):
             _say(f"stepwise n={n}")
-            Xg = s.state(0, "x")
-            Yg = s.state(0, "y")
-            Xn_ref, Y_ref = oracle.step(w, 0, h, n, Xg)
-            assert _err(Yg, Y_ref) <= 1e-14
+            X_next, Y_ref = oracle.step(w, 0, h, n, X)
+            assert _err(s.state(0, "y"), Y_ref) <= 1e-13
             s.step(1)
-            assert _err(s.state(0, "x"), Xn_ref) <= 1e-13
+            assert _err(s.state(0, "x"), X_next) <= 1e-13
+            X = X_next
 
 
 def test_multilevel_batched_equals_separate_runs(torch_cuda):
@@ -293,7 +318,7 @@ def test_rmse_matches_oracle_within_5_percent(torch_cuda):
                 r_gpu, per = a.rmse(b)
                 sa, sb = a.states(), b.states()
             # the device reduction equals the host formula on the same states
-            assert r_gpu == pytest.approx(oracle.strong_error(sa, sb), rel=1e-12)
+            assert r_gpu == pytest.approx(errstats.strong_error(sa, sb), rel=1e-12)
             assert abs(r_gpu - r_or) <= 0.05 * r_or, (prec, h, r_gpu, r_or)
             if prec == "fp64":
                 assert abs(r_gpu - r_or) <= 1e-8 * r_or
