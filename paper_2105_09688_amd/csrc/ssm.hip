@@ -15,6 +15,7 @@
 
 using namespace ssm;
 
+static constexpr int kRedBlocks = 256;  // blocks of the fixed-order moment / rMSE reductions
 static constexpr double kLog2e = 1.4426950408889634073599246810018921;  // log2(e)
 
 // ---------------------------------------------------------------------------
@@ -214,6 +215,7 @@ struct ssm_ctx {
     Flags* dflags = nullptr;
     int32_t* dnmax = nullptr;      // [nblk_tot][kSlotsPerBlk] largest Newton iteration count
     double* dstage = nullptr;  // staging for state copies / moments
+    double* dred = nullptr;    // [kMaxD][kRedBlocks] partial sums of the moment / rMSE reductions
     int64_t bytes = 0;
     // per phase (tick % max_stride) work lists: offsets into dpair / dblk
     std::vector<int64_t> pair_off, pair_cnt, blk_off, blk_cnt;
@@ -308,7 +310,7 @@ static void free_ctx(ssm_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* bufs[] = {c->X, c->Y, c->Ys, c->Bp, c->Bpj, c->pairsum, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
                     c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list, c->smean_part, c->smean,
-                    c->dtick, c->dW, c->surr_res, c->dnmax};
+                    c->dtick, c->dW, c->surr_res, c->dnmax, c->dred};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     recycle_events(c, c->ev_pair);
@@ -932,6 +934,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     int64_t maxN = 0;
     for (auto& S : c->sys) maxN = std::max(maxN, S.N);
     ALLOC(c->dstage, std::max<size_t>((size_t)c->d * maxN * sizeof(double), 2 * kMaxD * sizeof(double)));
+    ALLOC(c->dred, (size_t)kMaxD * kRedBlocks * sizeof(double));
 #undef ALLOC
     hipError_t he = hipMemcpyAsync(c->dsys, sd.data(), sd.size() * sizeof(SysDev), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess && !pairs.empty()) he = hipMemcpyAsync(c->dpair, pairs.data(), pairs.size() * sizeof(PairItem), hipMemcpyHostToDevice, c->stream);
@@ -983,25 +986,43 @@ extern "C" ssm_status ssm_run(ssm_ctx* c)
 // ---------------------------------------------------------------------------
 // moments, state access, rMSE
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void k_moments(const T* __restrict__ X, int64_t P, int64_t off, int64_t N, int d, double* __restrict__ out)
+// Reductions over one system's particles in a fixed order: block b of a
+// grid of nb <= kRedBlocks blocks adds the particles b kBlk + t + m nb kBlk
+// per thread and then over the block (tree), and one block adds the nb
+// partials in block order.
+
+static unsigned red_blocks(int64_t N)
 {
-    // one block of kBlk threads; fixed-order strided sums + tree
+    return (unsigned)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (N + kBlk - 1) / kBlk));
+}
+
+// Partial sums per component k of X_k (mean == nullptr) or of (X_k - mean[k])^2.
+template <typename T>
+__global__ void k_moments_part(const T* __restrict__ X, int64_t P, int64_t off, int64_t N, int d,
+                               const double* __restrict__ mean, double* __restrict__ part)
+{
+    __shared__ double red[kBlk];
+    for (int k = 0; k < d; ++k) {
+        const double m = mean ? mean[k] : 0.0;
+        double s = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlk) {
+            const double x = (double)X[k * P + off + i];
+            s += mean ? (x - m) * (x - m) : x;
+        }
+        const double t = block_sum(s, red);
+        if (threadIdx.x == 0) part[k * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// out[k] = scale * (sum over b < nb of part[k nb + b]), one block.
+__global__ void k_red_final(const double* __restrict__ part, int nb, int d, double scale, double* __restrict__ out)
+{
     __shared__ double red[kBlk];
     for (int k = 0; k < d; ++k) {
         double s = 0.0;
-        for (int64_t i = threadIdx.x; i < N; i += kBlk) s += (double)X[k * P + off + i];
-        const double mean = block_sum(s, red) / (double)N;
-        double v = 0.0;
-        for (int64_t i = threadIdx.x; i < N; i += kBlk) {
-            const double c = (double)X[k * P + off + i] - mean;
-            v += c * c;
-        }
-        const double var = block_sum(v, red) / (double)N;
-        if (threadIdx.x == 0) {
-            out[k] = mean;
-            out[kMaxD + k] = var;
-        }
+        for (int b = threadIdx.x; b < nb; b += kBlk) s += part[k * nb + b];
+        const double t = block_sum(s, red);
+        if (threadIdx.x == 0) out[k] = t * scale;
     }
 }
 
@@ -1021,19 +1042,20 @@ __global__ void k_scatter(const double* __restrict__ in, int64_t P, int64_t off,
     for (int k = 0; k < d; ++k) X[k * P + off + i] = (T)in[(int64_t)k * N + i];
 }
 
+// Partial sums of |A^i - B^i|^2 (same grid rule as k_moments_part).
 template <typename TA, typename TB>
-__global__ void k_sqdiff(const TA* __restrict__ A, int64_t PA, int64_t offA, const TB* __restrict__ B, int64_t PB,
-                         int64_t offB, int64_t N, int d, double* __restrict__ out)
+__global__ void k_sqdiff_part(const TA* __restrict__ A, int64_t PA, int64_t offA, const TB* __restrict__ B, int64_t PB,
+                              int64_t offB, int64_t N, int d, double* __restrict__ part)
 {
     __shared__ double red[kBlk];
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < N; i += kBlk)
+    for (int64_t i = (int64_t)blockIdx.x * kBlk + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlk)
         for (int k = 0; k < d; ++k) {
             const double c = (double)A[k * PA + offA + i] - (double)B[k * PB + offB + i];
             s += c * c;
         }
-    const double tot = block_sum(s, red);
-    if (threadIdx.x == 0) out[0] = tot;
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // one system of a against one system of b; result in dout (device), async on a's stream
@@ -1042,13 +1064,16 @@ static ssm_status launch_sqdiff(ssm_ctx* a, int sa, ssm_ctx* b, int sb, double* 
     const SysHost& A = a->sys[sa];
     const SysHost& B = b->sys[sb];
     const bool fa = a->prec == SSM_FP64, fb = b->prec == SSM_FP64;
-#define SQD(TA, TB) hipLaunchKernelGGL((k_sqdiff<TA, TB>), dim3(1), dim3(kBlk), 0, a->stream, (const TA*)a->X, a->P, A.off, \
-                                       (const TB*)b->X, b->P, B.off, A.N, a->d, dout)
+    const unsigned nb = red_blocks(A.N);
+#define SQD(TA, TB) hipLaunchKernelGGL((k_sqdiff_part<TA, TB>), dim3(nb), dim3(kBlk), 0, a->stream, (const TA*)a->X, a->P, \
+                                       A.off, (const TB*)b->X, b->P, B.off, A.N, a->d, a->dred)
     if (fa && fb) SQD(double, double);
     else if (fa) SQD(double, float);
     else if (fb) SQD(float, double);
     else SQD(float, float);
 #undef SQD
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_red_final, dim3(1), dim3(kBlk), 0, a->stream, (const double*)a->dred, (int)nb, 1, 1.0, dout);
     HIP_TRY(hipGetLastError());
     return SSM_OK;
 }
@@ -1058,11 +1083,23 @@ extern "C" ssm_status ssm_moments(ssm_ctx* c, int32_t sys, double* mean, double*
     if (!c || !mean || !var) return fail(SSM_ERR_INVALID, "NULL argument");
     if (sys < 0 || sys >= (int32_t)c->sys.size()) return fail(SSM_ERR_INVALID, "sys out of range");
     const SysHost& S = c->sys[sys];
-    if (c->prec == SSM_FP64)
-        hipLaunchKernelGGL(k_moments<double>, dim3(1), dim3(kBlk), 0, c->stream, (const double*)c->X, c->P, S.off, S.N, c->d, c->dstage);
-    else
-        hipLaunchKernelGGL(k_moments<float>, dim3(1), dim3(kBlk), 0, c->stream, (const float*)c->X, c->P, S.off, S.N, c->d, c->dstage);
-    HIP_TRY(hipGetLastError());
+    // two passes (mean, then the mean square deviation about it), each a
+    // fixed-order partial-sum launch and a final one-block sum into dstage
+    const unsigned nb = red_blocks(S.N);
+    const double inv_n = 1.0 / (double)S.N;
+    for (int pass = 0; pass < 2; ++pass) {
+        const double* mean = pass ? c->dstage : nullptr;
+        if (c->prec == SSM_FP64)
+            hipLaunchKernelGGL(k_moments_part<double>, dim3(nb), dim3(kBlk), 0, c->stream, (const double*)c->X, c->P, S.off,
+                               S.N, c->d, mean, c->dred);
+        else
+            hipLaunchKernelGGL(k_moments_part<float>, dim3(nb), dim3(kBlk), 0, c->stream, (const float*)c->X, c->P, S.off,
+                               S.N, c->d, mean, c->dred);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_red_final, dim3(1), dim3(kBlk), 0, c->stream, (const double*)c->dred, (int)nb, c->d, inv_n,
+                           c->dstage + pass * kMaxD);
+        HIP_TRY(hipGetLastError());
+    }
     double buf[2 * kMaxD];
     HIP_TRY(hipMemcpyAsync(buf, c->dstage, sizeof(buf), hipMemcpyDeviceToHost, c->stream));
     ssm_status st = ssm_sync(c);
