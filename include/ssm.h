@@ -208,6 +208,32 @@ ssm_status ssm_get_state(ssm_ctx *ctx, int32_t sys, int32_t which, double *host,
  * precision) and recompute Y* for it.  Synchronizes. */
 ssm_status ssm_set_state(ssm_ctx *ctx, int32_t sys, const double *host);
 
+/* Device layout of the particle state X of a context: one row of *P slots per
+ * component (row k starts at element k * *P), system s at slots
+ * [offsets[s], offsets[s] + N_s) of every row (offsets: host [n_sys], may be
+ * NULL; each a multiple of 256), elements of *elt_bytes bytes (8: double in
+ * FP64 mode, 4: float in the FP32 modes; may be NULL).  The other slots are
+ * padding. */
+ssm_status ssm_state_layout(ssm_ctx *ctx, int64_t *P, int64_t *offsets, int32_t *elt_bytes);
+
+/* Make a caller-owned device buffer (for instance a torch tensor) the
+ * context's state X, so the caller reads the particles in place.  bytes >=
+ * d * P * elt_bytes (ssm_state_layout); 16-byte aligned.  The current state,
+ * padding included, is copied into it and the context's own X is freed.  The
+ * caller keeps the buffer alive until ssm_destroy (or until another buffer is
+ * bound) and never frees it while the context may use it; the library never
+ * frees it.  The kernels write X on the context's stream: read it after
+ * ssm_sync or on that stream.  A caller that writes X (padding slots stay
+ * finite) calls ssm_state_refresh before the next step, as the library keeps
+ * Y* = F_h(X) of (2.3) one step ahead.  Synchronizes. */
+ssm_status ssm_bind_state(ssm_ctx *ctx, void *dev, size_t bytes);
+
+/* Recompute Y* = F_h(X) (2.3) and the block sums of X for system sys
+ * (sys = -1: every system) after the caller changed X in a bound buffer.
+ * SSM_ERR_STATE when v depends on mu^X (as for ssm_set_state).
+ * Synchronizes. */
+ssm_status ssm_state_refresh(ssm_ctx *ctx, int32_t sys);
+
 /* Strong error between two contexts with identical system layouts:
  * per_sys[s] = sum_i |X_a^i - X_b^i|^2 over system s (host [n_sys], may be
  * NULL), *rmse = sqrt(sum over all systems / total particles).  This is the

@@ -16,7 +16,7 @@ SSM_FP64, SSM_FP32, SSM_FP32_KAHAN = 0, 1, 2
 # every function the header declares (checked by the CPU test suite)
 EXPORTS = (
     "ssm_init", "ssm_step", "ssm_run", "ssm_sync", "ssm_moments", "ssm_get_state",
-    "ssm_set_state", "ssm_rmse", "ssm_sqdiff", "ssm_info", "ssm_profile", "ssm_destroy", "ssm_last_error",
+    "ssm_set_state", "ssm_state_layout", "ssm_bind_state", "ssm_state_refresh", "ssm_rmse", "ssm_sqdiff", "ssm_info", "ssm_profile", "ssm_destroy", "ssm_last_error",
     "ssm_pair_sum", "ssm_pair_workspace_bytes", "ssm_implicit_solve", "ssm_brownian",
     "ssm_philox_blocks", "ssm_mlp_num_params", "ssm_surrogate_load", "ssm_surrogate_enable",
     "ssm_surrogate_samples", "ssm_mlp_forward", "ssm_mlp_loss_grad", "ssm_mlp_train",
@@ -85,6 +85,9 @@ def load():
         "ssm_moments": (st, [vp, i32, dp, dp]),
         "ssm_get_state": (st, [vp, i32, i32, dp, C.POINTER(C.c_int64)]),
         "ssm_set_state": (st, [vp, i32, dp]),
+        "ssm_state_layout": (st, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+        "ssm_bind_state": (st, [vp, vp, C.c_size_t]),
+        "ssm_state_refresh": (st, [vp, i32]),
         "ssm_rmse": (st, [vp, vp, dp, dp]),
         "ssm_sqdiff": (st, [vp, i32, vp, i32, dp]),
         "ssm_info": (st, [vp, C.POINTER(Info)]),

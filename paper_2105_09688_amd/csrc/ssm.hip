@@ -191,6 +191,7 @@ struct ssm_ctx {
     std::vector<SysHost> sys;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    bool x_bound = false;      // X lives in a caller-owned buffer (ssm_bind_state)
     int64_t P = 0;          // padded slots
     int64_t nblk_tot = 0;
     int64_t max_stride = 1;
@@ -216,6 +217,7 @@ struct ssm_ctx {
     int32_t* dnmax = nullptr;      // [nblk_tot][kSlotsPerBlk] largest Newton iteration count
     double* dstage = nullptr;  // staging for state copies / moments
     double* dred = nullptr;    // [kMaxD][kRedBlocks] partial sums of the moment / rMSE reductions
+    double* dsq = nullptr;     // [systems] squared differences of ssm_rmse
     int64_t bytes = 0;
     // per phase (tick % max_stride) work lists: offsets into dpair / dblk
     std::vector<int64_t> pair_off, pair_cnt, blk_off, blk_cnt;
@@ -308,9 +310,9 @@ static void free_ctx(ssm_ctx* c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    void* bufs[] = {c->X, c->Y, c->Ys, c->Bp, c->Bpj, c->pairsum, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
+    void* bufs[] = {c->x_bound ? nullptr : c->X, c->Y, c->Ys, c->Bp, c->Bpj, c->pairsum, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
                     c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list, c->smean_part, c->smean,
-                    c->dtick, c->dW, c->surr_res, c->dnmax, c->dred};
+                    c->dtick, c->dW, c->surr_res, c->dnmax, c->dred, c->dsq};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     recycle_events(c, c->ev_pair);
@@ -935,6 +937,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     for (auto& S : c->sys) maxN = std::max(maxN, S.N);
     ALLOC(c->dstage, std::max<size_t>((size_t)c->d * maxN * sizeof(double), 2 * kMaxD * sizeof(double)));
     ALLOC(c->dred, (size_t)kMaxD * kRedBlocks * sizeof(double));
+    ALLOC(c->dsq, c->sys.size() * sizeof(double));
 #undef ALLOC
     hipError_t he = hipMemcpyAsync(c->dsys, sd.data(), sd.size() * sizeof(SysDev), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess && !pairs.empty()) he = hipMemcpyAsync(c->dpair, pairs.data(), pairs.size() * sizeof(PairItem), hipMemcpyHostToDevice, c->stream);
@@ -1129,21 +1132,12 @@ extern "C" ssm_status ssm_get_state(ssm_ctx* c, int32_t sys, int32_t which, doub
     return st;
 }
 
-extern "C" ssm_status ssm_set_state(ssm_ctx* c, int32_t sys, const double* host)
+// Recompute Y* = F_h(X) and its block sums for system sys after X was
+// written from outside the step loop (the parity of the system's step count
+// selects the double-buffered sums).  Synchronizes.
+static ssm_status refresh_implicit(ssm_ctx* c, int32_t sys)
 {
-    if (!c || !host) return fail(SSM_ERR_INVALID, "NULL argument");
-    if (sys < 0 || sys >= (int32_t)c->sys.size()) return fail(SSM_ERR_INVALID, "sys out of range");
-    if (!c->fused) return fail(SSM_ERR_STATE, "set_state needs v independent of mu^X");
-    c->surr_res_valid = false;  // the stored residuals belong to the old state
     const SysHost& S = c->sys[sys];
-    HIP_TRY(hipMemcpyAsync(c->dstage, host, (size_t)c->d * S.N * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    const unsigned g = (unsigned)((S.N + kBlk - 1) / kBlk);
-    if (c->prec == SSM_FP64)
-        hipLaunchKernelGGL(k_scatter<double>, dim3(g), dim3(kBlk), 0, c->stream, c->dstage, c->P, S.off, S.N, c->d, (double*)c->X);
-    else
-        hipLaunchKernelGGL(k_scatter<float>, dim3(g), dim3(kBlk), 0, c->stream, c->dstage, c->P, S.off, S.N, c->d, (float*)c->X);
-    HIP_TRY(hipGetLastError());
-    // recompute Y* and its block sums for this system (parity of its step count)
     std::vector<BlkItem> items;
     for (int64_t b = 0; b < S.nblk; ++b) items.push_back(BlkItem{sys, (int32_t)b});
     BlkItem* ditems = nullptr;
@@ -1165,7 +1159,76 @@ extern "C" ssm_status ssm_set_state(ssm_ctx* c, int32_t sys, const double* host)
     }
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     (void)hipFree(ditems);
-    if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("set_state: ") + hipGetErrorString(he));
+    if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("implicit refresh: ") + hipGetErrorString(he));
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_set_state(ssm_ctx* c, int32_t sys, const double* host)
+{
+    if (!c || !host) return fail(SSM_ERR_INVALID, "NULL argument");
+    if (sys < 0 || sys >= (int32_t)c->sys.size()) return fail(SSM_ERR_INVALID, "sys out of range");
+    if (!c->fused) return fail(SSM_ERR_STATE, "set_state needs v independent of mu^X");
+    c->surr_res_valid = false;  // the stored residuals belong to the old state
+    const SysHost& S = c->sys[sys];
+    HIP_TRY(hipMemcpyAsync(c->dstage, host, (size_t)c->d * S.N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    const unsigned g = (unsigned)((S.N + kBlk - 1) / kBlk);
+    if (c->prec == SSM_FP64)
+        hipLaunchKernelGGL(k_scatter<double>, dim3(g), dim3(kBlk), 0, c->stream, c->dstage, c->P, S.off, S.N, c->d, (double*)c->X);
+    else
+        hipLaunchKernelGGL(k_scatter<float>, dim3(g), dim3(kBlk), 0, c->stream, c->dstage, c->P, S.off, S.N, c->d, (float*)c->X);
+    HIP_TRY(hipGetLastError());
+    ssm_status st = refresh_implicit(c, sys);
+    if (st != SSM_OK) return st;
+    return ssm_sync(c);
+}
+
+extern "C" ssm_status ssm_state_layout(ssm_ctx* c, int64_t* P, int64_t* offsets, int32_t* elt_bytes)
+{
+    if (!c || !P) return fail(SSM_ERR_INVALID, "NULL argument");
+    *P = c->P;
+    if (offsets)
+        for (size_t s = 0; s < c->sys.size(); ++s) offsets[s] = c->sys[s].off;
+    if (elt_bytes) *elt_bytes = (int32_t)elt(c->prec);
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_bind_state(ssm_ctx* c, void* dev, size_t bytes)
+{
+    if (!c || !dev) return fail(SSM_ERR_INVALID, "NULL argument");
+    const size_t need = (size_t)c->d * (size_t)c->P * elt(c->prec);
+    if (bytes < need) return fail(SSM_ERR_INVALID, "buffer smaller than d x P elements of the storage precision");
+    if ((uintptr_t)dev % 16 != 0) return fail(SSM_ERR_INVALID, "buffer must be 16-byte aligned");
+    if (dev == c->X) return SSM_OK;
+    // the current state (padding slots included) moves into the buffer in stream order
+    HIP_TRY(hipMemcpyAsync(dev, c->X, need, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (!c->x_bound) {
+        (void)hipFree(c->X);
+        c->bytes -= (int64_t)need;
+    }
+    c->X = dev;
+    c->x_bound = true;
+    // captured tick graphs hold the old address
+    for (auto& g : c->phase_graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    return ssm_sync(c);
+}
+
+extern "C" ssm_status ssm_state_refresh(ssm_ctx* c, int32_t sys)
+{
+    if (!c) return fail(SSM_ERR_INVALID, "ctx is NULL");
+    if (sys < -1 || sys >= (int32_t)c->sys.size()) return fail(SSM_ERR_INVALID, "sys out of range");
+    if (!c->fused) return fail(SSM_ERR_STATE, "state_refresh needs v independent of mu^X");
+    ssm_status st = ssm_sync(c);
+    if (st != SSM_OK) return st;
+    c->surr_res_valid = false;
+    for (int32_t s = (sys < 0 ? 0 : sys); s < (sys < 0 ? (int32_t)c->sys.size() : sys + 1); ++s) {
+        st = refresh_implicit(c, s);
+        if (st != SSM_OK) return st;
+    }
     return ssm_sync(c);
 }
 
@@ -1178,15 +1241,11 @@ extern "C" ssm_status ssm_rmse(ssm_ctx* a, ssm_ctx* b, double* per_sys, double* 
     ssm_status st = ssm_sync(b);
     if (st != SSM_OK) return st;
     const int n = (int)a->sys.size();
-    double* dout = nullptr;
-    HIP_TRY(hipMalloc((void**)&dout, n * sizeof(double)));
-    for (int s = 0; s < n && st == SSM_OK; ++s) st = launch_sqdiff(a, s, b, s, dout + s);
-    std::vector<double> h(n);
-    hipError_t he = hipSuccess;
-    if (st == SSM_OK) he = hipMemcpyAsync(h.data(), dout, n * sizeof(double), hipMemcpyDeviceToHost, a->stream);
-    if (he == hipSuccess) he = hipStreamSynchronize(a->stream);
-    (void)hipFree(dout);
+    for (int s = 0; s < n && st == SSM_OK; ++s) st = launch_sqdiff(a, s, b, s, a->dsq + s);
     if (st != SSM_OK) return st;
+    std::vector<double> h(n);
+    hipError_t he = hipMemcpyAsync(h.data(), a->dsq, n * sizeof(double), hipMemcpyDeviceToHost, a->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(a->stream);
     if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("rmse: ") + hipGetErrorString(he));
     double tot = 0.0;
     int64_t cnt = 0;

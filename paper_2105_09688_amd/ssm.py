@@ -128,6 +128,38 @@ class SSM:
         X = np.ascontiguousarray(X, dtype=np.float64).reshape(self.d, self.N[sys])
         check(_lib.load().ssm_set_state(self._h, sys, X.ctypes.data_as(C.POINTER(C.c_double))))
 
+    # -- the state in caller-owned device memory -----------------------------
+    def state_layout(self):
+        """(P, offsets, element bytes) of the device state X (ssm_state_layout)."""
+        P = C.c_int64()
+        offs = (C.c_int64 * len(self.N))()
+        e = C.c_int32()
+        check(_lib.load().ssm_state_layout(self._h, C.byref(P), offs, C.byref(e)))
+        return P.value, list(offs), e.value
+
+    def bind_state(self, buf=None):
+        """Make a CUDA tensor [d][P] of the storage dtype the context's X
+        (ssm_bind_state); a new one is allocated when buf is None.  Returns it;
+        the context keeps a reference, so the memory outlives the context."""
+        torch = _torch()
+        P, offs, e = self.state_layout()
+        dt = torch.float64 if e == 8 else torch.float32
+        if buf is None:
+            buf = torch.empty((self.d, P), dtype=dt, device="cuda")
+        if buf.dtype != dt or not buf.is_cuda or not buf.is_contiguous() or tuple(buf.shape) != (self.d, P):
+            raise ValueError(f"state buffer must be a contiguous CUDA tensor {dt} of shape ({self.d}, {P})")
+        check(_lib.load().ssm_bind_state(self._h, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+        self._bound, self._offs = buf, offs
+        return buf
+
+    def state_view(self, sys: int = 0):
+        """View [d][N_s] of system sys in the bound state tensor (after bind_state)."""
+        return self._bound[:, self._offs[sys]:self._offs[sys] + self.N[sys]]
+
+    def refresh(self, sys: int = -1) -> None:
+        """Recompute Y* after X was changed through the bound tensor (ssm_state_refresh)."""
+        check(_lib.load().ssm_state_refresh(self._h, int(sys)))
+
     def rmse(self, other: "SSM"):
         per = np.zeros(len(self.N))
         r = C.c_double()

@@ -263,6 +263,50 @@ def test_linear_ou_without_pair_term(torch_cuda):
             assert _err(s.state(e), ref[e]) <= FP64_TOL
 
 
+def test_bound_state_is_the_context_state(torch_cuda):
+    """A torch tensor bound as the state X (ssm_bind_state): the run in it
+    equals an unbound run bitwise and its views equal get_state; X written
+    through the tensor followed by ssm_state_refresh equals ssm_set_state of
+    the same values; undersized or misaligned buffers are refused."""
+    import ctypes as C
+    from paper_2105_09688_amd import _lib
+    torch = torch_cuda
+    w = W.batched(n_ens=2, levels=(4, 5), h_fine=2.0 ** -8, sizes=[300, 65])
+    w["T"] = 0.25
+    for prec in ("fp64", "fp32_kahan"):
+        _say(f"bound state {prec}")
+        with _ssm(w, prec) as a, _ssm(w, prec) as b:
+            buf = a.bind_state()
+            P, offs, e = a.state_layout()
+            assert tuple(buf.shape) == (w["d"], P) and all(o % 256 == 0 for o in offs)
+            assert e == (8 if prec == "fp64" else 4)
+            a.step(3)
+            b.step(3)
+            a.sync()
+            b.sync()
+            for s in range(len(a.N)):
+                va = a.state_view(s).double().cpu().numpy()
+                assert np.array_equal(va, a.state(s)) and np.array_equal(va, b.state(s)), (prec, s)
+            Xn = np.random.default_rng(5).normal(size=(w["d"], a.N[0]))
+            Xs = Xn.astype(np.float64 if prec == "fp64" else np.float32)
+            a.state_view(0).copy_(torch.tensor(Xs, device="cuda"))
+            torch.cuda.synchronize()
+            a.refresh(0)
+            b.set_state(0, Xs.astype(np.float64))
+            a.step(2)
+            b.step(2)
+            for s in range(len(a.N)):
+                assert np.array_equal(a.state(s), b.state(s)), (prec, s)
+                assert np.array_equal(a.state(s, "y"), b.state(s, "y")), (prec, s)
+    with _ssm(w, "fp64") as c:
+        P, _, e = c.state_layout()
+        t = torch.zeros(w["d"] * P + 8, dtype=torch.float64, device="cuda")
+        lib = _lib.load()
+        assert lib.ssm_bind_state(c._h, C.c_void_p(t.data_ptr()), w["d"] * P * e - 8) == _lib.SSM_ERR_INVALID
+        assert lib.ssm_bind_state(c._h, C.c_void_p(t.data_ptr() + 8), w["d"] * P * e) == _lib.SSM_ERR_INVALID
+        assert lib.ssm_state_refresh(c._h, 7) == _lib.SSM_ERR_INVALID
+
+
 def test_single_particle_and_ragged_sizes(torch_cuda):
     for N in (1, 2, 255, 257):
         w = W.small_parity(n_ens=1, N=N, h=2.0 ** -5, h_fine=2.0 ** -5)
