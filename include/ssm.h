@@ -384,6 +384,35 @@ ssm_status ssm_mlp_loss_grad(int32_t d, const float *master, const float *U, con
 ssm_status ssm_mlp_train(int32_t d, const float *U, const float *T, int64_t n_samples,
                          const ssm_train_cfg *cfg, float *master, float *loss_hist, void *stream);
 
+/* Settings of ssm_surrogate_train. */
+typedef struct {
+    int32_t n_ens;       /* training systems: ensembles ens0 .. ens0 + n_ens - 1 (keep them
+                            apart from the ensembles the network will be used on) */
+    int32_t ens0;
+    int64_t N;           /* particles per training system (0: N of the context's system 0) */
+    int64_t n_samples;   /* training rows in total, a multiple of n_ens * snapshots */
+    int32_t snapshots;   /* states per training run at which rows are drawn: the states after
+                            k M / snapshots steps, k = 0 .. snapshots - 1, M = T / h */
+    int32_t pad;
+    uint64_t seed;       /* row draws and, without initial weights, the fresh weights */
+    ssm_train_cfg train; /* Adam settings (ssm_mlp_train) */
+} ssm_surrogate_train_cfg;
+
+/* Train the surrogate for this context's workload and load it into the
+ * context (an extension; not in the paper).  Runs the exact method on n_ens
+ * systems that copy the context's system 0 (coefficients, h, T, precision,
+ * seed; ensembles and N from cfg), draws n_samples / (n_ens snapshots) rows
+ * (ssm_surrogate_samples) at each snapshot, and trains with ssm_mlp_train
+ * from init (host [ssm_mlp_num_params(d)]) or, if init is NULL, from fresh
+ * weights: each weight matrix uniform on +-sqrt(6 / (fan_in + fan_out)),
+ * biases zero, parameter p from word p % 4 of the Philox block with counter
+ * (p / 4, 0, 0, 5 * 2^32) under key (seed, 0).  master_out (host, may be NULL)
+ * receives the trained weights, loss_hist (host float [train.steps], may be
+ * NULL) the minibatch losses.  The rows live in device memory allocated for
+ * the call (n_samples x (2d + 32) floats).  Synchronizes. */
+ssm_status ssm_surrogate_train(ssm_ctx *ctx, const ssm_surrogate_train_cfg *cfg, const float *init,
+                               float *master_out, float *loss_hist);
+
 #ifdef __cplusplus
 }
 #endif

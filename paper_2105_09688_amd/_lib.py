@@ -19,7 +19,7 @@ EXPORTS = (
     "ssm_set_state", "ssm_state_layout", "ssm_bind_state", "ssm_state_refresh", "ssm_rmse", "ssm_sqdiff", "ssm_info", "ssm_profile", "ssm_destroy", "ssm_last_error",
     "ssm_pair_sum", "ssm_pair_workspace_bytes", "ssm_implicit_solve", "ssm_brownian",
     "ssm_philox_blocks", "ssm_mlp_num_params", "ssm_surrogate_load", "ssm_surrogate_enable",
-    "ssm_surrogate_samples", "ssm_mlp_forward", "ssm_mlp_loss_grad", "ssm_mlp_train",
+    "ssm_surrogate_samples", "ssm_mlp_forward", "ssm_mlp_loss_grad", "ssm_mlp_train", "ssm_surrogate_train",
 )
 
 
@@ -60,6 +60,13 @@ class TrainCfg(C.Structure):
     _fields_ = [
         ("steps", C.c_int64), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
         ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64),
+    ]
+
+
+class SurrTrainCfg(C.Structure):
+    _fields_ = [
+        ("n_ens", C.c_int32), ("ens0", C.c_int32), ("N", C.c_int64), ("n_samples", C.c_int64),
+        ("snapshots", C.c_int32), ("pad", C.c_int32), ("seed", C.c_uint64), ("train", TrainCfg),
     ]
 
 
@@ -107,6 +114,7 @@ def load():
         "ssm_mlp_forward": (st, [i32, vp, vp, i64, vp, vp]),
         "ssm_mlp_loss_grad": (st, [i32, vp, vp, vp, i64, vp, dp, vp]),
         "ssm_mlp_train": (st, [i32, vp, vp, i64, C.POINTER(TrainCfg), vp, vp, vp]),
+        "ssm_surrogate_train": (st, [vp, C.POINTER(SurrTrainCfg), vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -192,6 +192,10 @@ struct ssm_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool x_bound = false;      // X lives in a caller-owned buffer (ssm_bind_state)
+    ssm_config cfg{};          // the creating config (system arrays below), for training runs
+    std::vector<int64_t> cfg_N;
+    std::vector<int32_t> cfg_ens;
+    std::vector<double> cfg_h;
     int64_t P = 0;          // padded slots
     int64_t nblk_tot = 0;
     int64_t max_stride = 1;
@@ -751,6 +755,10 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
 
     ssm_ctx* c = new (std::nothrow) ssm_ctx();
     if (!c) return fail(SSM_ERR_OOM, "host allocation failed");
+    c->cfg = *cfg;
+    c->cfg_N.assign(cfg->N, cfg->N + cfg->n_sys);
+    c->cfg_ens.assign(cfg->ens, cfg->ens + cfg->n_sys);
+    c->cfg_h.assign(cfg->h, cfg->h + cfg->n_sys);
     c->d = cfg->d;
     c->prec = cfg->precision;
     c->fused = (cfg->v_kappa == 0.0 && cfg->v_lam == 0.0);
@@ -1705,5 +1713,87 @@ extern "C" ssm_status ssm_mlp_train(int32_t d, const float* U, const float* Tt, 
     (void)hipFree(w.base);
     if (s != SSM_OK) return s;
     if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("mlp_train: ") + hipGetErrorString(he));
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_surrogate_train(ssm_ctx* c, const ssm_surrogate_train_cfg* tc, const float* init,
+                                          float* master_out, float* loss_hist)
+{
+    if (!c || !tc) return fail(SSM_ERR_INVALID, "NULL argument");
+    if (!c->has_pair) return fail(SSM_ERR_STATE, "the surrogate replaces the pairwise term; b_g is 0");
+    if (tc->n_ens < 1 || tc->snapshots < 1 || tc->N < 0 || tc->n_samples < 1 ||
+        tc->n_samples % ((int64_t)tc->n_ens * tc->snapshots) != 0)
+        return fail(SSM_ERR_INVALID, "need n_ens >= 1, snapshots >= 1, N >= 0 and n_samples a multiple of n_ens x snapshots");
+    const int d = c->d;
+    const int64_t np = mlp_params(d), per = tc->n_samples / ((int64_t)tc->n_ens * tc->snapshots);
+    const int64_t Ntr = tc->N > 0 ? tc->N : c->cfg_N[0];
+    const double h0 = c->cfg_h[0];
+    int64_t M = 0;
+    if (!is_int_ratio(c->cfg.T, h0, &M)) return fail(SSM_ERR_INVALID, "T / h of system 0 is not an integer");
+    if (tc->snapshots > M) return fail(SSM_ERR_INVALID, "more snapshots than steps");
+    // device rows, weights
+    float *U = nullptr, *Tt = nullptr, *master = nullptr;
+    auto release = [&]() {
+        if (U) (void)hipFree(U);
+        if (Tt) (void)hipFree(Tt);
+        if (master) (void)hipFree(master);
+    };
+    if (hipMalloc((void**)&U, (size_t)tc->n_samples * raw_in(d) * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&Tt, (size_t)tc->n_samples * d * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&master, (size_t)np * sizeof(float)) != hipSuccess) {
+        release();
+        return fail(SSM_ERR_OOM, "surrogate_train: training rows");
+    }
+    hipError_t he = hipSuccess;
+    if (init) {
+        he = hipMemcpyAsync(master, init, (size_t)np * sizeof(float), hipMemcpyHostToDevice, c->stream);
+    } else {
+        hipLaunchKernelGGL(k_mlp_init, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, c->stream, tc->seed, d, master);
+        he = hipGetLastError();
+    }
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) { release(); return fail(SSM_ERR_HIP, std::string("surrogate_train: ") + hipGetErrorString(he)); }
+    // exact runs of systems like system 0 (ensembles ens0 ..), rows drawn at
+    // ticks k M / snapshots
+    ssm_config cfg = c->cfg;
+    cfg.n_sys = 1;
+    cfg.stream = c->stream;
+    cfg.graphs = 0;
+    ssm_status st = SSM_OK;
+    for (int32_t e = 0; e < tc->n_ens && st == SSM_OK; ++e) {
+        int64_t Nn = Ntr;
+        int32_t ens = tc->ens0 + e;
+        double h = h0;
+        cfg.N = &Nn;
+        cfg.ens = &ens;
+        cfg.h = &h;
+        ssm_ctx* r = nullptr;
+        st = ssm_init(&cfg, &r);
+        int64_t at = 0;
+        for (int32_t k = 0; k < tc->snapshots && st == SSM_OK; ++k) {
+            const int64_t tick = (int64_t)k * M / tc->snapshots;
+            st = ssm_step(r, tick - at);
+            at = tick;
+            const int64_t row = ((int64_t)e * tc->snapshots + k) * per;
+            if (st == SSM_OK)
+                st = ssm_surrogate_samples(r, 0, per, tc->seed + 1000003ull * (uint64_t)(e * tc->snapshots + k + 1),
+                                           U + row * raw_in(d), Tt + row * d);
+        }
+        ssm_destroy(r);
+    }
+    if (st == SSM_OK) st = ssm_mlp_train(d, U, Tt, tc->n_samples, &tc->train, master, loss_hist, c->stream);
+    if (st == SSM_OK) st = ensure_surrogate_buffers(c);
+    if (st == SSM_OK) st = pack_weights(master, d, c->dmlp, c->stream);
+    if (st == SSM_OK && master_out) {
+        he = hipMemcpyAsync(master_out, master, (size_t)np * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+        if (he != hipSuccess) st = fail(SSM_ERR_HIP, std::string("surrogate_train: ") + hipGetErrorString(he));
+    }
+    if (st == SSM_OK) {
+        he = hipStreamSynchronize(c->stream);
+        if (he != hipSuccess) st = fail(SSM_ERR_HIP, std::string("surrogate_train: ") + hipGetErrorString(he));
+    }
+    release();
+    if (st != SSM_OK) return st;
+    c->surr_loaded = true;
     return SSM_OK;
 }

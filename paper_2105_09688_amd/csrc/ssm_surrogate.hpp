@@ -93,6 +93,30 @@ __device__ __forceinline__ float silu_prime_f(float z)
 }
 
 // ---------------------------------------------------------------------------
+// Fresh master weights: each weight matrix uniform on +-sqrt(6 / (fan_in +
+// fan_out)), biases zero.  Parameter p takes word p % 4 of the Philox block
+// with counter (p / 4, 0, 0, 5 * 2^32) under key (seed, 0) (stream tag 5).
+// ---------------------------------------------------------------------------
+__global__ void k_mlp_init(uint64_t seed, int d, float* __restrict__ master)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const MlpOffsets o = mlp_offsets(d);
+    if (p >= mlp_params(d)) return;
+    int fan_in = 0, fan_out = 0;
+    if (p < o.b1) { fan_in = mlp_in(d); fan_out = kHid; }
+    else if (p >= o.W2 && p < o.b2) { fan_in = kHid; fan_out = kHid; }
+    else if (p >= o.W3 && p < o.b3) { fan_in = kHid; fan_out = kHid; }
+    else if (p >= o.W4 && p < o.b4) { fan_in = kHid; fan_out = d; }
+    float v = 0.0f;
+    if (fan_in > 0) {
+        const Block4 b = philox4x64_10((uint64_t)(p / 4), 0ull, 0ull, (uint64_t)5 << 32, seed, 0ull);
+        const double u = unit_open(b.w[p % 4]);
+        v = (float)(sqrt(6.0 / (double)(fan_in + fan_out)) * (2.0 * u - 1.0));
+    }
+    master[p] = v;
+}
+
+// ---------------------------------------------------------------------------
 // master (flat FP32) -> packed BF16 (+ transposes), zero padding
 // ---------------------------------------------------------------------------
 __global__ void k_mlp_pack(const float* __restrict__ master, int d, MlpPacked* __restrict__ P)

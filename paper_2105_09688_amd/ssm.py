@@ -128,6 +128,26 @@ class SSM:
         X = np.ascontiguousarray(X, dtype=np.float64).reshape(self.d, self.N[sys])
         check(_lib.load().ssm_set_state(self._h, sys, X.ctypes.data_as(C.POINTER(C.c_double))))
 
+    def surrogate_train(self, n_samples: int, n_ens: int = 2, ens0: int = 1, N: int = 0, snapshots: int = 32,
+                        steps: int = 4000, batch: int = 2048, lr: float = 1e-3, seed: int = 0, init=None):
+        """Train the surrogate inside the library on exact runs of n_ens systems
+        like system 0 and load it (ssm_surrogate_train).  Returns (weights,
+        loss history) as numpy float32 arrays."""
+        cfg = _lib.SurrTrainCfg()
+        cfg.n_ens, cfg.ens0, cfg.N, cfg.n_samples = int(n_ens), int(ens0), int(N), int(n_samples)
+        cfg.snapshots, cfg.seed = int(snapshots), int(seed)
+        cfg.train.steps, cfg.train.batch, cfg.train.lr, cfg.train.seed = int(steps), int(batch), float(lr), int(seed)
+        out = np.zeros(mlp_num_params(self.d), dtype=np.float32)
+        hist = np.zeros(int(steps), dtype=np.float32)
+        ini = None
+        if init is not None:
+            ini = np.ascontiguousarray(init, dtype=np.float32)
+            if ini.size != out.size:
+                raise ValueError(f"init needs {out.size} parameters")
+        check(_lib.load().ssm_surrogate_train(self._h, C.byref(cfg), None if ini is None else ini.ctypes.data,
+                                              out.ctypes.data, hist.ctypes.data))
+        return out, hist
+
     # -- the state in caller-owned device memory -----------------------------
     def state_layout(self):
         """(P, offsets, element bytes) of the device state X (ssm_state_layout)."""

@@ -40,7 +40,8 @@ def _c_layout(tmp_path, struct, fields):
     return [int(v) for v in out]
 
 
-@pytest.mark.parametrize("struct,cls", [("ssm_config", _lib.Config), ("ssm_info_t", _lib.Info), ("ssm_train_cfg", _lib.TrainCfg)])
+@pytest.mark.parametrize("struct,cls", [("ssm_config", _lib.Config), ("ssm_info_t", _lib.Info), ("ssm_train_cfg", _lib.TrainCfg),
+                                        ("ssm_surrogate_train_cfg", _lib.SurrTrainCfg)])
 def test_struct_layout_matches_header(tmp_path, struct, cls):
     names = [f for f, _ in cls._fields_]
     got = _c_layout(tmp_path, struct, names)

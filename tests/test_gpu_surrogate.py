@@ -382,3 +382,47 @@ def test_trained_surrogate_gains_over_the_exact_method(torch_cuda):
     assert info["surr_ticks"] >= 40  # of 60 non-check ticks
     assert t_ex / t_su >= 2.0
     assert rms < 1e-3
+
+
+def test_library_training_gives_a_usable_surrogate(torch_cuda):
+    """ssm_surrogate_train: exact runs of ensembles 1-2 (N = 4096, rows at 32
+    states each), Adam in two phases, loaded into the context; the same
+    residual-mode run as above then stays within 5 % of the oracle's exact
+    strong error with most ticks on the network.  The fresh weights follow
+    the stated law (matrices uniform on +-sqrt(6 / (fan_in + fan_out)), zero
+    biases), seen through one Adam step of negligible size."""
+    from paper_2105_09688_amd.ssm import SSM
+    h, hf = 2.0 ** -9, 2.0 ** -13
+    w = W.surrogate_d2(N=1024, h=h, h_fine=hf)
+    w["T"] = 0.25
+    ref_w = W.with_h(w, hf)
+    _say("oracle exact run and 2^-13 proxy")
+    o = oracle.run(w)[0]
+    o_ref = oracle.run(ref_w)[0]
+    r_oracle = oracle.strong_error(o, o_ref)
+    rows = 2 * 32 * 4096
+    with SSM(w, precision="fp32_kahan") as s:
+        _say("fresh weights")
+        p0, _ = s.surrogate_train(n_samples=2 * 32 * 64, n_ens=2, ens0=1, N=512, snapshots=32, steps=1,
+                                  batch=64, lr=1e-30, seed=9)
+        off, in_net = 0, 2 * D + 32
+        for (o_, i_) in [(64, in_net), (64, 64), (64, 64), (D, 64)]:
+            W_, b_ = p0[off:off + o_ * i_].astype(np.float64), p0[off + o_ * i_:off + o_ * i_ + o_]
+            lim = np.sqrt(6.0 / (o_ + i_))
+            assert np.max(np.abs(W_)) <= lim * (1 + 1e-6) and np.max(np.abs(b_)) <= 1e-28
+            assert abs(W_.mean()) <= 0.2 * lim and abs(W_.var() / (lim * lim / 3.0) - 1.0) <= 0.3
+            off += o_ * i_ + o_
+        _say("library training")
+        p, hist = s.surrogate_train(n_samples=rows, n_ens=2, ens0=1, N=4096, snapshots=32, steps=6000,
+                                    batch=2048, lr=1e-3, seed=1)
+        assert np.all(np.isfinite(hist)) and np.mean(hist[-50:]) < 0.05 * np.mean(hist[:20])
+        p, _ = s.surrogate_train(n_samples=rows, n_ens=2, ens0=1, N=4096, snapshots=32, steps=3000,
+                                 batch=2048, lr=2e-4, seed=2, init=p)
+        s.surrogate_enable(check_every=16, tol=1e-2, mode="residual")
+        s.run()
+        info = s.info()
+        X = s.state(0)
+    r_gpu = errstats.strong_error(X, o_ref)
+    _say(f"rmse oracle exact {r_oracle:.4e}, gpu surrogate {r_gpu:.4e}; surrogate ticks {info['surr_ticks']}")
+    assert info["surr_ticks"] >= 60
+    assert abs(r_gpu - r_oracle) <= 0.05 * r_oracle
