@@ -32,6 +32,19 @@ def flops_per_pair(d: int) -> int:
     return 5 * d + 1
 
 
+ISSUE_LANE_OPS = 256 * 4 * 16 * 2.4e9  # non-packed VALU issue: CUs x SIMDs x lanes x clock
+
+
+def issue_ceiling_tflops(d: int, scheme: str) -> float:
+    """FP32 pair kernel's issue-bound ceiling in algorithmic TFLOP/s: without
+    packed FP32 each lane issues one VALU op per slot; an unordered pair costs
+    d subtractions, d multiply-adds for |z|^2, the exponential (2 slots, half
+    rate) and 2d accumulations (symmetric: 2d + 1 slots per ordered pair), an
+    ordered pair d + d + 2 + d (3d + 2 slots)."""
+    slots = 2 * d + 1 if scheme == "symmetric" else 3 * d + 2
+    return ISSUE_LANE_OPS / slots * flops_per_pair(d) / 1e12
+
+
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -598,6 +611,8 @@ def main():
             "traffic": recorded_traffic(f"k_pair {args.precision} d={d} N={N} R={info['targets_per_lane']} "
                                         f"L={info['sources_per_item']} {info['pair_scheme']}"),
             "flop_per_pair": flops_per_pair(d),
+            "issue_ceiling": None if args.precision == "fp64" else issue_ceiling_tflops(d, info["pair_scheme"]),
+            "frac_of_issue_ceiling": None if args.precision == "fp64" else achieved / issue_ceiling_tflops(d, info["pair_scheme"]),
             "pairs_per_launch": pairs,
             "avg_launch_ms": pair_avg_s * 1e3,
             "launches": info["pair_launches"],

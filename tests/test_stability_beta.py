@@ -78,3 +78,4 @@ def test_study_error_helpers_match_the_oracle_definitions(oracle_mod):
     hs = [2.0 ** -l for l in range(4, 9)]
     errs = [0.3 * h ** 0.5 * (1 + 0.05 * math.sin(l)) for l, h in enumerate(hs)]
     assert bench._slope(hs, errs) == pytest.approx(oracle_mod.ols_slope(hs, errs), rel=1e-10)
+
