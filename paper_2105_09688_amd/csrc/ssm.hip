@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/ssm.h"
@@ -180,6 +181,7 @@ struct SysHost {
     int64_t blk0, nblk;
     int64_t splits;
     int64_t steps_done;
+    int64_t win_off = -1;  // offset of its path group's Brownian window (-1: none)
 };
 
 struct ssm_ctx {
@@ -255,6 +257,12 @@ struct ssm_ctx {
     bool dtick_valid = true;  // device counter equals the host tick
     double* dW = nullptr;  // [d][P] Brownian increments of the current tick
     int bm_lanes = 1;      // lanes per particle in k_brownian_sum
+    // shared Brownian windows of path groups (systems of one ensemble and size)
+    double* win = nullptr;      // [groups][max_stride][d][N_g] per-tick normal sums
+    BlkItem* dwin_items = nullptr;
+    int64_t win_items = 0;      // blocks of one member per group
+    int64_t r_min = 1;          // fine increments per tick
+    int win_lanes = 1;          // lanes per particle in k_bm_window
     bool use_graphs = false;
     std::vector<hipGraphExec_t> phase_graph;
     // kernel timing: event pairs recorded around launches while profiling
@@ -316,7 +324,7 @@ static void free_ctx(ssm_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* bufs[] = {c->x_bound ? nullptr : c->X, c->Y, c->Ys, c->Bp, c->Bpj, c->pairsum, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
                     c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list, c->smean_part, c->smean,
-                    c->dtick, c->dW, c->surr_res, c->dnmax, c->dred, c->dsq};
+                    c->dtick, c->dW, c->surr_res, c->dnmax, c->dred, c->dsq, c->win, c->dwin_items};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     recycle_events(c, c->ev_pair);
@@ -514,6 +522,22 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
     const bool run_exact = !surr_on || check || c->surr_fallback;
     const bool run_surr = surr_on && (check || !c->surr_fallback);
     const bool prof = c->profiling && c->tick % c->profile_every == 0;
+    if (ph == 0 && c->win_items > 0 && nb > 0) {
+        // the path groups' Brownian windows for ticks tick .. tick + max_stride - 1
+        const dim3 gw((unsigned)(c->win_items * c->win_lanes), (unsigned)c->max_stride);
+#define SSM_WIN(LPV)                                                                                                   \
+    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_bm_window<D, LPV>), gw, dim3(kBlk), 0, c->stream, c->dwin_items, c->dsys, \
+                                         c->coef, c->r_min, c->tick, tdev, c->win))
+        switch (c->win_lanes) {
+            case 16: SSM_WIN(16); break;
+            case 8: SSM_WIN(8); break;
+            case 4: SSM_WIN(4); break;
+            case 2: SSM_WIN(2); break;
+            default: SSM_WIN(1); break;
+        }
+#undef SSM_WIN
+        HIP_TRY(hipGetLastError());
+    }
     if (c->has_pair && np > 0 && run_exact) {
         dim3 grid((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves));
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -552,10 +576,10 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
     if (comb) {                                                                                                       \
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_prep<T, D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, ncb, items,     \
                                              c->dsys, c->coef, c->P, (const T*)c->Bp, c->Bpj, c->pairsum, c->tick,   \
-                                             tdev, c->dW));                                                           \
+                                             tdev, (const double*)c->win, c->dW));                                    \
     } else {                                                                                                          \
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_brownian_sum<D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, items,    \
-                                             c->dsys, c->coef, c->P, c->tick, tdev, c->dW));                          \
+                                             c->dsys, c->coef, c->P, c->tick, tdev, (const double*)c->win, c->dW));   \
     }
         switch (c->bm_lanes) {
             case 16: SSM_BM(16); break;
@@ -818,6 +842,26 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     if (c->max_stride > 4096) { free_ctx(c); return fail(SSM_ERR_INVALID, "h_max / h_min larger than 4096"); }
     c->P = off;
     c->nblk_tot = blk;
+    // path groups: systems of one ensemble and size step on the same Brownian
+    // paths; with several step sizes, such a group draws each tick's normals
+    // once into a window of max_stride ticks that all its members sum from
+    std::vector<BlkItem> win_items;
+    int64_t win_doubles = 0;
+    if (c->max_stride > 1) {
+        std::map<std::pair<int64_t, int32_t>, std::vector<int>> groups;
+        for (int s = 0; s < (int)c->sys.size(); ++s) groups[{c->sys[s].N, c->sys[s].ens}].push_back(s);
+        for (auto& kv : groups) {
+            if (kv.second.size() < 2) continue;
+            for (int s : kv.second) c->sys[s].win_off = win_doubles;
+            const SysHost& R0 = c->sys[kv.second[0]];
+            for (int64_t b = 0; b < R0.nblk; ++b) win_items.push_back(BlkItem{kv.second[0], (int32_t)b});
+            win_doubles += c->max_stride * (int64_t)cfg->d * R0.N;
+        }
+        is_int_ratio(h_min, cfg->h_fine, &c->r_min);
+        const int64_t wb = (c->r_min * cfg->d + 3) / 4;
+        c->win_lanes = wb >= 16 ? 16 : wb >= 8 ? 8 : wb >= 4 ? 4 : wb >= 2 ? 2 : 1;
+    }
+    c->win_items = (int64_t)win_items.size();
     is_int_ratio(cfg->T, h_min, &c->ticks_total);
 
     // pair tiling: R targets per lane, L sources per item, scheme
@@ -871,9 +915,11 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     std::vector<BlkItem> blks;
     std::vector<int32_t> sys_lists;
     {
-        // Philox blocks per step and particle: about r d / 4
+        // per step and particle: about r d / 4 Philox blocks, or (path groups)
+        // `stride` window entries, four per lane
         int64_t bmax = 1;
-        for (auto& S : c->sys) bmax = std::max<int64_t>(bmax, (S.r * c->d + 3) / 4);
+        for (auto& S : c->sys)
+            bmax = std::max<int64_t>(bmax, S.win_off >= 0 ? (S.stride + 3) / 4 : (S.r * c->d + 3) / 4);
         c->bm_lanes = bmax >= 16 ? 16 : bmax >= 8 ? 8 : bmax >= 4 ? 4 : bmax >= 2 ? 2 : 1;
     }
     c->phase_graph.assign(c->max_stride, nullptr);
@@ -921,6 +967,8 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
         x.sym_B = c->sym ? 64 * c->R * kWaves : 0;
         x.sym_L = c->sym ? (int32_t)c->L : 0;
         x.h = S.h;
+        x.win_off = S.win_off >= 0 ? S.win_off : 0;
+        x.win_W = S.win_off >= 0 ? (int32_t)c->max_stride : 0;
         x.pair_scale = c->has_pair ? cfg->b_g / ((double)S.N * cf.coord_scale) : 0.0;
         sd.push_back(x);
     }
@@ -945,12 +993,18 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     for (auto& S : c->sys) maxN = std::max(maxN, S.N);
     ALLOC(c->dstage, std::max<size_t>((size_t)c->d * maxN * sizeof(double), 2 * kMaxD * sizeof(double)));
     ALLOC(c->dred, (size_t)kMaxD * kRedBlocks * sizeof(double));
+    if (c->win_items > 0) {
+        ALLOC(c->win, (size_t)win_doubles * sizeof(double));
+        ALLOC(c->dwin_items, (size_t)c->win_items * sizeof(BlkItem));
+    }
     ALLOC(c->dsq, c->sys.size() * sizeof(double));
 #undef ALLOC
     hipError_t he = hipMemcpyAsync(c->dsys, sd.data(), sd.size() * sizeof(SysDev), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess && !pairs.empty()) he = hipMemcpyAsync(c->dpair, pairs.data(), pairs.size() * sizeof(PairItem), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipMemcpyAsync(c->dblk, blks.data(), blks.size() * sizeof(BlkItem), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipMemcpyAsync(c->dsys_list, sys_lists.data(), sys_lists.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess && c->win_items > 0)
+        he = hipMemcpyAsync(c->dwin_items, win_items.data(), win_items.size() * sizeof(BlkItem), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(c->dflags, 0, sizeof(Flags), c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(c->dnmax, 0, (size_t)c->nblk_tot * kSlotsPerBlk * sizeof(int32_t), c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(c->dtick, 0, sizeof(int64_t), c->stream);

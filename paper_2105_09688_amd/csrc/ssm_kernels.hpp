@@ -45,6 +45,9 @@ struct SysDev {
     int32_t pad;
     double h;           // time step
     double pair_scale;  // b_g / (N c): scaled pair sums -> b's pair term
+    int64_t win_off;    // shared Brownian window of the system's path group (win_W > 0)
+    int32_t win_W;      // ticks per window (0: the system draws its own increments)
+    int32_t pad2;
 };
 
 struct PairItem {
@@ -512,28 +515,51 @@ __device__ __forceinline__ void stream_sum(uint64_t seed, uint64_t i, uint64_t e
 // <= 16) share one particle and take every LP-th Philox block of the step;
 // their partial sums are combined by a fixed butterfly.  Block g of the grid
 // handles sub-block g % LP of item g / LP (256 / LP particles).
+// A system of a path group (systems of one ensemble and size at several step
+// sizes, so on the same Brownian paths) reads its normals' sums from the
+// group's window instead: win[win_off + (p D + k) N + i] holds the sum of
+// particle i's normals of component k over tick p of the current window of
+// win_W ticks (k_bm_window), and a step of `stride` ticks starting at window
+// tick p0 adds the entries p0 .. p0 + stride - 1 (lane q takes p0 + q,
+// p0 + q + LP, ...).  Each normal is then drawn once per window, not once
+// per step size.
+template <int LP, int D>
+__device__ __forceinline__ void lane_butterfly(double (&zs)[kMaxD])
+{
+#pragma unroll
+    for (int w = LP / 2; w > 0; w >>= 1)
+#pragma unroll
+        for (int k = 0; k < D; ++k) zs[k] += __shfl_xor(zs[k], w, 64);
+}
+
 template <int D, int LP>
 __device__ __forceinline__ void brownian_block(int vb, const BlkItem* __restrict__ items,
                                                const SysDev* __restrict__ sys, const Coef& cf, int64_t P,
                                                int64_t tick_arg, const int64_t* __restrict__ tick_dev,
-                                               double* __restrict__ dW)
+                                               const double* __restrict__ win, double* __restrict__ dW)
 {
     const BlkItem it = items[vb / LP];
     const int sub = vb % LP;
     const SysDev S = sys[it.sys];
     const int q = threadIdx.x % LP;
     const int i = it.blk * kBlk + sub * (kBlk / LP) + threadIdx.x / LP;
-    const int64_t n = tick_of(tick_dev, tick_arg) / S.stride;
+    const int64_t t = tick_of(tick_dev, tick_arg);
+    const int64_t n = t / S.stride;
     double zs[kMaxD] = {0.0, 0.0, 0.0, 0.0};
     if (i < S.N) {
-        const uint64_t q0 = (uint64_t)n * (uint64_t)S.r * D;
-        const uint64_t q1 = q0 + (uint64_t)S.r * D;
-        stream_sum<D>(cf.seed, (uint64_t)i, (uint64_t)S.ens, q0, q1, q0 / 4 + q, LP, zs);
+        if (S.win_W > 0) {
+            const int p0 = (int)(t % S.win_W);
+            const double* __restrict__ w = win + S.win_off;
+            for (int p = p0 + q; p < p0 + S.stride; p += LP)
+#pragma unroll
+                for (int k = 0; k < D; ++k) zs[k] += w[((int64_t)p * D + k) * S.N + i];
+        } else {
+            const uint64_t q0 = (uint64_t)n * (uint64_t)S.r * D;
+            const uint64_t q1 = q0 + (uint64_t)S.r * D;
+            stream_sum<D>(cf.seed, (uint64_t)i, (uint64_t)S.ens, q0, q1, q0 / 4 + q, LP, zs);
+        }
     }
-#pragma unroll
-    for (int w = LP / 2; w > 0; w >>= 1)
-#pragma unroll
-        for (int k = 0; k < D; ++k) zs[k] += __shfl_xor(zs[k], w, 64);
+    lane_butterfly<LP, D>(zs);
     if (q == 0 && i < S.N) {
 #pragma unroll
         for (int k = 0; k < D; ++k) dW[k * P + S.off + i] = cf.sqrt_hf * zs[k];
@@ -545,9 +571,41 @@ __global__ __launch_bounds__(kBlk) void k_brownian_sum(const BlkItem* __restrict
                                                        const SysDev* __restrict__ sys, Coef cf,
                                                        int64_t P, int64_t tick_arg,
                                                        const int64_t* __restrict__ tick_dev,
-                                                       double* __restrict__ dW)
+                                                       const double* __restrict__ win, double* __restrict__ dW)
 {
-    brownian_block<D, LP>(blockIdx.x, items, sys, cf, P, tick_arg, tick_dev, dW);
+    brownian_block<D, LP>(blockIdx.x, items, sys, cf, P, tick_arg, tick_dev, win, dW);
+}
+
+// k_bm_window: the window of a path group, drawn at its first tick t0
+// (*tick_dev or tick_arg): win[win_off + (p D + k) N + i] = sum of particle
+// i's normals of component k over the fine steps of tick t0 + p, that is
+// stream normals [((t0 + p) r_min + m) d + k, m < r_min] with r_min fine
+// steps per tick.  Items are the blocks of one member system per group;
+// blockIdx.y = p; LP lanes per particle as in k_brownian_sum.
+template <int D, int LP>
+__global__ __launch_bounds__(kBlk) void k_bm_window(const BlkItem* __restrict__ items,
+                                                    const SysDev* __restrict__ sys, Coef cf, int64_t r_min,
+                                                    int64_t tick_arg, const int64_t* __restrict__ tick_dev,
+                                                    double* __restrict__ win)
+{
+    const BlkItem it = items[blockIdx.x / LP];
+    const int sub = blockIdx.x % LP;
+    const int p = blockIdx.y;
+    const SysDev S = sys[it.sys];
+    const int q = threadIdx.x % LP;
+    const int i = it.blk * kBlk + sub * (kBlk / LP) + threadIdx.x / LP;
+    const int64_t t = tick_of(tick_dev, tick_arg) + p;
+    double zs[kMaxD] = {0.0, 0.0, 0.0, 0.0};
+    if (i < S.N) {
+        const uint64_t q0 = (uint64_t)t * (uint64_t)r_min * D;
+        const uint64_t q1 = q0 + (uint64_t)r_min * D;
+        stream_sum<D>(cf.seed, (uint64_t)i, (uint64_t)S.ens, q0, q1, q0 / 4 + q, LP, zs);
+    }
+    lane_butterfly<LP, D>(zs);
+    if (q == 0 && i < S.N) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) win[S.win_off + ((int64_t)p * D + k) * S.N + i] = zs[k];
+    }
 }
 
 // k_prep: the combine (first n_combine blocks) and the Brownian sums (the
@@ -558,14 +616,15 @@ __global__ __launch_bounds__(kBlk) void k_prep(int n_combine, const BlkItem* __r
                                                const SysDev* __restrict__ sys, Coef cf, int64_t P,
                                                const PT* __restrict__ Bp, const float* __restrict__ Bpj,
                                                double* __restrict__ pairsum, int64_t tick_arg,
-                                               const int64_t* __restrict__ tick_dev, double* __restrict__ dW)
+                                               const int64_t* __restrict__ tick_dev, const double* __restrict__ win,
+                                               double* __restrict__ dW)
 {
     static_assert(64 * kCombineWaves == kBlk, "one block shape for both parts");
     __shared__ double part[kCombineWaves][D][64];
     if ((int)blockIdx.x < n_combine)
         combine_block<PT, D>(blockIdx.x, items, sys, P, Bp, Bpj, pairsum, part);
     else
-        brownian_block<D, LP>(blockIdx.x - n_combine, items, sys, cf, P, tick_arg, tick_dev, dW);
+        brownian_block<D, LP>(blockIdx.x - n_combine, items, sys, cf, P, tick_arg, tick_dev, win, dW);
 }
 
 // Advance the context's device tick counter (last launch of every tick).
