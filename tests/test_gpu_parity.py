@@ -225,6 +225,32 @@ def test_multilevel_batched_equals_separate_runs(torch_cuda):
             assert _err(g, r) <= tol, (prec, k, w["systems"][k])
 
 
+@pytest.mark.parametrize("d", [2, 3])
+def test_shared_brownian_windows_in_d_2_and_3(torch_cuda, d):
+    """Path groups (one ensemble and size at several step sizes) sharing a
+    Brownian window, in d = 2 (8 normals per tick) and d = 3 with h_fine =
+    h_min (3 normals per tick, so Philox blocks straddle ticks), beside a
+    system of its own: every system equals the oracle's run of it alone."""
+    if d == 2:
+        base = W.surrogate_d2(N=300, h=2.0 ** -6, h_fine=2.0 ** -8)
+        hs = (2.0 ** -4, 2.0 ** -5, 2.0 ** -6)
+    else:
+        base = W.precision_d3(N=300, h=2.0 ** -6)
+        hs = (2.0 ** -3, 2.0 ** -4, 2.0 ** -6)
+    systems = [(300, 0, h) for h in hs] + [(65, 1, hs[0]), (65, 1, hs[2]), (129, 2, hs[1])]
+    w = W.with_systems(base, systems)
+    w["T"] = 0.25
+    _say(f"oracle: {len(systems)} systems, d={d}")
+    ref = oracle.run(w)
+    for prec, tol in (("fp64", FP64_TOL), ("fp32_kahan", FP32_TOL)):
+        _say(f"gpu windows d={d} {prec}")
+        with _ssm(w, prec) as s:
+            s.run()
+            got = s.states()
+        for k, (g, r) in enumerate(zip(got, ref)):
+            assert _err(g, r) <= tol, (prec, k, systems[k])
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32_kahan", FP32_TOL), ("fp32", FP32_TOL)])
 def test_run_d3_and_d2(torch_cuda, precision, tol):
     for w in (W.precision_d3(N=700), W.surrogate_d2(N=900, h=2.0 ** -9, h_fine=2.0 ** -10)):
