@@ -872,9 +872,9 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
         for (auto& S : c->sys) Ns.push_back(S.N);
         c->R = cfg->targets_per_lane > 0 ? cfg->targets_per_lane : default_R(c->d, Ns, c->sym);
     }
-    if (c->sym && (int64_t)64 * c->R * kWaves * c->d > kSymLDS) {
+    if (c->sym && (int64_t)64 * c->R * kWaves * c->d > sym_lds(c->d)) {
         // a target group's j-side sums must fit the kernel's LDS buffer
-        if (cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "symmetric scheme: targets_per_lane too large for this d (64 x R x 4 x d must be <= 2048)"); }
+        if (cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "symmetric scheme: targets_per_lane too large for this d (64 x R x 4 x d must be <= " + std::to_string(sym_lds(c->d)) + ")"); }
         c->sym = false;
     }
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -1397,7 +1397,7 @@ static KPlan kernel_plan(int32_t d, int64_t N, int32_t precision)
     KPlan p{};
     p.sym = precision != SSM_FP64;
     p.R = default_R(d, std::vector<int64_t>{N}, p.sym);
-    if (p.sym && (int64_t)64 * p.R * kWaves * d > kSymLDS) p.sym = false;
+    if (p.sym && (int64_t)64 * p.R * kWaves * d > sym_lds(d)) p.sym = false;
     p.L = default_L(std::vector<int64_t>{N}, p.R, p.sym, d);
     std::vector<std::pair<int64_t, PairItem>> tmp;
     p.isplits = plan_system(0, N, p.R, p.sym, p.L, tmp, &p.nb);

@@ -29,7 +29,14 @@ constexpr int kBlk = 256;      // particles per update block (and system alignme
 constexpr int kWaves = 4;      // wavefronts per pair block
 constexpr int kUnroll = 8;     // sources per inner-loop iteration
 constexpr int kKahanChunk = 128;  // sources summed plainly before a compensated add
-constexpr int kSymLDS = 2048;     // floats of LDS j-side buffer per wavefront (symmetric scheme)
+// Floats of LDS j-side buffer per wavefront in the symmetric scheme: a
+// target group times d must fit (the diagonal item's j-side sums).  d = 3
+// takes 3072 (1024 sources per flush instead of 682: 1.5 % faster at
+// N = 2^18); d = 1, 2 measured slower with it.  A d = 3 row has 64 more
+// floats, where the lanes that store no j-side sum write (no branch around
+// the store: 1 % faster at d = 3, slower at d = 1, 2).
+__host__ __device__ constexpr int sym_lds(int D) { return D == 3 ? 3072 : 2048; }
+__host__ __device__ constexpr int sym_row(int D) { return sym_lds(D) + (D == 3 ? 64 : 0); }
 
 struct SysDev {
     int64_t off;        // first slot of the system in [P]
@@ -740,7 +747,7 @@ __device__ __forceinline__ void sym_route(const float (&accj)[16][D], float (&to
     for (int c = 0; c < D; ++c) tot[c] += dpp_ror<K>(accj[K][c]);
 }
 
-// The chunk's j-side sums (before the sign flip) go to out[c * (kSymLDS / D) + j + jshift]
+// The chunk's j-side sums (before the sign flip) go to out[c * (sym_lds(D) / D) + j + jshift]
 // for the chunk's valid sources j when write_j holds.  JSIDE = false drops
 // the j-side arithmetic at compile time.
 template <int D, int R, bool JSIDE = true>
@@ -802,9 +809,13 @@ __device__ __forceinline__ void sym_chunk(const float* __restrict__ base, int64_
         tot[c] += __shfl_xor(tot[c], 16, 64);
         tot[c] += __shfl_xor(tot[c], 32, 64);
     }
-    if (write_j && lane < 16 && vj) {
+    if constexpr (D == 3) {
+        const bool wr = write_j && lane < 16 && vj;
 #pragma unroll
-        for (int c = 0; c < D; ++c) out[c * (kSymLDS / D) + j + jshift] = tot[c];
+        for (int c = 0; c < D; ++c) out[wr ? (int)(c * (sym_lds(D) / D) + j + jshift) : sym_lds(D) + lane] = tot[c];
+    } else if (write_j && lane < 16 && vj) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) out[c * (sym_lds(D) / D) + j + jshift] = tot[c];
     }
 }
 
@@ -818,7 +829,7 @@ __device__ __forceinline__ void sym_chunk(const float* __restrict__ base, int64_
 //    partials (zero for block 0); or
 //  - a later source range (jrow = a): unordered pairs with every block of
 //    the group; i-side partial `split`, j-side row a.
-// j-side sums pass through LDS (kSymLDS / d sources at a time) and are added
+// j-side sums pass through LDS (sym_lds(d) / d sources at a time) and are added
 // over the wavefronts in a fixed order before they are written.
 template <int D, int R, bool KAHAN>
 __device__ __forceinline__ void kahan_fold(float (&acc)[R][D], float (&hi)[R][D], float (&lo)[R][D])
@@ -838,10 +849,10 @@ __device__ __forceinline__ void kahan_fold(float (&acc)[R][D], float (&hi)[R][D]
 // Sum the wavefronts' LDS j-side sums for sources [j0, j0 + n) (LDS index
 // j - lds0) and store them, negated, in row `row` of the j-side partials.
 template <int D>
-__device__ __forceinline__ void jside_flush(float (*jred)[kSymLDS], float* __restrict__ Bpj, int64_t row,
+__device__ __forceinline__ void jside_flush(float (*jred)[sym_row(D)], float* __restrict__ Bpj, int64_t row,
                                             int64_t P, int64_t off, int j0, int n, int lds0)
 {
-    constexpr int stride = kSymLDS / D;
+    constexpr int stride = sym_lds(D) / D;
     float* Bpj_row = Bpj + row * D * P;
 #pragma unroll
     for (int c = 0; c < D; ++c)
@@ -860,8 +871,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sym(const PairItem* __rest
                                                           const float* __restrict__ Ys, int64_t P,
                                                           float* __restrict__ Bp, float* __restrict__ Bpj)
 {
-    constexpr int stride = kSymLDS / D;  // LDS j-side capacity (sources) per component
-    __shared__ float jred[kWaves][kSymLDS];
+    constexpr int stride = sym_lds(D) / D;  // LDS j-side capacity (sources) per component
+    __shared__ float jred[kWaves][sym_row(D)];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const PairItem it = items[blockIdx.x];
@@ -896,9 +907,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sym(const PairItem* __rest
     const int own_end = min(tb0 + blk, g_end);
     const int start = diag ? tb0 : it.src0;
     const int end = diag ? g_end : it.src0 + it.nsrc;
-    const int piece = diag ? kSymLDS : stride;  // group x d <= kSymLDS: one piece
+    const int piece = diag ? sym_lds(D) : stride;  // group x d <= sym_lds(D): one piece
     if (diag) {
-        for (int q = lane; q < kSymLDS; q += 64) jred[wave][q] = 0.0f;
+        for (int q = lane; q < sym_lds(D); q += 64) jred[wave][q] = 0.0f;
     }
     int chunks = 0;
     for (int u0 = start; u0 < end; u0 += piece) {
