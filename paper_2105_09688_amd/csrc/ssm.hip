@@ -1551,8 +1551,9 @@ static ssm_status ensure_surrogate_buffers(ssm_ctx* c)
 {
     if (c->dmlp) return SSM_OK;
     ssm_status st;
-#define ALLOC2(ptr, bytes) do { st = dev_alloc(c, (void**)&(ptr), (bytes)); if (st != SSM_OK) return st; } while (0)
-    ALLOC2(c->dmlp, sizeof(MlpPacked));
+    // each buffer only once (a call after a failed one resumes); dmlp last, as
+    // it marks the set complete
+#define ALLOC2(ptr, bytes) do { if (!(ptr)) { st = dev_alloc(c, (void**)&(ptr), (bytes)); if (st != SSM_OK) return st; } } while (0)
     ALLOC2(c->surr, (size_t)c->d * c->P * sizeof(float));
     ALLOC2(c->surr_res, (size_t)c->d * c->P * sizeof(float));
     ALLOC2(c->rff_part, (size_t)c->nblk_tot * 2 * kRff * sizeof(double));
@@ -1560,7 +1561,6 @@ static ssm_status ensure_surrogate_buffers(ssm_ctx* c)
     ALLOC2(c->err_part, (size_t)c->nblk_tot * kErrStats * sizeof(double));
     ALLOC2(c->smean_part, (size_t)c->nblk_tot * kMaxD * sizeof(double));
     ALLOC2(c->smean, c->sys.size() * kMaxD * sizeof(float));
-#undef ALLOC2
     RffFreq* dfq = nullptr;
     HIP_TRY(hipMalloc((void**)&dfq, sizeof(RffFreq)));
     hipLaunchKernelGGL(k_rff_freq, dim3(1), dim3(64), 0, c->stream, c->coef.seed, c->d, c->ell, dfq);
@@ -1569,6 +1569,8 @@ static ssm_status ensure_surrogate_buffers(ssm_ctx* c)
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     (void)hipFree(dfq);
     if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("rff frequencies: ") + hipGetErrorString(he));
+    ALLOC2(c->dmlp, sizeof(MlpPacked));
+#undef ALLOC2
     return SSM_OK;
 }
 
