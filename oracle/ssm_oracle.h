@@ -125,6 +125,10 @@ int ssmo_run(const ssmo_cfg *cfg, int64_t stop_after, double *X_out, int64_t *st
 void ssmo_moments(int d, int64_t N, const double *X, double *mean, double *var);
 
 /* ---- learned-surrogate support (not in the paper; test infrastructure) ----
+ * The oracle evaluates and differentiates a network at given weights; it
+ * never trains one.  Trained weights are parity unpinned: they have no closed
+ * form, and only the exact check at run time and the strong-error comparison
+ * with the exact method judge a trained network.
  * Random Fourier feature frequencies: omega_k = Z(3, k, 0, 0)[0..d) / ell,
  * i.e. omega_k ~ N(0, I / ell^2), for which E cos(omega.(x - z)) =
  * exp(-|x - z|^2 / (2 ell^2)).  omega: [K][d]. */
