@@ -73,6 +73,9 @@ def _load():
                                      C.POINTER(C.c_int64), dp]
     lib.ssmo_step.argtypes = [C.POINTER(_Cfg), C.c_int32, C.c_int64, C.c_double, C.c_int64, dp, dp]
     lib.ssmo_step.restype = C.c_int
+    lib.ssmo_step_at.argtypes = [C.POINTER(_Cfg), C.c_int32, C.c_int64, C.c_double, C.c_int64, dp, C.c_int64,
+                                 C.POINTER(C.c_int64), dp]
+    lib.ssmo_step_at.restype = C.c_int
     lib.ssmo_init_state.argtypes = [C.POINTER(_Cfg), C.c_int32, C.c_int64, dp]
     lib.ssmo_run.argtypes = [C.POINTER(_Cfg), C.c_int64, dp, C.POINTER(C.c_int64)]
     lib.ssmo_run.restype = C.c_int
@@ -238,6 +241,22 @@ def step(w: dict, ens: int, h: float, n: int, X: np.ndarray):
     st = lib.ssmo_step(C.byref(c), ens, X.shape[1], h, n, _dp(X), _dp(Y))
     _check(st, "step")
     return X, Y
+
+
+def step_at(w: dict, ens: int, h: float, n: int, X: np.ndarray, idx) -> np.ndarray:
+    """One SSM step of one system from X_n, evaluated at the particles ``idx``
+    only: X_{n+1} at them, [d][len(idx)] (Y* is solved for every particle; the
+    O(N^2) term only at the sampled ones)."""
+    lib = _load()
+    keep = []
+    c = _cfg(w, keep)
+    X = _f64(np.atleast_2d(X))
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.zeros((X.shape[0], idx.size))
+    st = lib.ssmo_step_at(C.byref(c), ens, X.shape[1], h, n, _dp(X), idx.size,
+                          idx.ctypes.data_as(C.POINTER(C.c_int64)), _dp(out))
+    _check(st, "step_at")
+    return out
 
 
 def run(w: dict, stop_after: int = 0):

@@ -253,17 +253,10 @@ static int steps_per_increment(double h, double h_fine, int64_t *r)
     return SSMO_OK;
 }
 
-int ssmo_step(const ssmo_cfg *cfg, int32_t ens, int64_t N, double h, int64_t n,
-              double *X, double *Y_out)
+/* (2.3) for every particle: Y*_n^i = X_n^i + h v(t_n, Y*_n^i, mu^X_n). */
+static int implicit_all(const ssmo_cfg *cfg, int64_t N, double h, const double *X, double *Y)
 {
     const int d = cfg->d;
-    int64_t r;
-    if (steps_per_increment(h, cfg->h_fine, &r) != SSMO_OK) return SSMO_ERR_INVALID;
-    double *Y = (double *)malloc(sizeof(double) * (size_t)d * (size_t)N);
-    double *B = (double *)malloc(sizeof(double) * (size_t)d * (size_t)N);
-    if (!Y || !B) { free(Y); free(B); return SSMO_ERR_INVALID; }
-
-    /* (2.3): Y*_n^i = X_n^i + h v(t_n, Y*_n^i, mu^X_n) */
     double xbar[SSMO_MAX_D] = {0, 0, 0, 0};
     double m2 = 0.0;
     if (cfg->v_lam != 0.0) mean_of(d, N, X, xbar);
@@ -296,6 +289,35 @@ int ssmo_step(const ssmo_cfg *cfg, int32_t ens, int64_t N, double h, int64_t n,
         }
         for (int k = 0; k < d; ++k) Y[(int64_t)k * N + i] = yi[k];
     }
+    return status;
+}
+
+/* (2.4) for particle i, component k, given its drift term b (the O(N^2)
+ * part and b_c0 y + b_lam ybar already in it). */
+static double update_one(const ssmo_cfg *cfg, int64_t N, double h, const double *Y, const double *ybar,
+                         int64_t i, int k, double b, const double *dW)
+{
+    const int d = cfg->d;
+    const int64_t q = (int64_t)k * N + i;
+    /* the linear extension b_const + b_mat y + b_mean o ybar, terms in ascending l */
+    b += cfg->b_const[k];
+    for (int l = 0; l < d; ++l) b += cfg->b_mat[k * SSMO_MAX_D + l] * Y[(int64_t)l * N + i];
+    b += cfg->b_mean[k] * ybar[k];
+    double sig = cfg->s0[k] + cfg->s1[k] * Y[q] + cfg->s2[k] * ybar[k];
+    return (Y[q] + h * b) + sig * dW[k];
+}
+
+int ssmo_step(const ssmo_cfg *cfg, int32_t ens, int64_t N, double h, int64_t n,
+              double *X, double *Y_out)
+{
+    const int d = cfg->d;
+    int64_t r;
+    if (steps_per_increment(h, cfg->h_fine, &r) != SSMO_OK) return SSMO_ERR_INVALID;
+    double *Y = (double *)malloc(sizeof(double) * (size_t)d * (size_t)N);
+    double *B = (double *)malloc(sizeof(double) * (size_t)d * (size_t)N);
+    if (!Y || !B) { free(Y); free(B); return SSMO_ERR_INVALID; }
+
+    int status = implicit_all(cfg, N, h, X, Y);
     if (status != SSMO_OK) { free(Y); free(B); return status; }
 
     /* drift and diffusion at mu^Y_n */
@@ -308,22 +330,49 @@ int ssmo_step(const ssmo_cfg *cfg, int32_t ens, int64_t N, double h, int64_t n,
     for (int64_t i = 0; i < N; ++i) {
         double dW[SSMO_MAX_D];
         ssmo_brownian(cfg->seed, d, (uint64_t)i, (uint64_t)ens, (uint64_t)(n * r), r, cfg->h_fine, dW);
-        for (int k = 0; k < d; ++k) {
-            int64_t q = (int64_t)k * N + i;
-            double b = B[q];
-            /* the linear extension b_const + b_mat y + b_mean o ybar, terms in ascending l */
-            b += cfg->b_const[k];
-            for (int l = 0; l < d; ++l) b += cfg->b_mat[k * SSMO_MAX_D + l] * Y[(int64_t)l * N + i];
-            b += cfg->b_mean[k] * ybar[k];
-            double sig = cfg->s0[k] + cfg->s1[k] * Y[q] + cfg->s2[k] * ybar[k];
-            X[q] = (Y[q] + h * b) + sig * dW[k];
-        }
+        for (int k = 0; k < d; ++k) X[(int64_t)k * N + i] = update_one(cfg, N, h, Y, ybar, i, k, B[(int64_t)k * N + i], dW);
     }
     for (int64_t q = 0; q < (int64_t)d * N; ++q)
         if (!isfinite(X[q])) status = SSMO_ERR_NONFINITE;
     if (Y_out) memcpy(Y_out, Y, sizeof(double) * (size_t)d * (size_t)N);
     free(Y);
     free(B);
+    return status;
+}
+
+int ssmo_step_at(const ssmo_cfg *cfg, int32_t ens, int64_t N, double h, int64_t n, const double *X,
+                 int64_t n_idx, const int64_t *idx, double *X_at)
+{
+    const int d = cfg->d;
+    int64_t r;
+    if (steps_per_increment(h, cfg->h_fine, &r) != SSMO_OK) return SSMO_ERR_INVALID;
+    for (int64_t q = 0; q < n_idx; ++q)
+        if (idx[q] < 0 || idx[q] >= N) return SSMO_ERR_INVALID;
+    double *Y = (double *)malloc(sizeof(double) * (size_t)d * (size_t)N);
+    double *K = (double *)malloc(sizeof(double) * (size_t)d * (size_t)(n_idx > 0 ? n_idx : 1));
+    if (!Y || !K) { free(Y); free(K); return SSMO_ERR_INVALID; }
+    int status = implicit_all(cfg, N, h, X, Y);
+    if (status != SSMO_OK) { free(Y); free(K); return status; }
+    double ybar[SSMO_MAX_D];
+    mean_of(d, N, Y, ybar);
+    if (cfg->b_g != 0.0) {
+        ssmo_pair_sum_at(d, N, Y, cfg->b_ell, n_idx, idx, K);
+    } else {
+        for (int64_t q = 0; q < (int64_t)d * n_idx; ++q) K[q] = 0.0;
+    }
+    for (int64_t q = 0; q < n_idx; ++q) {
+        const int64_t i = idx[q];
+        double dW[SSMO_MAX_D];
+        ssmo_brownian(cfg->seed, d, (uint64_t)i, (uint64_t)ens, (uint64_t)(n * r), r, cfg->h_fine, dW);
+        for (int k = 0; k < d; ++k) {
+            /* the drift as ssmo_drift forms it: b_c0 y + b_lam ybar + b_g (pair term) */
+            const double b = cfg->b_c0 * Y[(int64_t)k * N + i] + cfg->b_lam * ybar[k] + cfg->b_g * K[(int64_t)k * n_idx + q];
+            X_at[(int64_t)k * n_idx + q] = update_one(cfg, N, h, Y, ybar, i, k, b, dW);
+            if (!isfinite(X_at[(int64_t)k * n_idx + q])) status = SSMO_ERR_NONFINITE;
+        }
+    }
+    free(Y);
+    free(K);
     return status;
 }
 

@@ -113,6 +113,14 @@ void ssmo_pair_sum(int d, int64_t N, const double *Y, double ell, double *K);
 int ssmo_step(const ssmo_cfg *cfg, int32_t ens, int64_t N, double h, int64_t n,
               double *X, double *Y_out);
 
+/* The same step at a sample of particles only: X_at[k][q] = X_{n+1}^{idx[q]}
+ * component k ([d][n_idx]) from X ([d][N], not modified).  Y* is solved for
+ * every particle (the measures need the whole cloud) and the O(N^2) term
+ * only at the sampled targets, with the same operations in the same order
+ * as ssmo_step. */
+int ssmo_step_at(const ssmo_cfg *cfg, int32_t ens, int64_t N, double h, int64_t n, const double *X,
+                 int64_t n_idx, const int64_t *idx, double *X_at);
+
 /* Initial condition X0^i_k = x0_mean[k] + x0_std[k] Z(1, i, 0, ens)_k. */
 void ssmo_init_state(const ssmo_cfg *cfg, int32_t ens, int64_t N, double *X);
 
