@@ -156,6 +156,53 @@ def test_full_size_single_gpu_steps_match_oracle(torch_cuda):
                 assert err <= tol, (prec, n, err)
 
 
+def _sample(N, k, seed):
+    idx = np.sort(np.random.default_rng(seed).choice(N, k, replace=False))
+    idx[0], idx[-1] = 0, N - 1
+    return idx
+
+
+@pytest.mark.parametrize("case", ["precision_d3_N2^18", "surrogate_d2_N2^20"])
+def test_full_size_first_step_sampled(torch_cuda, case):
+    """The d = 3 precision case (N = 2^18) and the d = 2 surrogate case
+    (N = 2^20) at full size in the library's default tiling: the first exact
+    step at 256 sampled particles against the oracle's step evaluated there
+    (its own X_0; Y* solved for every particle), FP32-compensated and FP64."""
+    w = W.precision_d3() if case.startswith("precision") else W.surrogate_d2()
+    N, ens, h = w["systems"][0]
+    idx = _sample(N, 256, 11)
+    _say(f"oracle step at 256 particles, {case}")
+    ref = oracle.step_at(w, ens, h, 0, oracle.init_state(w, ens, N), idx)
+    for prec, tol in (("fp32_kahan", FP32_TOL), ("fp64", FP64_TOL)):
+        _say(f"gpu first step {case} {prec}")
+        with _ssm(w, prec) as s:
+            s.step(1)
+            err = _err(s.state(0)[:, idx], ref)
+        _say(f"  max rel err {err:.3e}")
+        assert err <= tol, (case, prec, err)
+
+
+def test_full_size_batched_first_tick_sampled(torch_cuda):
+    """The batched case at full size (64 ensembles, N_e in [2^10, 2^16], five
+    step sizes, one context, shared Brownian windows): after the first tick,
+    on which every system steps, sampled particles of the largest and the
+    smallest ensemble at every step size against the oracle's step of that
+    system alone."""
+    w = W.batched(levels=(4, 5, 6, 7, 8))
+    systems = w["systems"]
+    sizes = sorted({sy[0] for sy in systems})
+    pick = [k for k, sy in enumerate(systems) if sy[0] in (sizes[0], sizes[-1])]
+    with _ssm(w, "fp32_kahan") as s:
+        s.step(1)
+        got = {k: s.state(k) for k in pick}
+    for k in pick:
+        N, ens, h = systems[k]
+        idx = _sample(N, 64, k)
+        _say(f"batched system {k}: N={N} ens={ens} h={h}")
+        ref = oracle.step_at(w, ens, h, 0, oracle.init_state(w, ens, N), idx)
+        assert _err(got[k][:, idx], ref) <= FP32_TOL, (k, N, h)
+
+
 # --------------------------------------------------------------------------- whole runs
 @pytest.fixture(scope="module")
 def c0_oracle():
