@@ -108,6 +108,26 @@ def test_init_rejects_incommensurate_levels():
     assert st == _lib.SSM_ERR_INVALID
 
 
+def test_init_rejects_empty_and_degenerate_inputs():
+    """Empty systems, no systems, a non-finite horizon or step, and a
+    component-wise cubic of the wrong sign are refused on the host."""
+    w = W.small_parity(n_ens=1, N=10)
+    w["systems"] = [(0, 0, 2.0 ** -8)]
+    st, msg = _init(w)
+    assert st == _lib.SSM_ERR_INVALID and "N out of range" in msg
+    st, msg = _init(W.small_parity(n_ens=1, N=10), n_sys=0)
+    assert st == _lib.SSM_ERR_INVALID
+    st, msg = _init(W.small_parity(n_ens=1, N=10), T=float("nan"))
+    assert st == _lib.SSM_ERR_INVALID and "T must be" in msg
+    w = W.small_parity(n_ens=1, N=10)
+    w["systems"] = [(10, 0, float("inf"))]
+    st, msg = _init(w)
+    assert st == _lib.SSM_ERR_INVALID
+    c_ak = (C.c_double * 4)(-1.0, 0.0, 0.0, 0.0)
+    st, msg = _init(W.small_parity(n_ens=1, N=10), v_componentwise=1, v_ak=c_ak)
+    assert st == _lib.SSM_ERR_INVALID and "v_ak" in msg
+
+
 def test_kernel_level_entry_points_validate_on_host():
     lib = _lib.load()
     assert lib.ssm_pair_sum(0, 10, 0, None, 1.0, None, None, 0, None) == _lib.SSM_ERR_INVALID
