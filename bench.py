@@ -185,6 +185,28 @@ def study_small(args, stream):
     return out
 
 
+def study_surrogate_tick(args, stream):
+    """Cost of one surrogate tick at the surrogate case's size (d=2, N=2^20,
+    FP32-compensated): one exact check tick, then 15 ticks on the network
+    (residual mode, every check accepted), timed with the library's events.
+    The weights are fresh (mlp_init): their accuracy does not change the work."""
+    from paper_2105_09688_amd import workloads as W
+    from paper_2105_09688_amd.ssm import SSM, mlp_init
+    w = W.surrogate_d2(N=args.N or 2 ** 20)
+    with SSM(w, precision="fp32_kahan", stream=stream) as s:
+        s.surrogate_load(mlp_init(w["d"], seed=0))
+        s.surrogate_enable(check_every=16, tol=1e9, mode="residual")
+        s.step(1)
+        s.sync()
+        t0 = time.perf_counter()
+        s.step(15)
+        s.sync()
+        dt = time.perf_counter() - t0
+        info = s.info()
+    return {"study": "surrogate_tick", "workload": f"d=2 N={w['systems'][0][0]} h=2^-9 fp32_kahan, residual mode",
+            "surrogate_ticks": info["surr_ticks"], "ms_per_surrogate_tick": dt / 15 * 1e3}
+
+
 def stability_beta(h, L_v, L_b, L_bt, L_s, L_st=0.0, L_vt=0.0):
     """beta of Theorem 2.9: sup_i E|X_n - Z_n|^2 <= (1 + beta h)^n sup_i E|X_0 - Z_0|^2,
     from the one-sided Lipschitz constant L_v of v, L_vt of its measure part,
@@ -513,7 +535,8 @@ def main():
     ap.add_argument("--precision", default="fp32_kahan", choices=["fp64", "fp32", "fp32_kahan"])
     ap.add_argument("--N", type=int, default=0)
     ap.add_argument("--train-steps", type=int, default=32000)
-    ap.add_argument("--study", choices=["none", "precision", "batched", "surrogate", "small", "families", "stability"],
+    ap.add_argument("--study", choices=["none", "precision", "batched", "surrogate", "surrogate_tick", "small", "families",
+                                        "stability"],
                     default="none",
                     help="run a study of another workload instead of the throughput line")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -540,7 +563,8 @@ def main():
     if args.study != "none":
         stream = torch.cuda.Stream()
         fn = {"precision": study_precision, "batched": study_batched, "surrogate": study_surrogate,
-              "small": study_small, "families": study_families, "stability": study_stability}[args.study]
+              "small": study_small, "families": study_families, "stability": study_stability,
+              "surrogate_tick": study_surrogate_tick}[args.study]
         print(json.dumps(fn(args, stream)), flush=True)
         return
     w = W.single_gpu_d1(N=args.N or 2 ** 16)
