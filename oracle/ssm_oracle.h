@@ -136,7 +136,7 @@ void ssmo_moments(int d, int64_t N, const double *X, double *mean, double *var);
  * The oracle evaluates and differentiates a network at given weights; it
  * never trains one.  Trained weights are parity unpinned: they have no closed
  * form, and only the exact check at run time and the strong-error comparison
- * with the exact method judge a trained network.
+ * with the exact method assess a trained network.
  * Random Fourier feature frequencies: omega_k = Z(3, k, 0, 0)[0..d) / ell,
  * i.e. omega_k ~ N(0, I / ell^2), for which E cos(omega.(x - z)) =
  * exp(-|x - z|^2 / (2 ell^2)).  omega: [K][d]. */
