@@ -32,7 +32,8 @@ def candidates(d: int, precision: str):
     schemes = ["ordered"] if precision == "fp64" else ["symmetric", "ordered"]
     out = []
     for scheme in schemes:
-        # symmetric: a target group (4 x 64 R particles) times d must fit 2048 LDS floats
+        # symmetric: a target group (4 x 64 R particles) times d must fit the LDS row
+        # (2048 floats; 3072 for d = 3, where R = 4 fits but measured slower than R = 2)
         Rs = {1: (2, 4, 8), 2: (1, 2, 4)}.get(d, (1, 2)) if scheme == "symmetric" else ((2, 4) if d == 1 else (1, 2))
         for R in Rs:
             for Lmul in (0.5, 1.0, 2.0):
