@@ -325,6 +325,23 @@ def test_step_at_sampled_particles_equals_the_full_step(oracle_mod):
         assert abs(mp.mpf(got) - xn) < 2e-15 * (1 + abs(xn)), (i, float(xn), got)
 
 
+def test_cucker_smale_velocities_flock_to_one(oracle_mod):
+    """Section 3.4.3: the velocities of the Cucker-Smale particles flock, V
+    converging to 1.  With the particle form of the mean terms (the reading
+    taken) the oracle's V at T = 2 has mean within 1e-2 of 1 and spread below
+    1e-3, from V_0 ~ N(1, 2); the opposite sign of the mean terms (the
+    coefficient line's form) leaves a spread above 1e-2, so the test tells
+    the two readings apart."""
+    w = W.cucker_smale(n_ens=2, N=300, h=2.0 ** -8, h_fine=2.0 ** -8)
+    for X in oracle_mod.run(w):
+        assert abs(X[0].mean() - 1.0) < 1e-2 and X[0].std() < 1e-3
+    w["systems"] = w["systems"][:1]
+    w["b"]["mat"] = [[2.0, 0.0], [1.0, 0.0]]
+    w["b"]["mean"] = [-2.0, 0.0]
+    w["sigma"]["s1"], w["sigma"]["s2"] = [4.0, 0.0], [-4.0, 0.0]
+    assert oracle_mod.run(w)[0][0].std() > 1e-2
+
+
 def test_initial_state_and_moments(oracle_mod):
     w = W.small_parity(n_ens=1, N=4000)
     X = oracle_mod.init_state(w, 0, 4000)
