@@ -369,6 +369,29 @@ def test_ou_mean_recursion_pathwise(oracle_mod):
         assert X.mean() == pytest.approx(mean, rel=1e-12, abs=1e-13)
 
 
+def test_affine_sigma_mean_recursion_pathwise(oracle_mod):
+    """Linear mean-field SDE with affine diffusion (v = rho x, b = lam E[X],
+    sigma = s1 x + s2 E[X], the form of the single-GPU coefficients' sigma):
+    averaging the update over the particles, with Y* = X / (1 - h rho), gives
+    per path
+      mean(X_{n+1}) = (1 + h lam) mean(Y*) + s1 mean(Y* dW) + s2 mean(Y*) mean(dW).
+    A sigma evaluated at X instead of Y*, or at Y*^i instead of mean(Y*) in
+    the s2 term, or a drift at mu^X, breaks it."""
+    rho, lam, s1, s2, h, N = -0.6, 0.5, 0.3, 0.2, 2.0 ** -5, 96
+    w = W.ou(rho=rho, lam=lam, eta=0.0, x0=0.8, x0_std=0.4, N=N, h=h, T=0.5, h_fine=2.0 ** -7)
+    w["sigma"] = dict(s0=[0.0], s1=[s1], s2=[s2])
+    X = oracle_mod.init_state(w, 0, N)[0]
+    r = 4
+    for n in range(16):
+        Y = X / (1.0 - h * rho)
+        ybar = Y.mean()
+        dW = np.array([math.sqrt(2.0 ** -7) * sum(oracle_mod.stream_normal(0, i, 0, n * r + m) for m in range(r))
+                       for i in range(N)])
+        m1 = (1 + h * lam) * ybar + s1 * np.mean(Y * dW) + s2 * ybar * dW.mean()
+        X = oracle_mod.step(w, 0, h, n, X[None, :])[0][0]
+        assert X.mean() == pytest.approx(m1, rel=1e-12, abs=1e-14)
+
+
 def test_weak_error_over_ensembles_follows_the_ou_mean_recursion(oracle_mod):
     """epsilon_1 (Section 3) of runs at h and at a finer h_ref on the same paths,
     over several ensembles: with v = rho x, b = lam E[X], sigma = eta the
