@@ -770,6 +770,18 @@ static ssm_status validate(const ssm_config* cfg)
     return SSM_OK;
 }
 
+// Largest j-side partial-sum buffer the symmetric scheme may take: 40 % of the
+// device's free memory, or 32 GiB if the runtime cannot say.
+static double jside_cap()
+{
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || free_b == 0) {
+        (void)hipGetLastError();
+        return 32.0 * (double)(1ull << 30);
+    }
+    return 0.4 * (double)free_b;
+}
+
 extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
 {
     if (!out) return fail(SSM_ERR_INVALID, "out is NULL");
@@ -895,10 +907,11 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
             c->nb_max = std::max(c->nb_max, nb);
         }
         // the symmetric scheme's j-side partials take groups x d x P floats; past
-        // 32 GiB the default falls back to ordered pairs
+        // 40 % of the device's free memory (115 GB of an idle MI355X's 288 GB;
+        // 32 GiB when it cannot be queried) the default falls back to ordered pairs
         const double jbytes = (double)c->nb_max * c->d * (double)c->P * sizeof(float);
-        if (!c->sym || jbytes <= 32.0 * (1ull << 30)) break;
-        if (cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "symmetric scheme needs more than 32 GiB of partial sums; raise targets_per_lane or use ordered pairs"); }
+        if (!c->sym || jbytes <= jside_cap()) break;
+        if (cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "symmetric scheme needs more than 40 % of the free device memory for its partial sums; raise targets_per_lane or use ordered pairs"); }
         c->sym = false;
     }
 

@@ -182,6 +182,26 @@ def test_full_size_first_step_sampled(torch_cuda, case):
         assert err <= tol, (case, prec, err)
 
 
+def test_maximum_size_symmetric_step_sampled(torch_cuda):
+    """d = 2, N = 2^21 (twice the surrogate case), the largest size the
+    symmetric scheme takes here: 64 GiB of j-side partial rows, within the
+    40 %-of-free-memory cap.  The first exact step at 128 sampled particles
+    against the oracle's step there, FP32-compensated."""
+    w = W.surrogate_d2(N=2 ** 21)
+    N, ens, h = w["systems"][0]
+    idx = _sample(N, 128, 21)
+    _say("oracle step at 128 particles, d=2 N=2^21")
+    ref = oracle.step_at(w, ens, h, 0, oracle.init_state(w, ens, N), idx)
+    with _ssm(w, "fp32_kahan") as s:
+        info = s.info()
+        _say(f"d=2 N=2^21: {info['pair_scheme']}, {info['device_bytes'] / 2 ** 30:.1f} GiB")
+        assert info["pair_scheme"] == "symmetric" and info["device_bytes"] > 64 * 2 ** 30
+        s.step(1)
+        err = _err(s.state(0)[:, idx], ref)
+    _say(f"  max rel err {err:.3e}")
+    assert err <= FP32_TOL
+
+
 def test_full_size_batched_first_tick_sampled(torch_cuda):
     """The batched case at full size (64 ensembles, N_e in [2^10, 2^16], five
     step sizes, one context, shared Brownian windows): after the first tick,
