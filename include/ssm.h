@@ -111,16 +111,17 @@ typedef struct {
     /* Tiling of the pairwise kernel; 0 = library default.  Results do not
      * depend on these beyond floating-point summation order. */
     int32_t targets_per_lane;  /* 1, 2, 4 or 8 (a target block is 64 x this; the symmetric scheme
-                                  takes groups of 4 blocks).  0: 4 for d = 1, 2 for d >= 2, halved
-                                  while one work item would exceed the average work of a resident
-                                  workgroup (small runs) */
+                                  takes groups of 4 blocks, whose 256 x this x d j-side sums must
+                                  fit 2048 floats (3072 at d = 3) or 1024 doubles (1536 at d = 3)).
+                                  0: 4 for d = 1, 2 for d >= 2, halved while one work item would
+                                  exceed the average work of a resident workgroup (small runs) and,
+                                  in the symmetric scheme, until the group fits */
     int32_t sources_per_item;  /* sources per work item: one wavefront's source range (ordered
                                   scheme, >= 64) or a range against a 4-block target group
                                   (symmetric, rounded up to a multiple of 16) */
-    int32_t pair_scheme;       /* 0: default (symmetric for the FP32 modes, ordered pairs for FP64);
+    int32_t pair_scheme;       /* 0: default (symmetric where the group fits, else ordered);
                                   1: every ordered pair (i, j) evaluated; 2: symmetric: each unordered
-                                  pair evaluated once, +q to i and -q to j (the kernel is odd),
-                                  FP32 modes only */
+                                  pair evaluated once, +q to i and -q to j (the kernel is odd) */
     int32_t graphs;            /* nonzero: each tick replays a HIP graph captured once per tick
                                   phase (tick % (h_max/h_min)); not used while profiling or with
                                   the surrogate enabled */

@@ -87,33 +87,43 @@ __global__ void k_implicit_plain(int64_t N, const double* __restrict__ X, double
 // kernel dispatch tables (d, R, precision)
 // ---------------------------------------------------------------------------
 // Symmetric scheme: one workgroup per item.
-template <int D>
+template <typename T, int D>
 static void launch_pair_sym_D(int R, bool kahan, int n, hipStream_t st, const PairItem* items, const SysDev* sys,
-                              const float* Ys, int64_t P, float* Bp, float* Bpj)
+                              const T* Ys, int64_t P, T* Bp, T* Bpj)
 {
     dim3 grid((unsigned)n), block(64 * kWaves);
-#define SSM_SYM_CASE(RR)                                                                                   \
-    case RR:                                                                                               \
-        if (kahan)                                                                                         \
-            hipLaunchKernelGGL((k_pair_sym<D, RR, true>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj);  \
-        else                                                                                               \
-            hipLaunchKernelGGL((k_pair_sym<D, RR, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj); \
+    if constexpr (sizeof(T) == sizeof(double)) {
+        // FP64: no compensation; R * d bounded by the LDS row
+        (void)kahan;
+        switch (R) {
+            case 1: hipLaunchKernelGGL((k_pair_sym<T, D, 1, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj); break;
+            case 2: if constexpr (D <= 3) hipLaunchKernelGGL((k_pair_sym<T, D, 2, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj); break;
+            case 4: if constexpr (D == 1) hipLaunchKernelGGL((k_pair_sym<T, D, 4, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj); break;
+            default: break;
+        }
+    } else {
+#define SSM_SYM_CASE(RR)                                                                                      \
+    case RR:                                                                                                  \
+        if (kahan)                                                                                            \
+            hipLaunchKernelGGL((k_pair_sym<T, D, RR, true>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj);  \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_pair_sym<T, D, RR, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj); \
         break;
-    switch (R) {
-        SSM_SYM_CASE(1)
-        SSM_SYM_CASE(2)
-        SSM_SYM_CASE(4)
-        SSM_SYM_CASE(8)
-        default: break;
-    }
+        switch (R) {
+            SSM_SYM_CASE(1)
+            SSM_SYM_CASE(2)
+            SSM_SYM_CASE(4)
+            SSM_SYM_CASE(8)
+            default: break;
+        }
 #undef SSM_SYM_CASE
+    }
 }
 
 template <typename T, int D>
 static void launch_pair_T(int R, bool kahan, dim3 grid, hipStream_t st, const PairItem* items,
-                          int n, const SysDev* sys, const T* Ys, int64_t P, T* Bp, float* Bpj)
+                          int n, const SysDev* sys, const T* Ys, int64_t P, T* Bp)
 {
-    (void)Bpj;
     dim3 block(64 * kWaves);
 #define SSM_PAIR_CASE(RR)                                                                      \
     case RR:                                                                                   \
@@ -133,31 +143,32 @@ static void launch_pair_T(int R, bool kahan, dim3 grid, hipStream_t st, const Pa
 }
 
 // Pair kernel launch: ordered scheme one wavefront per item (kWaves items per
-// workgroup), symmetric scheme (FP32 only) one workgroup per item.
+// workgroup), symmetric scheme one workgroup per item.
 template <typename T>
 static void launch_pair(int d, int R, bool kahan, dim3 grid, hipStream_t st, const PairItem* items,
-                        int n, const SysDev* sys, const T* Ys, int64_t P, T* Bp, float* Bpj, bool sym = false)
+                        int n, const SysDev* sys, const T* Ys, int64_t P, T* Bp, T* Bpj, bool sym)
 {
-    if constexpr (sizeof(T) == sizeof(float)) {
-        if (sym) {
-            switch (d) {
-                case 1: launch_pair_sym_D<1>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
-                case 2: launch_pair_sym_D<2>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
-                case 3: launch_pair_sym_D<3>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
-                case 4: launch_pair_sym_D<4>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
-                default: break;
-            }
-            return;
+    if (sym) {
+        switch (d) {
+            case 1: launch_pair_sym_D<T, 1>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
+            case 2: launch_pair_sym_D<T, 2>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
+            case 3: launch_pair_sym_D<T, 3>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
+            case 4: launch_pair_sym_D<T, 4>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
+            default: break;
         }
+        return;
     }
     switch (d) {
-        case 1: launch_pair_T<T, 1>(R, kahan, grid, st, items, n, sys, Ys, P, Bp, Bpj); break;
-        case 2: launch_pair_T<T, 2>(R, kahan, grid, st, items, n, sys, Ys, P, Bp, Bpj); break;
-        case 3: launch_pair_T<T, 3>(R, kahan, grid, st, items, n, sys, Ys, P, Bp, Bpj); break;
-        case 4: launch_pair_T<T, 4>(R, kahan, grid, st, items, n, sys, Ys, P, Bp, Bpj); break;
+        case 1: launch_pair_T<T, 1>(R, kahan, grid, st, items, n, sys, Ys, P, Bp); break;
+        case 2: launch_pair_T<T, 2>(R, kahan, grid, st, items, n, sys, Ys, P, Bp); break;
+        case 3: launch_pair_T<T, 3>(R, kahan, grid, st, items, n, sys, Ys, P, Bp); break;
+        case 4: launch_pair_T<T, 4>(R, kahan, grid, st, items, n, sys, Ys, P, Bp); break;
         default: break;
     }
 }
+
+// A symmetric target group (kWaves x 64 R particles) times d fits the LDS row.
+static bool sym_fits(bool fp64, int R, int d) { return (int64_t)64 * R * kWaves * d <= sym_lds_for(fp64, d); }
 
 #define SSM_DISPATCH_D(d, KERNEL_CALL)       \
     switch (d) {                             \
@@ -210,7 +221,7 @@ struct ssm_ctx {
     void* Y = nullptr;
     void* Ys = nullptr;
     void* Bp = nullptr;        // i-side partials [max_splits][d][P] in the storage precision
-    float* Bpj = nullptr;      // symmetric scheme: j-side partials [nb_max][d][P]
+    void* Bpj = nullptr;       // symmetric scheme: j-side partials [nb_max][d][P] (pair precision)
     double* pairsum = nullptr; // [d][P] scaled pair term of the last exact tick (k_combine)
     bool sym = false;          // symmetric pair scheme (FP32 modes)
     int64_t nb_max = 0;
@@ -547,7 +558,7 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
             if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
         }
         launch_pair<T>(d, c->R, c->prec == SSM_FP32_KAHAN, grid, c->stream, c->dpair + c->pair_off[ph],
-                       (int)np, c->dsys, Ys, c->P, (T*)c->Bp, c->Bpj, c->sym);
+                       (int)np, c->dsys, Ys, c->P, (T*)c->Bp, (T*)c->Bpj, c->sym);
         HIP_TRY(hipGetLastError());
         if (prof) {
             if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
@@ -575,7 +586,7 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
 #define SSM_BM(LPV)                                                                                                   \
     if (comb) {                                                                                                       \
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_prep<T, D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, ncb, items,     \
-                                             c->dsys, c->coef, c->P, (const T*)c->Bp, c->Bpj, c->pairsum, c->tick,   \
+                                             c->dsys, c->coef, c->P, (const T*)c->Bp, (const T*)c->Bpj, c->pairsum, c->tick, \
                                              tdev, (const double*)c->win, c->dW));                                    \
     } else {                                                                                                          \
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_brownian_sum<D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, items,    \
@@ -877,16 +888,18 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     is_int_ratio(cfg->T, h_min, &c->ticks_total);
 
     // pair tiling: R targets per lane, L sources per item, scheme
-    if (cfg->pair_scheme == 2 && c->prec == SSM_FP64) { free_ctx(c); return fail(SSM_ERR_INVALID, "the symmetric pair scheme is FP32 only"); }
-    c->sym = c->prec != SSM_FP64 && cfg->pair_scheme != 1;
+    const bool f64 = c->prec == SSM_FP64;
+    c->sym = cfg->pair_scheme != 1;
     {
         std::vector<int64_t> Ns;
         for (auto& S : c->sys) Ns.push_back(S.N);
         c->R = cfg->targets_per_lane > 0 ? cfg->targets_per_lane : default_R(c->d, Ns, c->sym);
     }
-    if (c->sym && (int64_t)64 * c->R * kWaves * c->d > sym_lds(c->d)) {
-        // a target group's j-side sums must fit the kernel's LDS buffer
-        if (cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "symmetric scheme: targets_per_lane too large for this d (64 x R x 4 x d must be <= " + std::to_string(sym_lds(c->d)) + ")"); }
+    // a target group's j-side sums must fit the kernel's LDS buffer
+    if (c->sym && cfg->targets_per_lane <= 0)
+        while (c->R > 1 && !sym_fits(f64, c->R, c->d)) c->R /= 2;
+    if (c->sym && !sym_fits(f64, c->R, c->d)) {
+        if (cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "symmetric scheme: targets_per_lane too large for this d and precision (64 x R x 4 x d must be <= " + std::to_string(sym_lds_for(f64, c->d)) + ")"); }
         c->sym = false;
     }
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -906,10 +919,10 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
             c->max_splits = std::max(c->max_splits, c->sys[s].splits);
             c->nb_max = std::max(c->nb_max, nb);
         }
-        // the symmetric scheme's j-side partials take groups x d x P floats; past
+        // the symmetric scheme's j-side partials take groups x d x P elements of the pair precision; past
         // 40 % of the device's free memory (115 GB of an idle MI355X's 288 GB;
         // 32 GiB when it cannot be queried) the default falls back to ordered pairs
-        const double jbytes = (double)c->nb_max * c->d * (double)c->P * sizeof(float);
+        const double jbytes = (double)c->nb_max * c->d * (double)c->P * elt(c->prec);
         if (!c->sym || jbytes <= jside_cap()) break;
         if (cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "symmetric scheme needs more than 40 % of the free device memory for its partial sums; raise targets_per_lane or use ordered pairs"); }
         c->sym = false;
@@ -991,7 +1004,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     ALLOC(c->Ys, field);
     ALLOC(c->Bp, c->has_pair ? (size_t)c->max_splits * c->d * c->P * elt(c->prec) : 0);
     ALLOC(c->pairsum, c->has_pair ? (size_t)c->d * c->P * sizeof(double) : 0);
-    ALLOC(c->Bpj, (c->has_pair && c->sym) ? (size_t)c->nb_max * c->d * c->P * sizeof(float) : 0);
+    ALLOC(c->Bpj, (c->has_pair && c->sym) ? (size_t)c->nb_max * c->d * c->P * elt(c->prec) : 0);
     ALLOC(c->psumX, 2 * (size_t)(c->d + 1) * c->nblk_tot * sizeof(double));
     ALLOC(c->psumY, 2 * (size_t)c->d * c->nblk_tot * sizeof(double));
     ALLOC(c->dsys, sd.size() * sizeof(SysDev));
@@ -1408,9 +1421,9 @@ struct KPlan {
 static KPlan kernel_plan(int32_t d, int64_t N, int32_t precision)
 {
     KPlan p{};
-    p.sym = precision != SSM_FP64;
+    p.sym = true;
     p.R = default_R(d, std::vector<int64_t>{N}, p.sym);
-    if (p.sym && (int64_t)64 * p.R * kWaves * d > sym_lds(d)) p.sym = false;
+    while (p.R > 1 && !sym_fits(precision == SSM_FP64, p.R, d)) p.R /= 2;
     p.L = default_L(std::vector<int64_t>{N}, p.R, p.sym, d);
     std::vector<std::pair<int64_t, PairItem>> tmp;
     p.isplits = plan_system(0, N, p.R, p.sym, p.L, tmp, &p.nb);
@@ -1424,7 +1437,7 @@ static size_t kernel_ws_bytes(int32_t d, int64_t N, int32_t precision, const KPl
 {
     return align256(sizeof(SysDev)) + align256(p.items.size() * sizeof(PairItem)) +
            align256((size_t)d * N * elt(precision)) + align256((size_t)p.isplits * d * N * elt(precision)) +
-           align256((size_t)std::max<int64_t>(p.nb, 1) * d * N * sizeof(float));
+           align256((size_t)std::max<int64_t>(p.nb, 1) * d * N * elt(precision));
 }
 
 extern "C" size_t ssm_pair_workspace_bytes(int32_t d, int64_t N, int32_t precision)
@@ -1462,7 +1475,7 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
     PairItem* dI = (PairItem*)w; w += align256(plan.items.size() * sizeof(PairItem));
     void* dYs = (void*)w; w += align256((size_t)d * N * elt(precision));
     void* dBp = (void*)w; w += align256((size_t)plan.isplits * d * N * elt(precision));
-    float* dBpj = (float*)w;
+    void* dBpj = (void*)w;
     HIP_TRY(hipMemcpyAsync(dS, &S, sizeof(S), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dI, plan.items.data(), plan.items.size() * sizeof(PairItem), hipMemcpyHostToDevice, st));
     const int64_t n = (int64_t)d * N;
@@ -1470,18 +1483,18 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
     const dim3 gp((unsigned)(plan.sym ? plan.items.size() : (plan.items.size() + kWaves - 1) / kWaves));
     if (precision == SSM_FP64) {
         hipLaunchKernelGGL(k_scale_copy<double>, g1, dim3(256), 0, st, (const double*)Y, (double*)dYs, n, c);
-        launch_pair<double>(d, plan.R, false, gp, st, dI, (int)plan.items.size(), dS, (const double*)dYs, N, (double*)dBp, dBpj);
+        launch_pair<double>(d, plan.R, false, gp, st, dI, (int)plan.items.size(), dS, (const double*)dYs, N, (double*)dBp, (double*)dBpj, plan.sym);
     } else {
         hipLaunchKernelGGL(k_scale_copy<float>, g1, dim3(256), 0, st, (const float*)Y, (float*)dYs, n, c);
-        launch_pair<float>(d, plan.R, precision == SSM_FP32_KAHAN, gp, st, dI, (int)plan.items.size(), dS, (const float*)dYs, N, (float*)dBp, dBpj, plan.sym);
+        launch_pair<float>(d, plan.R, precision == SSM_FP32_KAHAN, gp, st, dI, (int)plan.items.size(), dS, (const float*)dYs, N, (float*)dBp, (float*)dBpj, plan.sym);
     }
     const dim3 gc((unsigned)(4 * ((N + kBlk - 1) / kBlk)));
     if (precision == SSM_FP64) {
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<double, D>), gc, dim3(64 * kCombineWaves), 0, st,
-                                             (const BlkItem*)nullptr, dS, N, (const double*)dBp, dBpj, K));
+                                             (const BlkItem*)nullptr, dS, N, (const double*)dBp, (const double*)dBpj, K));
     } else {
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<float, D>), gc, dim3(64 * kCombineWaves), 0, st,
-                                             (const BlkItem*)nullptr, dS, N, (const float*)dBp, dBpj, K));
+                                             (const BlkItem*)nullptr, dS, N, (const float*)dBp, (const float*)dBpj, K));
     }
     HIP_TRY(hipGetLastError());
     // the host-side plan must outlive the asynchronous copies
@@ -1644,21 +1657,21 @@ extern "C" ssm_status ssm_surrogate_samples(ssm_ctx* c, int32_t sys, int64_t n, 
     const int64_t np = c->pair_cnt[0], nb = c->blk_cnt[0];
     const int d = c->d;
     if (c->prec == SSM_FP64) {
-        launch_pair<double>(d, c->R, false, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const double*)c->Ys, c->P, (double*)c->Bp, c->Bpj);
+        launch_pair<double>(d, c->R, false, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const double*)c->Ys, c->P, (double*)c->Bp, (double*)c->Bpj, c->sym);
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<double, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const double*)c->Y, c->rff, c->rff_part));
     } else {
-        launch_pair<float>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const float*)c->Ys, c->P, (float*)c->Bp, c->Bpj, c->sym);
+        launch_pair<float>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const float*)c->Ys, c->P, (float*)c->Bp, (float*)c->Bpj, c->sym);
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<float, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const float*)c->Y, c->rff, c->rff_part));
     }
     HIP_TRY(hipGetLastError());
     if (c->prec == SSM_FP64) {
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<double, D>), dim3((unsigned)(nb * 4)), dim3(64 * kCombineWaves), 0,
                                              c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const double*)c->Bp,
-                                             c->Bpj, c->pairsum));
+                                             (const double*)c->Bpj, c->pairsum));
     } else {
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<float, D>), dim3((unsigned)(nb * 4)), dim3(64 * kCombineWaves), 0,
                                              c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const float*)c->Bp,
-                                             c->Bpj, c->pairsum));
+                                             (const float*)c->Bpj, c->pairsum));
     }
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_rff_final, dim3((unsigned)c->sys_list_cnt[0], 2 * kRff), dim3(kBlk), 0, c->stream, c->dsys_list + c->sys_list_off[0], c->dsys, c->rff_part, c->mom);

@@ -40,6 +40,11 @@ constexpr int kKahanChunk = 256;
 // the store: 1 % faster at d = 3, slower at d = 1, 2).
 __host__ __device__ constexpr int sym_lds(int D) { return D == 3 ? 3072 : 2048; }
 __host__ __device__ constexpr int sym_row(int D) { return sym_lds(D) + (D == 3 ? 64 : 0); }
+// The same buffer in FP64: 1024 doubles (1536 at d = 3, where a target group
+// of 2 x 256 particles fills it), sources per flush a multiple of 16.
+__host__ __device__ constexpr int sym_lds_f64(int D) { return D == 3 ? 1536 : 1024; }
+// The buffer's capacity for a pair precision (fp64 or float storage).
+__host__ __device__ constexpr int sym_lds_for(bool fp64, int D) { return fp64 ? sym_lds_f64(D) : sym_lds(D); }
 
 struct SysDev {
     int64_t off;        // first slot of the system in [P]
@@ -123,7 +128,7 @@ __device__ __forceinline__ double exp2_fast<double>(double x)
 
 // The partial-sum rows of particle i of system S, in their fixed order:
 // ni i-side rows (Bp[q][k][P] in the storage precision: the target tile's or group's work
-// items) then, in the symmetric scheme, nj j-side rows (floats, Bpj[a][k][P]:
+// items) then, in the symmetric scheme, nj j-side rows (same precision, Bpj[a][k][P]:
 // every earlier group and the particle's own group).
 struct PairRows {
     int ni, nj;
@@ -140,7 +145,7 @@ __device__ __forceinline__ PairRows pair_rows(const SysDev& S, int i)
 // Sum, in ascending order, of the rows r = w, w + W, w + 2W, ... (r < ni + nj)
 // of component k at slot; loads are issued four at a time.
 template <int D, int W, typename PT>
-__device__ __forceinline__ double sum_rows(const PT* __restrict__ Bp, const float* __restrict__ Bpj,
+__device__ __forceinline__ double sum_rows(const PT* __restrict__ Bp, const PT* __restrict__ Bpj,
                                            PairRows pr, int k, int64_t P, int64_t slot, int w)
 {
     double acc = 0.0;
@@ -155,7 +160,7 @@ __device__ __forceinline__ double sum_rows(const PT* __restrict__ Bp, const floa
     for (; r < pr.ni; r += W) acc += (double)Bp[((int64_t)r * D + k) * P + slot];
     int q = r - pr.ni;
     for (; q + 3 * W < pr.nj; q += 4 * W) {
-        float v[4];
+        PT v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) v[u] = Bpj[((int64_t)(q + u * W) * D + k) * P + slot];
 #pragma unroll
@@ -178,7 +183,7 @@ constexpr int kCombineWaves = 4;
 template <typename PT, int D>
 __device__ __forceinline__ void combine_block(int vb, const BlkItem* __restrict__ items,
                                               const SysDev* __restrict__ sys, int64_t P, const PT* __restrict__ Bp,
-                                              const float* __restrict__ Bpj, double* __restrict__ out,
+                                              const PT* __restrict__ Bpj, double* __restrict__ out,
                                               double (*part)[D][64])
 {
     const int q4 = vb & 3;
@@ -208,7 +213,7 @@ template <typename PT, int D>
 __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(const BlkItem* __restrict__ items,
                                                                const SysDev* __restrict__ sys, int64_t P,
                                                                const PT* __restrict__ Bp,
-                                                               const float* __restrict__ Bpj,
+                                                               const PT* __restrict__ Bpj,
                                                                double* __restrict__ out)
 {
     __shared__ double part[kCombineWaves][D][64];
@@ -624,7 +629,7 @@ __global__ __launch_bounds__(kBlk) void k_bm_window(const BlkItem* __restrict__ 
 template <typename PT, int D, int LP>
 __global__ __launch_bounds__(kBlk) void k_prep(int n_combine, const BlkItem* __restrict__ items,
                                                const SysDev* __restrict__ sys, Coef cf, int64_t P,
-                                               const PT* __restrict__ Bp, const float* __restrict__ Bpj,
+                                               const PT* __restrict__ Bp, const PT* __restrict__ Bpj,
                                                double* __restrict__ pairsum, int64_t tick_arg,
                                                const int64_t* __restrict__ tick_dev, const double* __restrict__ win,
                                                double* __restrict__ dW)
@@ -718,93 +723,157 @@ __device__ __forceinline__ float dpp_ror(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + N, 0xF, 0xF, false));
 }
 
-template <int D, int R, int K, bool JSIDE>
-__device__ __forceinline__ void sym_step(const float (&s)[D], const float (&yi)[R][D], float (&acc)[R][D],
-                                         float (&accj)[16][D])
+// A double through the same rotation: its two 32-bit halves move alike.
+template <int N>
+__device__ __forceinline__ double dpp_ror(double v)
 {
-    float sk[D];
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x120 + N, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x120 + N, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+
+// LDS j-side row of the symmetric kernel in elements of T (FP64 rows carry
+// no dummy tail: their stores take the branch).
+template <typename T, int D>
+__host__ __device__ constexpr int sym_lds_t() { return sym_lds_for(sizeof(T) == 8, D); }
+template <typename T, int D>
+__host__ __device__ constexpr int sym_row_t() { return sizeof(T) == 8 ? sym_lds_f64(D) : sym_row(D); }
+
+template <typename T, int D, int R, int K, bool JSIDE>
+__device__ __forceinline__ void sym_step(const T (&s)[D], const T (&yi)[R][D], T (&acc)[R][D],
+                                         T (&accj)[16][D])
+{
+    T sk[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) sk[c] = (K == 0) ? s[c] : dpp_ror<(16 - K) & 15>(s[c]);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        float z[D];
-        float t = 0.0f;
+        T z[D];
+        T t = (T)0;
 #pragma unroll
         for (int c = 0; c < D; ++c) {
             z[c] = sk[c] - yi[r][c];
-            t = (c == 0) ? z[c] * z[c] : fmaf(z[c], z[c], t);
+            t = (c == 0) ? z[c] * z[c] : fma_t(z[c], z[c], t);
         }
-        const float e = __builtin_amdgcn_exp2f(-t);
+        const T e = exp2_fast<T>(-t);
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            acc[r][c] = fmaf(z[c], e, acc[r][c]);
-            if constexpr (JSIDE) accj[K][c] = fmaf(z[c], e, accj[K][c]);
+            acc[r][c] = fma_t(z[c], e, acc[r][c]);
+            if constexpr (JSIDE) accj[K][c] = fma_t(z[c], e, accj[K][c]);
         }
     }
 }
 
-template <int D, int K>
-__device__ __forceinline__ void sym_route(const float (&accj)[16][D], float (&tot)[D])
+// One step of the FP64 form: the same pair terms as sym_step against the
+// lane's current source sk, with one j-side accumulator that travels with it.
+template <typename T, int D, int R, bool JSIDE>
+__device__ __forceinline__ void sym_eval(const T (&sk)[D], const T (&yi)[R][D], T (&acc)[R][D], T (&aj)[D])
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        T z[D];
+        T t = (T)0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            z[c] = sk[c] - yi[r][c];
+            t = (c == 0) ? z[c] * z[c] : fma_t(z[c], z[c], t);
+        }
+        const T e = exp2_fast<T>(-t);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            acc[r][c] = fma_t(z[c], e, acc[r][c]);
+            if constexpr (JSIDE) aj[c] = fma_t(z[c], e, aj[c]);
+        }
+    }
+}
+
+template <typename T, int D, int K>
+__device__ __forceinline__ void sym_route(const T (&accj)[16][D], T (&tot)[D])
 {
 #pragma unroll
     for (int c = 0; c < D; ++c) tot[c] += dpp_ror<K>(accj[K][c]);
 }
 
-// The chunk's j-side sums (before the sign flip) go to out[c * (sym_lds(D) / D) + j + jshift]
+// The chunk's j-side sums (before the sign flip) go to out[c * (sym_lds_t<T, D>() / D) + j + jshift]
 // for the chunk's valid sources j when write_j holds.  JSIDE = false drops
 // the j-side arithmetic at compile time.
-template <int D, int R, bool JSIDE = true>
-__device__ __forceinline__ void sym_chunk(const float* __restrict__ base, int64_t P, int c0, int c_end,
-                                          const float (&yi)[R][D], float (&acc)[R][D], float* __restrict__ out,
+template <typename T, int D, int R, bool JSIDE = true>
+__device__ __forceinline__ void sym_chunk(const T* __restrict__ base, int64_t P, int c0, int c_end,
+                                          const T (&yi)[R][D], T (&acc)[R][D], T* __restrict__ out,
                                           int64_t jshift, bool write_j = true)
 {
     const int lane = threadIdx.x & 63;
     const int p = lane & 15;
     const int j = c0 + p;
     const bool vj = j < c_end;
-    float s[D];
+    T s[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) s[c] = vj ? base[c * P + j] : 1e15f;
-    float accj[16][D];
+    for (int c = 0; c < D; ++c) s[c] = vj ? base[c * P + j] : (T)1e15;
+    T tot[D];
+    if constexpr (sizeof(T) == 8) {
+        // FP64: one j-side accumulator per component travels with its source
+        // (both move one lane per step; the 16th move brings both home) in
+        // place of 16 per-step accumulators and the route.  The steps stay a
+        // loop: unrolled, the scheduler interleaves the 16 exponentials and
+        // runs out of registers (d = 3, R = 2: 49.6 -> 38.1 ms per launch at
+        // N = 2^18; d = 1, R = 4: 1.82 -> 1.48 ms at N = 2^16).
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
+        for (int c = 0; c < D; ++c) tot[c] = (T)0;
+#pragma unroll 1
+        for (int k = 0; k < 16; ++k) {
+            sym_eval<T, D, R, JSIDE>(s, yi, acc, tot);
 #pragma unroll
-        for (int c = 0; c < D; ++c) accj[k][c] = 0.0f;
-    sym_step<D, R, 0, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 1, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 2, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 3, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 4, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 5, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 6, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 7, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 8, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 9, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 10, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 11, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 12, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 13, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 14, JSIDE>(s, yi, acc, accj);
-    sym_step<D, R, 15, JSIDE>(s, yi, acc, accj);
-    if constexpr (!JSIDE) return;
-    float tot[D];
+            for (int c = 0; c < D; ++c) {
+                s[c] = dpp_ror<15>(s[c]);
+                if constexpr (JSIDE) tot[c] = dpp_ror<15>(tot[c]);
+            }
+        }
+        if constexpr (!JSIDE) return;
+    } else {
+        T accj[16][D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) tot[c] = accj[0][c];
-    sym_route<D, 1>(accj, tot);
-    sym_route<D, 2>(accj, tot);
-    sym_route<D, 3>(accj, tot);
-    sym_route<D, 4>(accj, tot);
-    sym_route<D, 5>(accj, tot);
-    sym_route<D, 6>(accj, tot);
-    sym_route<D, 7>(accj, tot);
-    sym_route<D, 8>(accj, tot);
-    sym_route<D, 9>(accj, tot);
-    sym_route<D, 10>(accj, tot);
-    sym_route<D, 11>(accj, tot);
-    sym_route<D, 12>(accj, tot);
-    sym_route<D, 13>(accj, tot);
-    sym_route<D, 14>(accj, tot);
-    sym_route<D, 15>(accj, tot);
+        for (int k = 0; k < 16; ++k)
+#pragma unroll
+            for (int c = 0; c < D; ++c) accj[k][c] = (T)0;
+        sym_step<T, D, R, 0, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 1, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 2, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 3, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 4, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 5, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 6, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 7, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 8, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 9, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 10, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 11, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 12, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 13, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 14, JSIDE>(s, yi, acc, accj);
+        sym_step<T, D, R, 15, JSIDE>(s, yi, acc, accj);
+        if constexpr (!JSIDE) return;
+#pragma unroll
+        for (int c = 0; c < D; ++c) tot[c] = accj[0][c];
+        sym_route<T, D, 1>(accj, tot);
+        sym_route<T, D, 2>(accj, tot);
+        sym_route<T, D, 3>(accj, tot);
+        sym_route<T, D, 4>(accj, tot);
+        sym_route<T, D, 5>(accj, tot);
+        sym_route<T, D, 6>(accj, tot);
+        sym_route<T, D, 7>(accj, tot);
+        sym_route<T, D, 8>(accj, tot);
+        sym_route<T, D, 9>(accj, tot);
+        sym_route<T, D, 10>(accj, tot);
+        sym_route<T, D, 11>(accj, tot);
+        sym_route<T, D, 12>(accj, tot);
+        sym_route<T, D, 13>(accj, tot);
+        sym_route<T, D, 14>(accj, tot);
+        sym_route<T, D, 15>(accj, tot);
+    }
 #pragma unroll
     for (int c = 0; c < D; ++c) {
         // across the rows through the LDS crossbar (ds_bpermute runs beside the
@@ -812,13 +881,13 @@ __device__ __forceinline__ void sym_chunk(const float* __restrict__ base, int64_
         tot[c] += __shfl_xor(tot[c], 16, 64);
         tot[c] += __shfl_xor(tot[c], 32, 64);
     }
-    if constexpr (D == 3) {
+    if constexpr (D == 3 && sizeof(T) == 4) {
         const bool wr = write_j && lane < 16 && vj;
 #pragma unroll
         for (int c = 0; c < D; ++c) out[wr ? (int)(c * (sym_lds(D) / D) + j + jshift) : sym_lds(D) + lane] = tot[c];
     } else if (write_j && lane < 16 && vj) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) out[c * (sym_lds(D) / D) + j + jshift] = tot[c];
+        for (int c = 0; c < D; ++c) out[c * (sym_lds_t<T, D>() / D) + j + jshift] = tot[c];
     }
 }
 
@@ -834,57 +903,57 @@ __device__ __forceinline__ void sym_chunk(const float* __restrict__ base, int64_
 //    the group; i-side partial `split`, j-side row a.
 // j-side sums pass through LDS (sym_lds(d) / d sources at a time) and are added
 // over the wavefronts in a fixed order before they are written.
-template <int D, int R, bool KAHAN>
-__device__ __forceinline__ void kahan_fold(float (&acc)[R][D], float (&hi)[R][D], float (&lo)[R][D])
+template <typename T, int D, int R, bool KAHAN>
+__device__ __forceinline__ void kahan_fold(T (&acc)[R][D], T (&hi)[R][D], T (&lo)[R][D])
 {
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            const float a = acc[r][c];
-            const float sm = hi[r][c] + a;
-            lo[r][c] += (fabsf(hi[r][c]) >= fabsf(a)) ? (hi[r][c] - sm) + a : (a - sm) + hi[r][c];
+            const T a = acc[r][c];
+            const T sm = hi[r][c] + a;
+            lo[r][c] += (fabs(hi[r][c]) >= fabs(a)) ? (hi[r][c] - sm) + a : (a - sm) + hi[r][c];
             hi[r][c] = sm;
-            acc[r][c] = 0.0f;
+            acc[r][c] = (T)0;
         }
 }
 
 // Sum the wavefronts' LDS j-side sums for sources [j0, j0 + n) (LDS index
 // j - lds0) and store them, negated, in row `row` of the j-side partials.
-template <int D>
-__device__ __forceinline__ void jside_flush(float (*jred)[sym_row(D)], float* __restrict__ Bpj, int64_t row,
+template <typename T, int D>
+__device__ __forceinline__ void jside_flush(T (*jred)[(sym_row_t<T, D>())], T* __restrict__ Bpj, int64_t row,
                                             int64_t P, int64_t off, int j0, int n, int lds0)
 {
-    constexpr int stride = sym_lds(D) / D;
-    float* Bpj_row = Bpj + row * D * P;
+    constexpr int stride = sym_lds_t<T, D>() / D;
+    T* Bpj_row = Bpj + row * D * P;
 #pragma unroll
     for (int c = 0; c < D; ++c)
         for (int jj = threadIdx.x; jj < n; jj += 64 * kWaves) {
             const int li = c * stride + (j0 + jj - lds0);
-            float v = jred[0][li];
+            T v = jred[0][li];
 #pragma unroll
             for (int w = 1; w < kWaves; ++w) v += jred[w][li];
             Bpj_row[c * P + off + j0 + jj] = -v;
         }
 }
 
-template <int D, int R, bool KAHAN>
+template <typename T, int D, int R, bool KAHAN>
 __global__ __launch_bounds__(64 * kWaves) void k_pair_sym(const PairItem* __restrict__ items,
                                                           const SysDev* __restrict__ sys,
-                                                          const float* __restrict__ Ys, int64_t P,
-                                                          float* __restrict__ Bp, float* __restrict__ Bpj)
+                                                          const T* __restrict__ Ys, int64_t P,
+                                                          T* __restrict__ Bp, T* __restrict__ Bpj)
 {
-    constexpr int stride = sym_lds(D) / D;  // LDS j-side capacity (sources) per component
-    __shared__ float jred[kWaves][sym_row(D)];
+    constexpr int stride = sym_lds_t<T, D>() / D;  // LDS j-side capacity (sources) per component
+    __shared__ T jred[kWaves][(sym_row_t<T, D>())];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const PairItem it = items[blockIdx.x];
     const SysDev S = sys[it.sys];
-    const float* __restrict__ base = Ys + S.off;
+    const T* __restrict__ base = Ys + S.off;
     const int blk = 64 * R;
     const int tb0 = it.tgt0 + wave * blk;  // this wavefront's target block
 
-    float yi[R][D], acc[R][D], hi[R][D], lo[R][D];
+    T yi[R][D], acc[R][D], hi[R][D], lo[R][D];
     bool valid[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -892,8 +961,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sym(const PairItem* __rest
         valid[r] = i < S.N;
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            yi[r][c] = valid[r] ? base[c * P + i] : -1e15f;
-            acc[r][c] = hi[r][c] = lo[r][c] = 0.0f;
+            yi[r][c] = valid[r] ? base[c * P + i] : (T)-1e15;
+            acc[r][c] = hi[r][c] = lo[r][c] = (T)0;
         }
     }
 
@@ -910,9 +979,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sym(const PairItem* __rest
     const int own_end = min(tb0 + blk, g_end);
     const int start = diag ? tb0 : it.src0;
     const int end = diag ? g_end : it.src0 + it.nsrc;
-    const int piece = diag ? sym_lds(D) : stride;  // group x d <= sym_lds(D): one piece
+    const int piece = diag ? sym_lds_t<T, D>() : stride;  // group x d <= the row: one piece
     if (diag) {
-        for (int q = lane; q < sym_lds(D); q += 64) jred[wave][q] = 0.0f;
+        for (int q = lane; q < sym_lds_t<T, D>(); q += 64) jred[wave][q] = (T)0;
     }
     int chunks = 0;
     for (int u0 = start; u0 < end; u0 += piece) {
@@ -920,24 +989,24 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sym(const PairItem* __rest
         const int64_t jshift = diag ? -(int64_t)it.tgt0 : -(int64_t)u0;
         for (int c0 = u0; c0 < u1; c0 += 16) {
             const int ce = (diag && c0 < own_end) ? own_end : u1;
-            sym_chunk<D, R>(base, P, c0, ce, yi, acc, &jred[wave][0], jshift, !(diag && c0 < own_end));
+            sym_chunk<T, D, R>(base, P, c0, ce, yi, acc, &jred[wave][0], jshift, !(diag && c0 < own_end));
             if constexpr (KAHAN) {
                 if (++chunks == kKahanChunk / 16) {
                     chunks = 0;
-                    kahan_fold<D, R, KAHAN>(acc, hi, lo);
+                    kahan_fold<T, D, R, KAHAN>(acc, hi, lo);
                 }
             }
         }
         if (!diag) {
             __syncthreads();
-            jside_flush<D>(jred, Bpj, (int64_t)it.jrow, P, S.off, u0, u1 - u0, u0);
+            jside_flush<T, D>(jred, Bpj, (int64_t)it.jrow, P, S.off, u0, u1 - u0, u0);
             if (u1 < end) __syncthreads();  // the next piece reuses the LDS
         }
     }
-    if constexpr (KAHAN) kahan_fold<D, R, KAHAN>(acc, hi, lo);
+    if constexpr (KAHAN) kahan_fold<T, D, R, KAHAN>(acc, hi, lo);
     if (diag) {
         __syncthreads();
-        jside_flush<D>(jred, Bpj, (int64_t)(it.tgt0 / (blk * kWaves)), P, S.off, it.tgt0, it.nsrc, it.tgt0);
+        jside_flush<T, D>(jred, Bpj, (int64_t)(it.tgt0 / (blk * kWaves)), P, S.off, it.tgt0, it.nsrc, it.tgt0);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -946,7 +1015,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sym(const PairItem* __rest
 #pragma unroll
         for (int c = 0; c < D; ++c) {
             // the compensated sum hi + lo, rounded once
-            const float v = KAHAN ? (float)((double)hi[r][c] + (double)lo[r][c]) : acc[r][c];
+            const T v = KAHAN ? (T)((double)hi[r][c] + (double)lo[r][c]) : acc[r][c];
             Bp[((int64_t)it.split * D + c) * P + S.off + i] = v;
         }
     }

@@ -29,12 +29,17 @@ def _key(workload: dict, precision: str) -> str:
 
 
 def candidates(d: int, precision: str):
-    schemes = ["ordered"] if precision == "fp64" else ["symmetric", "ordered"]
     out = []
-    for scheme in schemes:
+    for scheme in ("symmetric", "ordered"):
         # symmetric: a target group (4 x 64 R particles) times d must fit the LDS row
-        # (2048 floats; 3072 for d = 3, where R = 4 fits but measured slower than R = 2)
-        Rs = {1: (2, 4, 8), 2: (1, 2, 4)}.get(d, (1, 2)) if scheme == "symmetric" else ((2, 4) if d == 1 else (1, 2))
+        # (2048 floats, 3072 for d = 3, where R = 4 fits but measured slower than R = 2;
+        # 1024 doubles, 1536 for d = 3)
+        if scheme == "ordered":
+            Rs = (2, 4) if d == 1 else (1, 2)
+        elif precision == "fp64":
+            Rs = {1: (1, 2, 4), 2: (1, 2), 3: (1, 2)}.get(d, (1,))
+        else:
+            Rs = {1: (2, 4, 8), 2: (1, 2, 4)}.get(d, (1, 2))
         for R in Rs:
             for Lmul in (0.5, 1.0, 2.0):
                 out.append({"pair_scheme": scheme, "targets_per_lane": R, "L_factor": Lmul})

@@ -562,6 +562,28 @@ def test_symmetric_and_ordered_schemes_agree(torch_cuda):
                 assert _err(g, b) <= 2e-6
 
 
+def test_symmetric_fp64_matches_oracle_for_every_fitting_tiling(torch_cuda):
+    """FP64 in both pair schemes against the oracle, pathwise: the symmetric
+    scheme at every target-block size whose group fits the double LDS row
+    (R x d <= 4; R = 2 at d = 3), with the default source range and one
+    that is 16 past the row's capacity (two LDS pieces per item), on ragged
+    sizes in d = 1, 2, 3."""
+    for w in (W.small_parity(n_ens=2, N=1500), W.precision_d3(N=777), W.surrogate_d2(N=1300, h_fine=2.0 ** -9)):
+        w["T"] = 2.0 ** -5 if w["d"] == 1 else 2.0 ** -6
+        _say(f"oracle d={w['d']}")
+        ref = oracle.run(w)
+        Rs = {1: (1, 2, 4), 2: (1, 2), 3: (1, 2)}[w["d"]]
+        past = {1: 1040, 2: 528, 3: 528}[w["d"]]  # 1024 / d doubles per source (1536 / 3 at d = 3), + 16
+        cases = [("ordered", 2, 0)] + [("symmetric", R, L) for R in Rs for L in (0, past)]
+        for scheme, R, L in cases:
+            _say(f"fp64 d={w['d']} {scheme} R={R} L={L}")
+            with _ssm(w, "fp64", pair_scheme=scheme, targets_per_lane=R, sources_per_item=L) as s:
+                assert s.info()["pair_scheme"] == scheme
+                s.run()
+                for e, r in enumerate(ref):
+                    assert _err(s.state(e), r) <= FP64_TOL, (w["d"], scheme, R, L, e)
+
+
 def test_autotuner_choice_is_valid_and_cached(torch_cuda, tmp_path, monkeypatch):
     from paper_2105_09688_amd.tune import autotune
     monkeypatch.setenv("SSM_TUNE_CACHE", str(tmp_path / "tune.json"))
