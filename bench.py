@@ -134,7 +134,9 @@ def particle_steps(w, ticks):
 
 def study_precision(args, stream):
     """d=3 precision study: FP64, FP32 and FP32-compensated runs of the same
-    paths; errors of FP32 modes against the FP64 path (mean, variance, rMSE)."""
+    paths (the compensated mode also with every pair term compensated, on
+    ordered pairs); errors of the FP32 modes against the FP64 path (mean,
+    variance, rMSE)."""
     import numpy as np
     from paper_2105_09688_amd import workloads as W
     from paper_2105_09688_amd.ssm import SSM
@@ -142,18 +144,21 @@ def study_precision(args, stream):
     N = w["systems"][0][0]
     res = {}
     states = {}
-    for prec in ("fp64", "fp32_kahan", "fp32"):
-        s, dt, n = timed_run(SSM, w, prec, stream)
+    runs = (("fp64", "fp64", {}), ("fp32_kahan", "fp32_kahan", {}), ("fp32", "fp32", {}),
+            ("fp32_kahan_per_pair", "fp32_kahan", {"kahan_span": 1}))
+    for key, prec, kw in runs:
+        s, dt, n = timed_run(SSM, w, prec, stream, **kw)
         info = s.info()
-        states[prec] = (s.state(0), s.moments(0))
+        states[key] = (s.state(0), s.moments(0))
         pair_avg = info["pair_ms"] / 1e3 / max(1, info["pair_launches"])
-        res[prec] = {"seconds": dt, "steps": n, "particle_steps_per_s": N * n / dt,
-                     "pair_kernel_avg_ms": pair_avg * 1e3,
-                     "pair_tflops": float(N) * N * flops_per_pair(3) / pair_avg / 1e12}
+        res[key] = {"seconds": dt, "steps": n, "particle_steps_per_s": N * n / dt,
+                    "pair_kernel_avg_ms": pair_avg * 1e3,
+                    "pair_tflops": float(N) * N * flops_per_pair(3) / pair_avg / 1e12,
+                    "pair_scheme": info["pair_scheme"]}
         s.close()
-        print(f"[precision] {prec}: {dt:.2f} s", file=sys.stderr, flush=True)
+        print(f"[precision] {key}: {dt:.2f} s", file=sys.stderr, flush=True)
     X64, (m64, v64) = states["fp64"]
-    for prec in ("fp32_kahan", "fp32"):
+    for prec in ("fp32_kahan", "fp32", "fp32_kahan_per_pair"):
         X, (m, v) = states[prec]
         D = X - X64
         res[prec]["err_vs_fp64"] = {

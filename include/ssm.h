@@ -127,7 +127,10 @@ typedef struct {
                                   the surrogate enabled */
     /* Coefficient extensions (zero: off), see "Coefficients" above. */
     int32_t v_componentwise;   /* nonzero: component-wise cubic -v_ak[k] y_k^3 (v_a unused) */
-    int32_t pad2;
+    int32_t kahan_span;        /* SSM_FP32_KAHAN only: 0 -> plain sums over 256 sources between
+                                  compensated adds (default); 1 -> every pair term added by
+                                  Neumaier's method (a precision-study variant: ordered scheme,
+                                  about 2x the pair time at d = 3); other values are rejected */
     double v_ak[SSM_MAX_D];
     double b_const[SSM_MAX_D];
     double b_mat[SSM_MAX_D * SSM_MAX_D];

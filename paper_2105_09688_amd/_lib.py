@@ -36,7 +36,7 @@ class Config(C.Structure):
         ("stream", C.c_void_p),
         ("targets_per_lane", C.c_int32), ("sources_per_item", C.c_int32), ("pair_scheme", C.c_int32),
         ("graphs", C.c_int32),
-        ("v_componentwise", C.c_int32), ("pad2", C.c_int32),
+        ("v_componentwise", C.c_int32), ("kahan_span", C.c_int32),
         ("v_ak", C.c_double * MAX_D), ("b_const", C.c_double * MAX_D), ("b_mat", C.c_double * (MAX_D * MAX_D)),
         ("b_mean", C.c_double * MAX_D),
     ]

@@ -146,8 +146,25 @@ static void launch_pair_T(int R, bool kahan, dim3 grid, hipStream_t st, const Pa
 // workgroup), symmetric scheme one workgroup per item.
 template <typename T>
 static void launch_pair(int d, int R, bool kahan, dim3 grid, hipStream_t st, const PairItem* items,
-                        int n, const SysDev* sys, const T* Ys, int64_t P, T* Bp, T* Bpj, bool sym)
+                        int n, const SysDev* sys, const T* Ys, int64_t P, T* Bp, T* Bpj, bool sym,
+                        bool kpair = false)
 {
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (kpair) {
+            dim3 block(64 * kWaves);
+#define SSM_KPAIR_CASE(DD, RR)                                                                                  \
+    if (d == DD && R == RR) {                                                                                   \
+        hipLaunchKernelGGL((k_pair_kpair<DD, RR>), grid, block, 0, st, items, n, sys, Ys, P, Bp);               \
+        return;                                                                                                 \
+    }
+            SSM_KPAIR_CASE(1, 1) SSM_KPAIR_CASE(1, 2) SSM_KPAIR_CASE(1, 4) SSM_KPAIR_CASE(1, 8)
+            SSM_KPAIR_CASE(2, 1) SSM_KPAIR_CASE(2, 2) SSM_KPAIR_CASE(2, 4) SSM_KPAIR_CASE(2, 8)
+            SSM_KPAIR_CASE(3, 1) SSM_KPAIR_CASE(3, 2) SSM_KPAIR_CASE(3, 4) SSM_KPAIR_CASE(3, 8)
+            SSM_KPAIR_CASE(4, 1) SSM_KPAIR_CASE(4, 2) SSM_KPAIR_CASE(4, 4) SSM_KPAIR_CASE(4, 8)
+#undef SSM_KPAIR_CASE
+            return;
+        }
+    }
     if (sym) {
         switch (d) {
             case 1: launch_pair_sym_D<T, 1>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
@@ -223,7 +240,8 @@ struct ssm_ctx {
     void* Bp = nullptr;        // i-side partials [max_splits][d][P] in the storage precision
     void* Bpj = nullptr;       // symmetric scheme: j-side partials [nb_max][d][P] (pair precision)
     double* pairsum = nullptr; // [d][P] scaled pair term of the last exact tick (k_combine)
-    bool sym = false;          // symmetric pair scheme (FP32 modes)
+    bool sym = false;          // symmetric pair scheme
+    bool kpair = false;        // FP32-compensated with every pair term compensated (kahan_span = 1)
     int64_t nb_max = 0;
     double* psumX = nullptr;
     double* psumY = nullptr;
@@ -558,7 +576,7 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
             if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
         }
         launch_pair<T>(d, c->R, c->prec == SSM_FP32_KAHAN, grid, c->stream, c->dpair + c->pair_off[ph],
-                       (int)np, c->dsys, Ys, c->P, (T*)c->Bp, (T*)c->Bpj, c->sym);
+                       (int)np, c->dsys, Ys, c->P, (T*)c->Bp, (T*)c->Bpj, c->sym, c->kpair);
         HIP_TRY(hipGetLastError());
         if (prof) {
             if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
@@ -889,7 +907,11 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
 
     // pair tiling: R targets per lane, L sources per item, scheme
     const bool f64 = c->prec == SSM_FP64;
-    c->sym = cfg->pair_scheme != 1;
+    if (cfg->kahan_span != 0 && cfg->kahan_span != 1) { free_ctx(c); return fail(SSM_ERR_INVALID, "kahan_span must be 0 or 1"); }
+    if (cfg->kahan_span == 1 && c->prec != SSM_FP32_KAHAN) { free_ctx(c); return fail(SSM_ERR_INVALID, "kahan_span = 1 needs the FP32-compensated precision"); }
+    if (cfg->kahan_span == 1 && cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "kahan_span = 1 runs the ordered pair scheme only"); }
+    c->kpair = cfg->kahan_span == 1;
+    c->sym = cfg->pair_scheme != 1 && !c->kpair;
     {
         std::vector<int64_t> Ns;
         for (auto& S : c->sys) Ns.push_back(S.N);
@@ -1660,7 +1682,7 @@ extern "C" ssm_status ssm_surrogate_samples(ssm_ctx* c, int32_t sys, int64_t n, 
         launch_pair<double>(d, c->R, false, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const double*)c->Ys, c->P, (double*)c->Bp, (double*)c->Bpj, c->sym);
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<double, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const double*)c->Y, c->rff, c->rff_part));
     } else {
-        launch_pair<float>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const float*)c->Ys, c->P, (float*)c->Bp, (float*)c->Bpj, c->sym);
+        launch_pair<float>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const float*)c->Ys, c->P, (float*)c->Bp, (float*)c->Bpj, c->sym, c->kpair);
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<float, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const float*)c->Y, c->rff, c->rff_part));
     }
     HIP_TRY(hipGetLastError());

@@ -706,7 +706,7 @@ __device__ __forceinline__ void pair_block(const T* __restrict__ src, int64_t P,
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric (FP32) work item: each unordered pair (i, j), i in the wavefront's
+// Symmetric work item: each unordered pair (i, j), i in the wavefront's
 // target block and j in the item's source range, is evaluated once; +q goes to
 // i and -q to j (q = (s_j - s_i) exp2(-|s_j - s_i|^2) is odd in (i, j)).
 // Sources come in chunks of 16, one per lane of each 16-lane row (the four
@@ -1104,6 +1104,69 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair(const PairItem* __restrict
         if (!valid[r]) continue;
 #pragma unroll
         for (int k = 0; k < D; ++k) Bp[((int64_t)it.split * D + k) * P + S.off + i] = acc[r][k];
+    }
+}
+
+// FP32 study variant of the ordered kernel: every pair's term is added into
+// the target's (hi, lo) pair by Neumaier's method (no plain partial sums), so
+// the pair sums carry no FP32 accumulation error beyond each term's own
+// rounding.  Same items and partial layout as k_pair; hi + lo is rounded once
+// to float per item.
+template <int D, int R>
+__global__ __launch_bounds__(64 * kWaves) void k_pair_kpair(const PairItem* __restrict__ items, int n_items,
+                                                            const SysDev* __restrict__ sys,
+                                                            const float* __restrict__ Ys, int64_t P,
+                                                            float* __restrict__ Bp)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int idx = blockIdx.x * kWaves + wave;
+    if (idx >= n_items) return;
+    const PairItem it = items[idx];
+    const SysDev S = sys[it.sys];
+    const float* __restrict__ base = Ys + S.off;
+    float yi[R][D], hi[R][D], lo[R][D];
+    bool valid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = it.tgt0 + lane + 64 * r;
+        valid[r] = i < S.N;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            yi[r][k] = valid[r] ? base[k * P + i] : 0.0f;
+            hi[r][k] = lo[r][k] = 0.0f;
+        }
+    }
+    for (int j = it.src0; j < it.src0 + it.nsrc; ++j) {
+        float s[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) s[k] = base[k * P + j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float z[D];
+            float t = 0.0f;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                z[k] = s[k] - yi[r][k];
+                t = (k == 0) ? z[k] * z[k] : fmaf(z[k], z[k], t);
+            }
+            const float e = exp2_fast<float>(-t);
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const float a = z[k] * e;
+                const float sm = hi[r][k] + a;
+                lo[r][k] += (fabsf(hi[r][k]) >= fabsf(a)) ? (hi[r][k] - sm) + a : (a - sm) + hi[r][k];
+                hi[r][k] = sm;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = it.tgt0 + lane + 64 * r;
+        if (!valid[r]) continue;
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            Bp[((int64_t)it.split * D + k) * P + S.off + i] = (float)((double)hi[r][k] + (double)lo[r][k]);
     }
 }
 

@@ -79,10 +79,17 @@ def _init(w, **over):
     ("precision", 7, "precision"),
     ("targets_per_lane", 3, "targets_per_lane"),
     ("sources_per_item", 10, "sources_per_item"),
+    ("kahan_span", 2, "kahan_span"),
+    ("kahan_span", 1, "FP32-compensated"),  # the helper's precision is FP64
 ])
 def test_init_rejects_invalid_config(field, value, needle):
     st, msg = _init(W.small_parity(n_ens=1, N=10), **{field: value})
     assert st == _lib.SSM_ERR_INVALID and needle in msg, msg
+
+
+def test_per_pair_compensation_runs_ordered_pairs_only():
+    st, msg = _init(W.small_parity(n_ens=1, N=10), precision=_lib.SSM_FP32_KAHAN, kahan_span=1, pair_scheme=2)
+    assert st == _lib.SSM_ERR_INVALID and "ordered" in msg, msg
 
 
 def test_init_rejects_non_integer_grid_and_step_constraint():

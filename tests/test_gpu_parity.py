@@ -584,6 +584,27 @@ def test_symmetric_fp64_matches_oracle_for_every_fitting_tiling(torch_cuda):
                     assert _err(s.state(e), r) <= FP64_TOL, (w["d"], scheme, R, L, e)
 
 
+def test_per_pair_compensation_matches_oracle(torch_cuda):
+    """FP32-compensated with every pair term compensated (kahan_span = 1, the
+    precision study's variant, ordered pairs) against the oracle, pathwise,
+    and against the default compensated run, in d = 1 and 3 on ragged sizes
+    and several target-block sizes."""
+    for w in (W.small_parity(n_ens=2, N=1500), W.precision_d3(N=777)):
+        w["T"] = 2.0 ** -5 if w["d"] == 1 else 2.0 ** -6
+        ref = oracle.run(w)
+        with _ssm(w, "fp32_kahan") as s:
+            s.run()
+            base = s.states()
+        for R in (1, 2, 8):
+            _say(f"per-pair compensation d={w['d']} R={R}")
+            with _ssm(w, "fp32_kahan", kahan_span=1, targets_per_lane=R) as s:
+                assert s.info()["pair_scheme"] == "ordered"
+                s.run()
+                for e, r in enumerate(ref):
+                    assert _err(s.state(e), r) <= FP32_TOL, (w["d"], R, e)
+                    assert _err(s.state(e), base[e]) <= 2e-6, (w["d"], R, e)
+
+
 def test_autotuner_choice_is_valid_and_cached(torch_cuda, tmp_path, monkeypatch):
     from paper_2105_09688_amd.tune import autotune
     monkeypatch.setenv("SSM_TUNE_CACHE", str(tmp_path / "tune.json"))
