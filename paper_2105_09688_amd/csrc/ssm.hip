@@ -377,7 +377,7 @@ static bool is_int_ratio(double a, double b, int64_t* out)
 // Work items of one system's pair sums.
 //  Ordered-pair scheme: tiles of 64 R targets x source ranges of L sources;
 //    i-side partial q = source range q.
-//  Symmetric scheme (FP32): target groups of G = kWaves x 64 R particles
+//  Symmetric scheme: target groups of G = kWaves x 64 R particles
 //    (one workgroup); group a has a diagonal item (its own sources, ordered
 //    pairs, partial 0) and items over the later sources [G (a+1), N) in ranges
 //    of L (partial 1, 2, ...), each also writing j-side partial row a.  Every

@@ -91,7 +91,7 @@ def test_implicit_solve_matches_oracle(torch_cuda, d):
 
 
 # --------------------------------------------------------------------------- pairwise sums (2.4)
-@pytest.mark.parametrize("d,ell", [(1, 1.0), (2, 1.0), (3, 0.5)])
+@pytest.mark.parametrize("d,ell", [(1, 1.0), (2, 1.0), (3, 0.5), (4, 0.7)])
 @pytest.mark.parametrize("N", [1, 2, 63, 64, 65, 257, 1000, 4099])
 def test_pair_sum_matches_oracle(torch_cuda, d, ell, N):
     from paper_2105_09688_amd.ssm import pair_sum
@@ -328,6 +328,27 @@ def test_run_d3_and_d2(torch_cuda, precision, tol):
             s.run()
             got = s.state(0)
         assert _err(got, ref) <= tol
+
+
+def test_run_d4_in_both_schemes(torch_cuda):
+    """d = 4, the largest dimension the library takes: radial cubic drift,
+    Gaussian interaction, diagonal affine noise, a ragged N, in FP64 and
+    FP32-compensated, symmetric (R = 1, and R = 2 in FP32, where a group of
+    512 x 4 fills the float row) and ordered, against the oracle pathwise."""
+    w = W.precision_d3(N=601, h=2.0 ** -8)
+    w.update(d=4, T=2.0 ** -4, x0_mean=[0.2, -0.1, 0.0, 0.3], x0_std=[0.8, 1.0, 0.6, 0.9],
+             sigma=dict(s0=[0.2, 0.25, 0.15, 0.3], s1=[0.1, 0.0, 0.05, 0.1], s2=[0.0, 0.1, 0.0, 0.0]))
+    w["b"]["ell"] = 0.7
+    ref = oracle.run(w)[0]
+    cases = [("fp64", FP64_TOL, "symmetric", 1), ("fp64", FP64_TOL, "ordered", 2),
+             ("fp32_kahan", FP32_TOL, "symmetric", 1), ("fp32_kahan", FP32_TOL, "symmetric", 2),
+             ("fp32_kahan", FP32_TOL, "ordered", 4)]
+    for prec, tol, scheme, R in cases:
+        _say(f"d=4 {prec} {scheme} R={R}")
+        with _ssm(w, prec, pair_scheme=scheme, targets_per_lane=R) as s:
+            assert s.info()["pair_scheme"] == scheme
+            s.run()
+            assert _err(s.state(0), ref) <= tol, (prec, scheme, R)
 
 
 def test_measure_dependent_v_unfused_path(torch_cuda):
