@@ -120,10 +120,33 @@ __device__ __forceinline__ float exp2_fast<float>(float x)
     return __builtin_amdgcn_exp2f(x);  // v_exp_f32
 }
 
+// FP64 2^x for x <= 0, the pair kernels' argument -|c dy|^2 (NaN passes through).
+// x = n + r with n = rint(x) and |r| <= 1/2 exact; 2^r is the degree-11
+// polynomial that interpolates 2^r at the 12 Chebyshev nodes of [-1/2, 1/2]
+// (interpolation error 4.2e-18 relative; coefficients rounded to double from
+// 60-digit values; 0.80 ulp worst case with Horner's rounding); 2^n by ldexp,
+// n clamped at -1100 so that every x below the double range, the padding's
+// -4e30 included, gives exactly 0.  16 instructions, none of them range tests
+// (the device library's exp2 took about 20: d = 1, N = 2^16 symmetric pair
+// kernel 1.48 -> 1.29 ms per launch, timed the same way).
+__device__ __forceinline__ double exp2_poly_coef(int k)
+{
+    constexpr double c[12] = {0x1.0000000000000p+0,  0x1.62e42fefa39efp-1, 0x1.ebfbdff82c5aep-3,
+                              0x1.c6b08d704a0c6p-5,  0x1.3b2ab6fb9f1a5p-7, 0x1.5d87fe78a3f9cp-10,
+                              0x1.430913112c61bp-13, 0x1.ffcbfc6da6ed1p-17, 0x1.62bfc2c86d700p-20,
+                              0x1.b524ebd13a55fp-24, 0x1.e6228acd1c6e5p-28, 0x1.e9ec1fcb69a7fp-32};
+    return c[k];
+}
+
 template <>
 __device__ __forceinline__ double exp2_fast<double>(double x)
 {
-    return exp2(x);
+    const double n = rint(x);
+    const double r = x - n;
+    double p = exp2_poly_coef(11);
+#pragma unroll
+    for (int k = 10; k >= 0; --k) p = fma(p, r, exp2_poly_coef(k));
+    return ldexp(p, (int)fmax(n, -1100.0));
 }
 
 // The partial-sum rows of particle i of system S, in their fixed order:
@@ -818,9 +841,8 @@ __device__ __forceinline__ void sym_chunk(const T* __restrict__ base, int64_t P,
         // FP64: one j-side accumulator per component travels with its source
         // (both move one lane per step; the 16th move brings both home) in
         // place of 16 per-step accumulators and the route.  The steps stay a
-        // loop: unrolled, the scheduler interleaves the 16 exponentials and
-        // runs out of registers (d = 3, R = 2: 49.6 -> 38.1 ms per launch at
-        // N = 2^18; d = 1, R = 4: 1.82 -> 1.48 ms at N = 2^16).
+        // loop: unrolled measured slower (d = 3, R = 2, N = 2^18: 46.3 against
+        // 35.5 ms per launch; d = 1, R = 4, N = 2^16: 1.60 against 1.29 ms).
 #pragma unroll
         for (int c = 0; c < D; ++c) tot[c] = (T)0;
 #pragma unroll 1
