@@ -13,12 +13,25 @@ constexpr int kMaxD = 4;
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each round multiplies
 // words 0 and 2 by two fixed odd 64-bit constants into 128-bit products and
 // mixes the high halves with words 1, 3 and the round key; the key advances
-// by two Weyl increments per round.  64x64->128 products map to the 32-bit
-// multiplier of the vector ALU (the compiler expands __umul64hi).
+// by two Weyl increments per round.
 // ---------------------------------------------------------------------------
 struct Block4 {
     uint64_t w[4];
 };
+
+// The 128-bit product a b from four 32 x 32 + 64 multiply-adds
+// (v_mad_u64_u32), both halves from the same partial products.  No sum
+// overflows: (2^32 - 1)^2 + 2 (2^32 - 1) < 2^64.
+__device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t* lo, uint64_t* hi)
+{
+    const uint64_t a0 = (uint32_t)a, a1 = a >> 32, b0 = (uint32_t)b, b1 = b >> 32;
+    const uint64_t t = a0 * b0;
+    const uint64_t u = a1 * b0 + (t >> 32);
+    const uint64_t v = a0 * b1 + (uint32_t)u;
+    const uint64_t w = a1 * b1 + (u >> 32);
+    *hi = w + (v >> 32);
+    *lo = (v << 32) | (uint32_t)t;
+}
 
 __device__ __forceinline__ Block4 philox4x64_10(uint64_t x0, uint64_t x1, uint64_t x2, uint64_t x3,
                                                 uint64_t k0, uint64_t k1)
@@ -29,10 +42,9 @@ __device__ __forceinline__ Block4 philox4x64_10(uint64_t x0, uint64_t x1, uint64
     constexpr uint64_t kWeylB = 0xBB67AE8584CAA73Bull;
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint64_t a_lo = kMulA * x0;
-        const uint64_t a_hi = __umul64hi(kMulA, x0);
-        const uint64_t b_lo = kMulB * x2;
-        const uint64_t b_hi = __umul64hi(kMulB, x2);
+        uint64_t a_lo, a_hi, b_lo, b_hi;
+        mulhilo64(kMulA, x0, &a_lo, &a_hi);
+        mulhilo64(kMulB, x2, &b_lo, &b_hi);
         const uint64_t n0 = b_hi ^ x1 ^ k0;
         const uint64_t n2 = a_hi ^ x3 ^ k1;
         x0 = n0;
