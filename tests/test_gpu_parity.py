@@ -63,7 +63,11 @@ def test_brownian_increments_match_oracle(torch_cuda, d, r):
     _say(f"brownian d={d} r={r}")
     got = brownian(d, N, seed, ens, n0, r, hf).cpu().numpy()
     ref = np.stack([oracle.brownian(seed, d, i, ens, n0, r, hf) for i in range(N)], axis=1)
-    assert np.max(np.abs(got - ref)) <= 1e-13
+    err = np.max(np.abs(got - ref))
+    _say(f"  max abs diff {err:.3e} (increments up to {np.max(np.abs(ref)):.2f})")
+    # a few ulps of the largest increment: the device's own log and sine/cosine
+    # against the oracle's libm (measured: at most 1.1e-16 on increments up to 0.3)
+    assert err <= 8 * 2.0 ** -52 * np.max(np.abs(ref))
 
 
 # --------------------------------------------------------------------------- implicit step (2.3)
