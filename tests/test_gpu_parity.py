@@ -645,6 +645,27 @@ def test_autotuner_choice_is_valid_and_cached(torch_cuda, tmp_path, monkeypatch)
         assert _err(s.state(0), ref) <= FP32_TOL
 
 
+def test_autotuner_in_fp64_tries_both_schemes_and_its_choice_matches_oracle(torch_cuda, tmp_path, monkeypatch):
+    """The FP64 candidates include the symmetric scheme at every target-block
+    size whose group fits the double LDS row; the chosen tiling runs to the
+    FP64 bar against the oracle."""
+    from paper_2105_09688_amd.tune import autotune, candidates
+    cands = candidates(2, "fp64")
+    assert {c["pair_scheme"] for c in cands} == {"symmetric", "ordered"}
+    assert {c["targets_per_lane"] for c in cands if c["pair_scheme"] == "symmetric"} == {1, 2}
+    monkeypatch.setenv("SSM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    w = W.surrogate_d2(N=1500, h=2.0 ** -9, h_fine=2.0 ** -9)
+    w["T"] = 2.0 ** -5
+    choice = autotune(w, "fp64", steps=2)
+    _say(f"fp64 autotune choice {choice}")
+    ref = oracle.run(w)[0]
+    with _ssm(w, "fp64", targets_per_lane=choice["targets_per_lane"],
+              sources_per_item=choice["sources_per_item"], pair_scheme=choice["pair_scheme"]) as s:
+        assert s.info()["pair_scheme"] == choice["pair_scheme"]
+        s.run()
+        assert _err(s.state(0), ref) <= FP64_TOL
+
+
 def test_profile_stride_times_the_sampled_ticks_only(torch_cuda):
     """ssm_profile(every = k): events around the launches of ticks with
     tick % k == 0; every = 0 switches timing off; the run itself is unchanged."""
