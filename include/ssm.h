@@ -142,7 +142,8 @@ typedef struct {
     int64_t ticks_total;     /* T / h_min */
     int32_t newton_max_seen; /* largest Newton iteration count seen so far */
     int32_t newton_failures; /* particles whose implicit solve failed (sticky) */
-    int32_t nonfinite;       /* particles that became non-finite (sticky) */
+    int32_t nonfinite;       /* non-finite particles met by the implicit solve, which follows every
+                                update and every ssm_set_state / ssm_state_refresh (sticky) */
     int32_t n_pair_items;    /* work items of the pairwise kernel per tick (phase 0): wavefronts in
                                 the ordered scheme, workgroups in the symmetric scheme */
     int32_t targets_per_lane;
@@ -193,7 +194,10 @@ ssm_status ssm_step(ssm_ctx *ctx, int64_t n_ticks);
 ssm_status ssm_run(ssm_ctx *ctx);
 
 /* Wait for the context's stream; return SSM_ERR_NEWTON / SSM_ERR_NONFINITE if
- * a kernel flagged a particle since init. */
+ * a kernel flagged a particle since init (a NaN or infinite coordinate, from
+ * the update (2.4) or written by the caller, is passed through unchanged
+ * and flagged: the explicit part of the scheme is where the paper locates
+ * the risk of corrupted particles; the run continues on the device). */
 ssm_status ssm_sync(ssm_ctx *ctx);
 
 /* Empirical moments of system sys (Section 3): mean[k] = (1/N) sum_i X_k^i and
@@ -209,8 +213,21 @@ ssm_status ssm_moments(ssm_ctx *ctx, int32_t sys, double *mean, double *var);
 ssm_status ssm_get_state(ssm_ctx *ctx, int32_t sys, int32_t which, double *host, int64_t *step);
 
 /* Overwrite X of system sys with host [d][N] (rounded to the storage
- * precision) and recompute Y* for it.  Synchronizes. */
-ssm_status ssm_set_state(ssm_ctx *ctx, int32_t sys, const double *host);
+ * precision) and recompute Y* = F_h(X) of (2.3) for it (when v depends on
+ * mu^X, from the moments of the new X).
+ * step = -1 keeps the context's step count.  step >= 0 declares host to be
+ * X after `step` steps of system sys: the context moves to tick
+ * t = step * (h / h_min), which must be a step boundary of every system
+ * (a multiple of h_max / h_min) and at most T / h_min, and every system's
+ * step count becomes ceil(t / (h_s / h_min)).  The next step then draws the
+ * Brownian increment dW_step of (2.4), so a state saved with ssm_get_state
+ * (which returns the step count) continues on the same Brownian path in a
+ * fresh context (Section 3 compares step sizes on the same paths).  Moving
+ * the tick recomputes Y* of every system; in a context of several systems the
+ * caller restores each of them, each with a step of the same tick.  The
+ * surrogate's stored residuals and gains are dropped: ticks up to the next
+ * check use the exact pair sums.  Synchronizes. */
+ssm_status ssm_set_state(ssm_ctx *ctx, int32_t sys, const double *host, int64_t step);
 
 /* Device layout of the particle state X of a context: one row of *P slots per
  * component (row k starts at element k * *P), system s at slots
@@ -233,8 +250,9 @@ ssm_status ssm_state_layout(ssm_ctx *ctx, int64_t *P, int64_t *offsets, int32_t 
 ssm_status ssm_bind_state(ssm_ctx *ctx, void *dev, size_t bytes);
 
 /* Recompute Y* = F_h(X) (2.3) and the block sums of X for system sys
- * (sys = -1: every system) after the caller changed X in a bound buffer.
- * SSM_ERR_STATE when v depends on mu^X (as for ssm_set_state).
+ * (sys = -1: every system) after the caller changed X in a bound buffer (when
+ * v depends on mu^X, from the moments of the changed X).  The surrogate's
+ * stored residuals and gains are dropped, as in ssm_set_state.
  * Synchronizes. */
 ssm_status ssm_state_refresh(ssm_ctx *ctx, int32_t sys);
 
@@ -292,7 +310,8 @@ size_t ssm_pair_workspace_bytes(int32_t d, int64_t N, int32_t precision);
  * c = X^i + h v(c, mu_X) for the coefficient family above (Lemma 4.1).  X, Y:
  * device [d][N] double.  xbar: host [d] (mean of mu_X, used if v_lam != 0);
  * m2: second moment of mu_X (used if v_kappa != 0).  iters: device [N] int32
- * (Newton iterations, -1 on failure), may be NULL.  Asynchronous on stream. */
+ * (Newton iterations, -1 on failure, -2 where X^i is not finite: Y^i = X^i),
+ * may be NULL.  Asynchronous on stream. */
 ssm_status ssm_implicit_solve(int32_t d, int64_t N, const double *X, double h, double v_rho,
                               double v_a, double v_kappa, double v_lam, const double *xbar,
                               double m2, int32_t max_iter, double *Y, int32_t *iters, void *stream);
@@ -363,6 +382,14 @@ ssm_status ssm_surrogate_load(ssm_ctx *ctx, const float *master, int64_t n);
  * Check ticks synchronize the stream.  check_every = 0 turns the surrogate
  * off.  Enabling (again) forgets the gain and the residuals. */
 ssm_status ssm_surrogate_enable(ssm_ctx *ctx, int32_t check_every, double tol, int32_t mode);
+
+/* The surrogate's raw output at the current Y* of system sys, from the
+ * kernels a surrogate tick runs: moments (host float [2K], may be NULL)
+ * receives C_1..C_K, S_1..S_K of mu^Y of the system, and out (host double
+ * [d][N]) the network output s^i of every particle, before its mean over
+ * the system is removed.  Needs loaded weights (SSM_ERR_STATE otherwise).
+ * Synchronizes. */
+ssm_status ssm_surrogate_predict(ssm_ctx *ctx, int32_t sys, double *out, float *moments);
 
 /* Training pairs from the current state of system sys: n draws (with
  * replacement, Philox stream tag 4 under seed) of a particle i, writing its

@@ -19,7 +19,7 @@ EXPORTS = (
     "ssm_set_state", "ssm_state_layout", "ssm_bind_state", "ssm_state_refresh", "ssm_rmse", "ssm_sqdiff", "ssm_info", "ssm_profile", "ssm_destroy", "ssm_last_error",
     "ssm_pair_sum", "ssm_pair_workspace_bytes", "ssm_implicit_solve", "ssm_brownian",
     "ssm_philox_blocks", "ssm_mlp_num_params", "ssm_surrogate_load", "ssm_surrogate_enable",
-    "ssm_surrogate_samples", "ssm_mlp_forward", "ssm_mlp_loss_grad", "ssm_mlp_train", "ssm_surrogate_train",
+    "ssm_surrogate_samples", "ssm_surrogate_predict", "ssm_mlp_forward", "ssm_mlp_loss_grad", "ssm_mlp_train", "ssm_surrogate_train",
 )
 
 
@@ -91,7 +91,7 @@ def load():
         "ssm_sync": (st, [vp]),
         "ssm_moments": (st, [vp, i32, dp, dp]),
         "ssm_get_state": (st, [vp, i32, i32, dp, C.POINTER(C.c_int64)]),
-        "ssm_set_state": (st, [vp, i32, dp]),
+        "ssm_set_state": (st, [vp, i32, dp, C.c_int64]),
         "ssm_state_layout": (st, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
         "ssm_bind_state": (st, [vp, vp, C.c_size_t]),
         "ssm_state_refresh": (st, [vp, i32]),
@@ -111,6 +111,7 @@ def load():
         "ssm_surrogate_load": (st, [vp, vp, i64]),
         "ssm_surrogate_enable": (st, [vp, i32, C.c_double, i32]),
         "ssm_surrogate_samples": (st, [vp, i32, i64, u64, vp, vp]),
+        "ssm_surrogate_predict": (st, [vp, i32, dp, vp]),
         "ssm_mlp_forward": (st, [i32, vp, vp, i64, vp, vp]),
         "ssm_mlp_loss_grad": (st, [i32, vp, vp, vp, i64, vp, dp, vp]),
         "ssm_mlp_train": (st, [i32, vp, vp, i64, C.POINTER(TrainCfg), vp, vp, vp]),

@@ -9,10 +9,14 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "ssm.hip")
 LIB = os.path.join(HERE, "libssm.so")
 
-# Packed FP32 instructions are disabled for every HIP translation unit.
+# Packed FP32 instructions are disabled for every HIP translation unit.  The
+# matrix-core instructions keep their accumulators in ordinary VGPRs: the
+# inference kernel applies SiLU to every accumulator, and accumulators in
+# AGPRs cost one v_accvgpr_read per value (104 per pair of tiles).
 HIP_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function",
 ]
 

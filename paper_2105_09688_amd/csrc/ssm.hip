@@ -258,6 +258,7 @@ struct ssm_ctx {
     std::vector<int64_t> pair_off, pair_cnt, blk_off, blk_cnt;
     std::vector<int64_t> all_blk_off;  // blocks of every system (init / set_state)
     int64_t all_blk_cnt = 0;
+    std::vector<int64_t> sys_blk_off;  // per system: first of its blocks in the all-blocks list
     // learned surrogate of the pair term
     bool surr_loaded = false;
     int32_t surr_check_every = 0;  // 0: surrogate off
@@ -285,6 +286,8 @@ struct ssm_ctx {
     int64_t* dtick = nullptr;
     bool dtick_valid = true;  // device counter equals the host tick
     double* dW = nullptr;  // [d][P] Brownian increments of the current tick
+    bool needs_ybar = false;   // b or sigma uses the mean of mu^Y
+    double* ymean = nullptr;   // [n_sys][kMaxD] mean of mu^Y of the current step (k_prep / k_brownian_sum)
     int bm_lanes = 1;      // lanes per particle in k_brownian_sum
     // shared Brownian windows of path groups (systems of one ensemble and size)
     double* win = nullptr;      // [groups][max_stride][d][N_g] per-tick normal sums
@@ -353,7 +356,7 @@ static void free_ctx(ssm_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* bufs[] = {c->x_bound ? nullptr : c->X, c->Y, c->Ys, c->Bp, c->Bpj, c->pairsum, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
                     c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list, c->smean_part, c->smean,
-                    c->dtick, c->dW, c->surr_res, c->dnmax, c->dred, c->dsq, c->win, c->dwin_items};
+                    c->dtick, c->dW, c->surr_res, c->dnmax, c->dred, c->dsq, c->win, c->dwin_items, c->ymean};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     recycle_events(c, c->ev_pair);
@@ -600,15 +603,20 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
         // partials in the same launch (k_prep)
         const bool comb = c->has_pair && run_exact;
         const int ncb = comb ? (int)(nb * 4) : 0;
-        const unsigned gb = (unsigned)(ncb + nb * c->bm_lanes);
+        const int n_main = (int)(ncb + nb * c->bm_lanes);
+        // the stepping systems' means of mu^Y, when b or sigma needs them
+        const YMeanJob job{c->dsys_list + c->sys_list_off[ph], c->needs_ybar ? (int)c->sys_list_cnt[ph] : 0,
+                           c->psumY, c->nblk_tot, c->ymean};
+        const unsigned gb = (unsigned)(n_main + job.n);
 #define SSM_BM(LPV)                                                                                                   \
     if (comb) {                                                                                                       \
-        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_prep<T, D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, ncb, items,     \
-                                             c->dsys, c->coef, c->P, (const T*)c->Bp, (const T*)c->Bpj, c->pairsum, c->tick, \
-                                             tdev, (const double*)c->win, c->dW));                                    \
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_prep<T, D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, ncb, n_main,    \
+                                             items, c->dsys, c->coef, c->P, (const T*)c->Bp, (const T*)c->Bpj,        \
+                                             c->pairsum, c->tick, tdev, (const double*)c->win, c->dW, job));          \
     } else {                                                                                                          \
-        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_brownian_sum<D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, items,    \
-                                             c->dsys, c->coef, c->P, c->tick, tdev, (const double*)c->win, c->dW));   \
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_brownian_sum<D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, n_main,   \
+                                             items, c->dsys, c->coef, c->P, c->tick, tdev, (const double*)c->win,     \
+                                             c->dW, job));                                                            \
     }
         switch (c->bm_lanes) {
             case 16: SSM_BM(16); break;
@@ -626,7 +634,7 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
                                                          (float)c->surr_gain[2], (float)c->surr_gain[3]),
                                              (use_surr && c->surr_mode == SSM_SURR_RESIDUAL && c->surr_res_valid)
                                                  ? c->surr_res : nullptr,
-                                             c->dW,
+                                             c->dW, c->needs_ybar ? (const double*)c->ymean : nullptr,
                                              c->psumX, c->psumY, c->nblk_tot, c->dflags, c->dnmax));
         HIP_TRY(hipGetLastError());
         if (!c->fused) {
@@ -836,6 +844,9 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
         cf.s0[k] = in ? cfg->s0[k] : 0.0; cf.s1[k] = in ? cfg->s1[k] : 0.0; cf.s2[k] = in ? cfg->s2[k] : 0.0;
         cf.x0_mean[k] = in ? cfg->x0_mean[k] : 0.0; cf.x0_std[k] = in ? cfg->x0_std[k] : 0.0;
     }
+    c->needs_ybar = cfg->b_lam != 0.0;
+    for (int k = 0; k < cfg->d; ++k)
+        if (cfg->s2[k] != 0.0 || cfg->b_mean[k] != 0.0) c->needs_ybar = true;
     const double ell = c->has_pair ? cfg->b_ell : 1.0;
     c->ell = ell;
     cf.coord_scale = std::sqrt(kLog2e / (2.0 * ell * ell));
@@ -996,6 +1007,10 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
         c->all_blk_off.push_back((int64_t)blks.size());
         build_blk_items(c, all, blks);
         c->all_blk_cnt = (int64_t)blks.size() - c->all_blk_off[0];
+        // each system's blocks are consecutive in that list (ascending block order)
+        c->sys_blk_off.assign(c->sys.size(), -1);
+        for (int64_t q = c->all_blk_off[0]; q < (int64_t)blks.size(); ++q)
+            if (blks[q].blk == 0) c->sys_blk_off[blks[q].sys] = q;
     }
 
     // device state
@@ -1046,6 +1061,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
         ALLOC(c->dwin_items, (size_t)c->win_items * sizeof(BlkItem));
     }
     ALLOC(c->dsq, c->sys.size() * sizeof(double));
+    ALLOC(c->ymean, c->sys.size() * kMaxD * sizeof(double));
 #undef ALLOC
     hipError_t he = hipMemcpyAsync(c->dsys, sd.data(), sd.size() * sizeof(SysDev), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess && !pairs.empty()) he = hipMemcpyAsync(c->dpair, pairs.data(), pairs.size() * sizeof(PairItem), hipMemcpyHostToDevice, c->stream);
@@ -1244,42 +1260,78 @@ extern "C" ssm_status ssm_get_state(ssm_ctx* c, int32_t sys, int32_t which, doub
 
 // Recompute Y* = F_h(X) and its block sums for system sys after X was
 // written from outside the step loop (the parity of the system's step count
-// selects the double-buffered sums).  Synchronizes.
+// selects the double-buffered sums).  When v depends on mu^X, the block sums
+// of X (mean and second moment) are recomputed first, into the parity slot
+// the implicit solve reads.  Asynchronous on the context's stream.
 static ssm_status refresh_implicit(ssm_ctx* c, int32_t sys)
 {
     const SysHost& S = c->sys[sys];
-    std::vector<BlkItem> items;
-    for (int64_t b = 0; b < S.nblk; ++b) items.push_back(BlkItem{sys, (int32_t)b});
-    BlkItem* ditems = nullptr;
-    HIP_TRY(hipMalloc((void**)&ditems, items.size() * sizeof(BlkItem)));
-    hipError_t he = hipMemcpyAsync(ditems, items.data(), items.size() * sizeof(BlkItem), hipMemcpyHostToDevice, c->stream);
+    const BlkItem* items = c->dblk + c->sys_blk_off[sys];
+    const dim3 g((unsigned)S.nblk);
     // k_newton derives the step count from the tick: tick = (steps_done - 1) * stride
     const int64_t tick_arg = S.steps_done == 0 ? -1 : (S.steps_done - 1) * S.stride;
-    if (he == hipSuccess) {
-        if (c->prec == SSM_FP64) {
-            SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<double, D>), dim3((unsigned)items.size()), dim3(kBlk), 0, c->stream,
-                                                    ditems, c->dsys, c->coef, c->P, tick_arg, (const int64_t*)nullptr, (const double*)c->X, (double*)c->Y,
-                                                    (double*)c->Ys, c->psumX, c->psumY, c->nblk_tot, c->dflags, c->dnmax));
-        } else {
-            SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<float, D>), dim3((unsigned)items.size()), dim3(kBlk), 0, c->stream,
-                                                    ditems, c->dsys, c->coef, c->P, tick_arg, (const int64_t*)nullptr, (const float*)c->X, (float*)c->Y,
-                                                    (float*)c->Ys, c->psumX, c->psumY, c->nblk_tot, c->dflags, c->dnmax));
-        }
-        he = hipGetLastError();
+    if (c->prec == SSM_FP64) {
+        if (!c->fused)
+            SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_xsums<double, D>), g, dim3(kBlk), 0, c->stream, items, c->dsys,
+                                                    c->P, tick_arg, (const double*)c->X, c->psumX, c->nblk_tot));
+        SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<double, D>), g, dim3(kBlk), 0, c->stream,
+                                                items, c->dsys, c->coef, c->P, tick_arg, (const int64_t*)nullptr, (const double*)c->X, (double*)c->Y,
+                                                (double*)c->Ys, c->psumX, c->psumY, c->nblk_tot, c->dflags, c->dnmax));
+    } else {
+        if (!c->fused)
+            SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_xsums<float, D>), g, dim3(kBlk), 0, c->stream, items, c->dsys,
+                                                    c->P, tick_arg, (const float*)c->X, c->psumX, c->nblk_tot));
+        SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_newton<float, D>), g, dim3(kBlk), 0, c->stream,
+                                                items, c->dsys, c->coef, c->P, tick_arg, (const int64_t*)nullptr, (const float*)c->X, (float*)c->Y,
+                                                (float*)c->Ys, c->psumX, c->psumY, c->nblk_tot, c->dflags, c->dnmax));
     }
-    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
-    (void)hipFree(ditems);
-    if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("implicit refresh: ") + hipGetErrorString(he));
+    HIP_TRY(hipGetLastError());
     return SSM_OK;
 }
 
-extern "C" ssm_status ssm_set_state(ssm_ctx* c, int32_t sys, const double* host)
+// The surrogate's stored residuals and fitted gains belong to the state and
+// weights they were taken from: after a change of either, the ticks up to the
+// next check use the exact pair sums (as after a failed check).
+static void surrogate_invalidate(ssm_ctx* c)
+{
+    c->surr_res_valid = false;
+    c->surr_fallback = true;
+    for (int k = 0; k < kMaxD; ++k) c->surr_gain[k] = 1.0;
+}
+
+// Move the context to tick t (a step boundary of every system): each system's
+// step count becomes ceil(t / stride), and every system's Y* is recomputed at
+// the new parity of its step count.
+static ssm_status seek_tick(ssm_ctx* c, int64_t t)
+{
+    c->tick = t;
+    for (auto& S : c->sys) S.steps_done = (t + S.stride - 1) / S.stride;
+    c->dtick_valid = false;
+    for (int32_t s = 0; s < (int32_t)c->sys.size(); ++s) {
+        ssm_status st = refresh_implicit(c, s);
+        if (st != SSM_OK) return st;
+    }
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_set_state(ssm_ctx* c, int32_t sys, const double* host, int64_t step)
 {
     if (!c || !host) return fail(SSM_ERR_INVALID, "NULL argument");
     if (sys < 0 || sys >= (int32_t)c->sys.size()) return fail(SSM_ERR_INVALID, "sys out of range");
-    if (!c->fused) return fail(SSM_ERR_STATE, "set_state needs v independent of mu^X");
-    c->surr_res_valid = false;  // the stored residuals belong to the old state
     const SysHost& S = c->sys[sys];
+    int64_t t = -1;
+    if (step >= 0) {
+        if (step > (c->ticks_total + S.stride - 1) / S.stride) return fail(SSM_ERR_INVALID, "step past T");
+        t = step * S.stride;
+        if (t % c->max_stride != 0)
+            return fail(SSM_ERR_INVALID, "step x (h / h_min) must be a multiple of h_max / h_min "
+                                         "(a step boundary of every system)");
+        if (t > c->ticks_total) return fail(SSM_ERR_INVALID, "step past T");
+    } else if (step != -1) {
+        return fail(SSM_ERR_INVALID, "step must be >= 0, or -1 to keep the step count");
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));  // dstage may still be read by earlier work
+    surrogate_invalidate(c);
     HIP_TRY(hipMemcpyAsync(c->dstage, host, (size_t)c->d * S.N * sizeof(double), hipMemcpyHostToDevice, c->stream));
     const unsigned g = (unsigned)((S.N + kBlk - 1) / kBlk);
     if (c->prec == SSM_FP64)
@@ -1287,7 +1339,7 @@ extern "C" ssm_status ssm_set_state(ssm_ctx* c, int32_t sys, const double* host)
     else
         hipLaunchKernelGGL(k_scatter<float>, dim3(g), dim3(kBlk), 0, c->stream, c->dstage, c->P, S.off, S.N, c->d, (float*)c->X);
     HIP_TRY(hipGetLastError());
-    ssm_status st = refresh_implicit(c, sys);
+    ssm_status st = (t >= 0 && t != c->tick) ? seek_tick(c, t) : refresh_implicit(c, sys);
     if (st != SSM_OK) return st;
     return ssm_sync(c);
 }
@@ -1331,10 +1383,9 @@ extern "C" ssm_status ssm_state_refresh(ssm_ctx* c, int32_t sys)
 {
     if (!c) return fail(SSM_ERR_INVALID, "ctx is NULL");
     if (sys < -1 || sys >= (int32_t)c->sys.size()) return fail(SSM_ERR_INVALID, "sys out of range");
-    if (!c->fused) return fail(SSM_ERR_STATE, "state_refresh needs v independent of mu^X");
     ssm_status st = ssm_sync(c);
     if (st != SSM_OK) return st;
-    c->surr_res_valid = false;
+    surrogate_invalidate(c);
     for (int32_t s = (sys < 0 ? 0 : sys); s < (sys < 0 ? (int32_t)c->sys.size() : sys + 1); ++s) {
         st = refresh_implicit(c, s);
         if (st != SSM_OK) return st;
@@ -1626,6 +1677,8 @@ static ssm_status pack_weights(const float* master_dev, int d, MlpPacked* out, h
 {
     hipLaunchKernelGGL(k_mlp_pack, dim3((kHid * kStride + 255) / 256), dim3(256), 0, st, master_dev, d, out);
     HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_mlp_pack_infer, dim3(64), dim3(256), 0, st, master_dev, d, &out->inf);
+    HIP_TRY(hipGetLastError());
     return SSM_OK;
 }
 
@@ -1647,6 +1700,7 @@ extern "C" ssm_status ssm_surrogate_load(ssm_ctx* c, const float* master_host, i
     if (st != SSM_OK) return st;
     if (he != hipSuccess) return fail(SSM_ERR_HIP, std::string("surrogate_load: ") + hipGetErrorString(he));
     c->surr_loaded = true;
+    surrogate_invalidate(c);  // residuals and gains of other weights
     return SSM_OK;
 }
 
@@ -1666,6 +1720,25 @@ extern "C" ssm_status ssm_surrogate_enable(ssm_ctx* c, int32_t check_every, doub
     c->surr_res_valid = false;
     for (int k = 0; k < kMaxD; ++k) c->surr_gain[k] = 1.0;
     return SSM_OK;
+}
+
+extern "C" ssm_status ssm_surrogate_predict(ssm_ctx* c, int32_t sys, double* out, float* moments)
+{
+    if (!c || !out) return fail(SSM_ERR_INVALID, "NULL argument");
+    if (sys < 0 || sys >= (int32_t)c->sys.size()) return fail(SSM_ERR_INVALID, "sys out of range");
+    if (!c->surr_loaded) return fail(SSM_ERR_STATE, "load surrogate weights first");
+    // the tick's own launches (phase 0 lists every system) on the current Y*
+    ssm_status st = (c->prec == SSM_FP64) ? launch_surrogate<double>(c, 0) : launch_surrogate<float>(c, 0);
+    if (st != SSM_OK) return st;
+    const SysHost& S = c->sys[sys];
+    hipLaunchKernelGGL(k_gather<float>, dim3((unsigned)((S.N + kBlk - 1) / kBlk)), dim3(kBlk), 0, c->stream,
+                       (const float*)c->surr, c->P, S.off, S.N, c->d, c->dstage);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, c->dstage, (size_t)c->d * S.N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (moments)
+        HIP_TRY(hipMemcpyAsync(moments, c->mom + (int64_t)sys * 2 * kRff, 2 * kRff * sizeof(float),
+                               hipMemcpyDeviceToHost, c->stream));
+    return ssm_sync(c);
 }
 
 extern "C" ssm_status ssm_surrogate_samples(ssm_ctx* c, int32_t sys, int64_t n, uint64_t seed, float* U, float* Tt)
@@ -1716,8 +1789,8 @@ extern "C" ssm_status ssm_mlp_forward(int32_t d, const float* master, const floa
     HIP_TRY(hipMalloc((void**)&W, sizeof(MlpPacked)));
     ssm_status s = pack_weights(master, d, W, st);
     if (s == SSM_OK) {
-        const unsigned grid = (unsigned)std::min<int64_t>((n + 63) / 64, 4096);
-        hipLaunchKernelGGL(k_mlp_apply, dim3(grid), dim3(256), 0, st, U, n, d, W, out);
+        const unsigned grid = (unsigned)std::min<int64_t>((n + 127) / 128, 4096);
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_mlp_apply<D>), dim3(grid), dim3(256), 0, st, U, n, W, out));
         hipError_t he = hipGetLastError();
         if (he == hipSuccess) he = hipStreamSynchronize(st);
         if (he != hipSuccess) s = fail(SSM_ERR_HIP, std::string("mlp_forward: ") + hipGetErrorString(he));
@@ -1899,5 +1972,6 @@ extern "C" ssm_status ssm_surrogate_train(ssm_ctx* c, const ssm_surrogate_train_
     release();
     if (st != SSM_OK) return st;
     c->surr_loaded = true;
+    surrogate_invalidate(c);  // residuals and gains of other weights
     return SSM_OK;
 }

@@ -172,7 +172,8 @@ __device__ __forceinline__ void normals(uint64_t seed, uint32_t tag, uint64_t i,
 // root (q convex and increasing).  The bracket [lo, hi] is kept anyway: an
 // iterate that leaves it (possible only through rounding) is replaced by the
 // midpoint.  Iteration stops once a Newton correction is a few ulp.
-// Returns the iteration count, or -1 if max_iter is exhausted.
+// Returns the iteration count, -1 if max_iter is exhausted, or -2 (y = w) if
+// w is not finite (a corrupted particle: there is no root to find).
 // ---------------------------------------------------------------------------
 template <int D>
 __device__ __forceinline__ int implicit_radial(const double w[D], double alpha, double ha,
@@ -181,6 +182,13 @@ __device__ __forceinline__ int implicit_radial(const double w[D], double alpha, 
     double nw2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) nw2 = fma(w[k], w[k], nw2);
+    if (!isfinite(nw2)) {
+        // NaN or infinite coordinates (an overflowing |w|^2 of finite ones is
+        // far outside any state the scheme reaches): passed through, flagged
+#pragma unroll
+        for (int k = 0; k < D; ++k) y[k] = w[k];
+        return -2;
+    }
     const double nw = sqrt(nw2);
     if (nw == 0.0) {
 #pragma unroll

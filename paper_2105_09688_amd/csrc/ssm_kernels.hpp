@@ -340,29 +340,37 @@ __device__ __forceinline__ void solve_and_store(const SysDev& S, const Coef& cf,
     for (int k = 0; k < D; ++k) w[k] = x[k] + S.h * cf.v_lam * xbar[k];
     const double alpha = 1.0 - S.h * (cf.v_rho - cf.v_kappa * m2);
     int it = 0;
+    bool nonfin = false;  // a non-finite particle (from the update, or written by the caller)
     if (valid) {
         if (cf.v_cw) {
             // one scalar cubic per component: alpha y_k + h a_k y_k^3 = w_k
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const int ik = implicit_radial<1>(&w[k], alpha, S.h * cf.v_ak[k], cf.newton_max_iter, &y[k]);
-                it = (it < 0 || ik < 0) ? -1 : max(it, ik);
+                if (ik == -2) nonfin = true;
+                else it = (it < 0 || ik < 0) ? -1 : max(it, ik);
             }
         } else {
             it = implicit_radial<D>(w, alpha, S.h * cf.v_a, cf.newton_max_iter, y);
+            if (it == -2) {
+                nonfin = true;
+                it = 0;
+            }
         }
     } else {
 #pragma unroll
         for (int k = 0; k < D; ++k) y[k] = 0.0;
     }
-    // failures: one atomic per wavefront that has any; iteration counts: the
-    // wavefront's maximum into its own slot
+    // failures and non-finite particles: one atomic per wavefront that has
+    // any; iteration counts: the wavefront's maximum into its own slot
     const uint64_t fails = __ballot(it < 0);
+    const uint64_t bad = __ballot(nonfin);
     int itmax = it;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) itmax = max(itmax, __shfl_xor(itmax, off, 64));
     if ((threadIdx.x & 63) == 0) {
         if (fails) atomicAdd(&flags->newton_fail, (int)__popcll(fails));
+        if (bad) atomicAdd(&flags->nonfinite, (int)__popcll(bad));
         int32_t* slot = nmax + gb * kSlotsPerBlk + (threadIdx.x >> 6);
         if (itmax > *slot) *slot = itmax;
     }
@@ -427,6 +435,43 @@ __global__ __launch_bounds__(kBlk) void k_newton(const BlkItem* __restrict__ ite
 }
 
 // ---------------------------------------------------------------------------
+// k_xsums: block sums of x_k and |x|^2 of the listed blocks into the parity
+// slot that k_newton reads for the same `tick_arg` (the moments of mu^X that a
+// measure-dependent v needs), computed as k_update computes them, for a state
+// X written from outside the step loop.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__global__ __launch_bounds__(kBlk) void k_xsums(const BlkItem* __restrict__ items,
+                                                const SysDev* __restrict__ sys, int64_t P,
+                                                int64_t tick_arg, const T* __restrict__ X,
+                                                double* __restrict__ psumX, int64_t nblk_tot)
+{
+    __shared__ double red[kBlk];
+    const BlkItem it = items[blockIdx.x];
+    const SysDev S = sys[it.sys];
+    const int64_t done = tick_arg < 0 ? 0 : tick_arg / S.stride + 1;
+    double* pX = psumX + (int64_t)(done & 1) * (D + 1) * nblk_tot;
+    const int i = it.blk * kBlk + threadIdx.x;
+    const bool valid = i < S.N;
+    double xn[kMaxD] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) xn[k] = (double)X[k * P + S.off + i];
+    }
+    double n2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) n2 += xn[k] * xn[k];
+    const int64_t gb = S.blk0 + it.blk;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double s = block_sum(valid ? xn[k] : 0.0, red);
+        if (threadIdx.x == 0) pX[(int64_t)k * nblk_tot + gb] = s;
+    }
+    const double s2 = block_sum(valid ? n2 : 0.0, red);
+    if (threadIdx.x == 0) pX[(int64_t)D * nblk_tot + gb] = s2;
+}
+
+// ---------------------------------------------------------------------------
 // k_update: eq. (2.4) for the listed blocks at the tick *tick_dev (the
 // context's device tick counter), with the Brownian increments of
 // k_brownian_sum, then (fused) the implicit step (2.3) of the next step.
@@ -443,6 +488,7 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
                                                  const float* __restrict__ surr_mean, int use_surr,
                                                  float4 surr_gain, const float* __restrict__ surr_res,
                                                  const double* __restrict__ dWbuf,
+                                                 const double* __restrict__ ymean,
                                                  double* __restrict__ psumX,
                                                  double* __restrict__ psumY, int64_t nblk_tot,
                                                  Flags* flags, int32_t* __restrict__ nmax)
@@ -453,16 +499,20 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
     const int64_t n = tick_of(tick_dev, tick_arg) / S.stride;  // step index of this update
     const int par_in = (int)(n & 1);
     const int par_out = par_in ^ 1;
-    // mean of mu^Y_n
+    // mean of mu^Y_n, reduced by the tick's preceding launch (null: the
+    // coefficients do not use it)
     double ybar[kMaxD] = {0.0, 0.0, 0.0, 0.0};
-    system_means<D>(S, psumY + (int64_t)par_in * D * nblk_tot, nblk_tot, D, ybar, red);
+    if (ymean) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) ybar[k] = ymean[(int64_t)it.sys * kMaxD + k];
+    }
+    (void)par_in;
 
     const int i = it.blk * kBlk + threadIdx.x;
     const bool valid = i < S.N;
     const int64_t slot = S.off + i;
     double xn[kMaxD] = {0.0, 0.0, 0.0, 0.0};
     if (valid) {
-        bool bad = false;
         double yv[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) yv[k] = (double)Y[k * P + slot];
@@ -491,10 +541,10 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
             const double sig = cf.s0[k] + cf.s1[k] * y + cf.s2[k] * ybar[k];
             const double dW = dWbuf[k * P + slot];
             xn[k] = (y + S.h * b) + sig * dW;
-            bad |= !isfinite(xn[k]);
         }
-        if (bad) atomicAdd(&flags->nonfinite, 1);
     }
+    // a non-finite new state is flagged by the implicit solve that follows
+    // (here when fused, else in k_newton), on the value as stored
     double n2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -604,14 +654,46 @@ __device__ __forceinline__ void brownian_block(int vb, const BlkItem* __restrict
     }
 }
 
+// The mean of mu^Y_n of one stepping system (listed system q of the tick),
+// reduced once from its block sums in a fixed order into ymean[s][k] for
+// k_update (which would otherwise reduce all of the system's block sums in
+// every one of its blocks: 4096 x 4096 x d reads at N = 2^20).
+struct YMeanJob {
+    const int32_t* sys_list;  // the tick's stepping systems
+    int n;                    // how many (0: the coefficients do not use the mean)
+    const double* psumY;
+    int64_t nblk_tot;
+    double* ymean;            // [n_sys][kMaxD]
+};
+
+template <int D>
+__device__ __forceinline__ void ymean_block(int q, const YMeanJob& job, const SysDev* __restrict__ sys,
+                                            int64_t tick_arg, const int64_t* __restrict__ tick_dev)
+{
+    __shared__ double red[kBlk];
+    const int s = job.sys_list[q];
+    const SysDev S = sys[s];
+    const int64_t n = tick_of(tick_dev, tick_arg) / S.stride;
+    double m[kMaxD];
+    system_means<D>(S, job.psumY + (int64_t)(n & 1) * D * job.nblk_tot, job.nblk_tot, D, m, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < D; ++k) job.ymean[(int64_t)s * kMaxD + k] = m[k];
+}
+
+// n_main blocks of Brownian sums, then job.n blocks of system means.
 template <int D, int LP>
-__global__ __launch_bounds__(kBlk) void k_brownian_sum(const BlkItem* __restrict__ items,
+__global__ __launch_bounds__(kBlk) void k_brownian_sum(int n_main, const BlkItem* __restrict__ items,
                                                        const SysDev* __restrict__ sys, Coef cf,
                                                        int64_t P, int64_t tick_arg,
                                                        const int64_t* __restrict__ tick_dev,
-                                                       const double* __restrict__ win, double* __restrict__ dW)
+                                                       const double* __restrict__ win, double* __restrict__ dW,
+                                                       YMeanJob job)
 {
-    brownian_block<D, LP>(blockIdx.x, items, sys, cf, P, tick_arg, tick_dev, win, dW);
+    if ((int)blockIdx.x < n_main)
+        brownian_block<D, LP>(blockIdx.x, items, sys, cf, P, tick_arg, tick_dev, win, dW);
+    else
+        ymean_block<D>(blockIdx.x - n_main, job, sys, tick_arg, tick_dev);
 }
 
 // k_bm_window: the window of a path group, drawn at its first tick t0
@@ -646,23 +728,26 @@ __global__ __launch_bounds__(kBlk) void k_bm_window(const BlkItem* __restrict__ 
     }
 }
 
-// k_prep: the combine (first n_combine blocks) and the Brownian sums (the
-// rest) of an exact tick in one launch; the two are independent, so the
-// HBM-bound combine runs beside the FP64-bound Philox/Box-Muller work.
+// k_prep: the combine (first n_combine blocks), the Brownian sums (up to
+// n_main) and the system means (job.n blocks) of an exact tick in one launch;
+// the parts are independent, so the HBM-bound combine runs beside the
+// FP64-bound Philox/Box-Muller work.
 template <typename PT, int D, int LP>
-__global__ __launch_bounds__(kBlk) void k_prep(int n_combine, const BlkItem* __restrict__ items,
+__global__ __launch_bounds__(kBlk) void k_prep(int n_combine, int n_main, const BlkItem* __restrict__ items,
                                                const SysDev* __restrict__ sys, Coef cf, int64_t P,
                                                const PT* __restrict__ Bp, const PT* __restrict__ Bpj,
                                                double* __restrict__ pairsum, int64_t tick_arg,
                                                const int64_t* __restrict__ tick_dev, const double* __restrict__ win,
-                                               double* __restrict__ dW)
+                                               double* __restrict__ dW, YMeanJob job)
 {
     static_assert(64 * kCombineWaves == kBlk, "one block shape for both parts");
     __shared__ double part[kCombineWaves][D][64];
     if ((int)blockIdx.x < n_combine)
         combine_block<PT, D>(blockIdx.x, items, sys, P, Bp, Bpj, pairsum, part);
-    else
+    else if ((int)blockIdx.x < n_main)
         brownian_block<D, LP>(blockIdx.x - n_combine, items, sys, cf, P, tick_arg, tick_dev, win, dW);
+    else
+        ymean_block<D>(blockIdx.x - n_main, job, sys, tick_arg, tick_dev);
 }
 
 // Advance the context's device tick counter (last launch of every tick).

@@ -28,8 +28,28 @@ constexpr int kRffWaves = 4;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Inference layout (k_mlp_infer, k_mlp_apply).  The products run transposed,
+// D = W (16 outputs x K) * act^T (K x 16 samples): each lane then holds, for
+// its sample l % 16, the outputs 16 nt + 4 (l / 16) + i of every output tile
+// nt, which are exactly the eight K entries it must supply to the next layer's
+// B operand once the next layer's input columns are taken in the order
+//   K slice ks, entry k (0..31)  <->  input feature (2 ks + (k % 8) / 4) 16 + 4 (k / 8) + k % 4.
+// So an activation never leaves its lane; the permutation is applied to the
+// weights once, when they are packed, and every A operand is stored in lane
+// order (lane l's 8 BF16 at [l]), one conflict-free 16-byte LDS read each.
+// Layer 1 takes only the position columns [hi(y), lo(y)] on the matrix cores;
+// the moment columns act on per-system constants, so their product with the
+// moments is a per-system bias computed in FP32 (W1m below).
+struct MlpInfer {
+    bf16x8 W1[4][64];         // [out tile][lane]: W1[16 nt + l % 16][k], k = 8 (l / 16) + j < 2 d, else 0
+    bf16x8 W2[4][2][64];      // [out tile][K slice][lane], permuted input columns
+    bf16x8 W3[4][2][64];
+    bf16x8 W4[2][64];         // [K slice][lane]: rows l % 16 < d
+    float W1m[kHid][2 * kRff];  // moment columns of W1 (BF16 values) as float
+};
+
 // Packed device weights: BF16 row-major [out][in] rows padded to kStride, and
-// the transposes needed by the backward pass; FP32 biases.
+// the transposes needed by the backward pass; FP32 biases; the inference layout.
 struct MlpPacked {
     __bf16 W1[kHid * kStride];      // [64 out][64 in (d + 2K used)]
     __bf16 W2[kHid * kStride];
@@ -39,6 +59,7 @@ struct MlpPacked {
     __bf16 W3t[kHid * kStride];
     __bf16 W4t[kHid * kStrideT4];   // [64 in][32 out (d used)]
     float b1[kHid], b2[kHid], b3[kHid], b4[kOutPad];
+    MlpInfer inf;
 };
 
 // Flat master layout (FP32), as the oracle's: W1[64][in] b1[64] W2[64][64] b2
@@ -143,6 +164,53 @@ __global__ void k_mlp_pack(const float* __restrict__ master, int d, MlpPacked* _
     }
 }
 
+// The inference layout of master (flat FP32) weights: A operands in lane
+// order with the permuted input columns of layers 2-4, and the moment columns
+// of W1 as float (of their BF16 values).
+__host__ __device__ constexpr int infer_feature(int ks, int k) { return (2 * ks + (k % 8) / 4) * 16 + 4 * (k / 8) + k % 4; }
+
+__global__ void k_mlp_pack_infer(const float* __restrict__ master, int d, MlpInfer* __restrict__ P)
+{
+    const MlpOffsets o = mlp_offsets(d);
+    const int in = mlp_in(d);
+    const int nW1 = 4 * 64 * 8, nW2 = 4 * 2 * 64 * 8, nW4 = 2 * 64 * 8, nM = kHid * 2 * kRff;
+    const int total = nW1 + 2 * nW2 + nW4 + nM;
+    // element stores through scalar pointers (flat index = the array's own
+    // [..][lane][j] order): one thread per BF16 value, no shared 16-byte word
+    __bf16* w1 = (__bf16*)P->W1;
+    __bf16* w2 = (__bf16*)P->W2;
+    __bf16* w3 = (__bf16*)P->W3;
+    __bf16* w4 = (__bf16*)P->W4;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        int q = e;
+        if (q < nW1) {
+            const int nt = q / 512, l = (q / 8) % 64, j = q % 8, k = 8 * (l / 16) + j;
+            w1[q] = (__bf16)((k < 2 * d) ? master[o.W1 + (int64_t)(16 * nt + l % 16) * in + k] : 0.0f);
+            continue;
+        }
+        q -= nW1;
+        if (q < 2 * nW2) {
+            const int layer = q / nW2;
+            q %= nW2;
+            const int nt = q / 1024, ks = (q / 512) % 2, l = (q / 8) % 64, j = q % 8;
+            const int f = infer_feature(ks, 8 * (l / 16) + j);
+            const int64_t base = layer == 0 ? o.W2 : o.W3;
+            (layer == 0 ? w2 : w3)[q] = (__bf16)master[base + (int64_t)(16 * nt + l % 16) * kHid + f];
+            continue;
+        }
+        q -= 2 * nW2;
+        if (q < nW4) {
+            const int ks = q / 512, l = (q / 8) % 64, j = q % 8, m = l % 16;
+            const int f = infer_feature(ks, 8 * (l / 16) + j);
+            w4[q] = (__bf16)((m < d) ? master[o.W4 + (int64_t)m * kHid + f] : 0.0f);
+            continue;
+        }
+        q -= nW4;
+        const int r = q / (2 * kRff), c = q % (2 * kRff);
+        P->W1m[r][c] = (float)(__bf16)master[o.W1 + (int64_t)r * in + 2 * d + c];
+    }
+}
+
 // Copy the forward weights (W1..W4, biases) into LDS.
 __device__ __forceinline__ void load_fwd_weights(const MlpPacked* __restrict__ P, __bf16* sW1, __bf16* sW2,
                                                  __bf16* sW3, __bf16* sW4, float* sb)
@@ -227,113 +295,6 @@ __device__ __forceinline__ void build_input_row(const float* r, int d, bf16x8 a[
             }
             a[ks][i] = v;
         }
-}
-
-// Split-precision activations for inference: every A operand is carried as
-// hi + lo with hi = bf16(v) and lo = bf16(v - hi) (about 16 significant bits),
-// and each product W x runs as W hi + W lo (two MFMAs per K slice).  The
-// weights stay BF16 (the network is trained with them), so the network stays
-// a smooth function of its inputs; plain BF16 activations add rounding noise
-// of order 1e-3 relative that changes from one step to the next.
-template <int NT>
-__device__ __forceinline__ void dense_tiles_split(const __bf16* W, const bf16x8 ah[2], const bf16x8 al[2],
-                                                  f32x4 acc[NT])
-{
-    const int l = threadIdx.x & 63;
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const bf16x8 b = *(const bf16x8*)&W[(nt * 16 + (l & 15)) * kStride + ks * 32 + 8 * (l >> 4)];
-            c = mfma_bf16(al[ks], b, c);
-            c = mfma_bf16(ah[ks], b, c);
-        }
-        acc[nt] = c;
-    }
-}
-
-// d_to_a for split activations: two LDS tiles [16][kStride] (hi, lo).
-template <int NT>
-__device__ __forceinline__ void d_to_a_split(const f32x4 v[NT], __bf16* th, __bf16* tl, bf16x8 ah[2],
-                                             bf16x8 al[2])
-{
-    const int l = threadIdx.x & 63;
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int q = (4 * (l >> 4) + i) * kStride + nt * 16 + (l & 15);
-            th[q] = bf_hi(v[nt][i]);
-            tl[q] = bf_lo(v[nt][i]);
-        }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-        ah[ks] = *(const bf16x8*)&th[(l & 15) * kStride + ks * 32 + 8 * (l >> 4)];
-        al[ks] = *(const bf16x8*)&tl[(l & 15) * kStride + ks * 32 + 8 * (l >> 4)];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Input features u = [hi(y), lo(y), m] as hi + lo parts: the coordinate
-// features are BF16 values already (lo part 0); each moment m splits into
-// bf16(m) + bf16(m - bf16(m)).  y0..y3: coordinates; mom: the 2K moments
-// (null: an all-zero row).
-__device__ __forceinline__ void build_input_split(float y0, float y1, float y2, float y3, const float* mom, int d,
-                                                  bf16x8 ah[2], bf16x8 al[2])
-{
-    const int l = threadIdx.x & 63;
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int k = ks * 32 + 8 * (l >> 4) + i;
-            __bf16 vh = (__bf16)0.0f, vl = (__bf16)0.0f;
-            if (mom && k < 2 * d) {
-                const int c = k < d ? k : k - d;
-                const float yc = (c == 0) ? y0 : (c == 1) ? y1 : (c == 2) ? y2 : y3;
-                vh = k < d ? bf_hi(yc) : bf_lo(yc);
-            } else if (mom && k < 2 * d + 2 * kRff) {
-                const float m = mom[k - 2 * d];
-                vh = bf_hi(m);
-                vl = bf_lo(m);
-            }
-            ah[ks][i] = vh;
-            al[ks][i] = vl;
-        }
-}
-
-// Split-precision forward of the wavefront's 16 samples (inference only):
-// output tile in D layout, columns 0..d-1 valid, bias added.
-__device__ __forceinline__ void mlp_forward16_split(const __bf16* sW1, const __bf16* sW2, const __bf16* sW3,
-                                                    const __bf16* sW4, const float* sb, bf16x8 ah[2], bf16x8 al[2],
-                                                    __bf16* th, __bf16* tl, f32x4& out)
-{
-    const int l = threadIdx.x & 63;
-    const __bf16* Ws[3] = {sW1, sW2, sW3};
-#pragma unroll
-    for (int layer = 0; layer < 3; ++layer) {
-        f32x4 acc[4];
-        dense_tiles_split<4>(Ws[layer], ah, al, acc);
-        f32x4 hv[4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const float bias = sb[layer * kHid + nt * 16 + (l & 15)];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) hv[nt][i] = silu_f(acc[nt][i] + bias);
-        }
-        d_to_a_split<4>(hv, th, tl, ah, al);
-    }
-    f32x4 o[1];
-    dense_tiles_split<1>(sW4, ah, al, o);
-    const float b4 = sb[3 * kHid + (l & 15)];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) out[i] = o[0][i] + b4;
 }
 
 // Forward pass of the wavefront's 16 samples.  Returns the output tile
@@ -436,9 +397,192 @@ __global__ __launch_bounds__(kBlk) void k_rff_final(const int32_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Inference: surrogate pair term for every particle of the listed blocks.
-// Each wavefront takes 16 consecutive particles of a 256-particle block.
-// Writes surr[k][slot] (FP32) for k < d.
+// Inference (split precision).  Every activation enters the matrix cores as
+// hi + lo with hi = bf16(v) and lo = bf16(v - hi) (about 16 significant bits),
+// each product as W hi + W lo; the weights stay BF16 (the network is trained
+// with them), so the network stays a smooth function of its inputs (plain
+// BF16 activations add rounding noise of order 1e-3 relative that changes
+// from one step to the next).  A wavefront runs two 16-sample tiles at a
+// time in the transposed layout of MlpInfer.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Two floats -> packed BF16 (one v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b)
+{
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
+// hi / lo B operands of 8 values (4 from each of two output tiles).
+__device__ __forceinline__ void split8(const f32x4& a, const f32x4& b, bf16x8& hi, bf16x8& lo)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 h, l;
+    const float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t hp = pk_bf16(v[2 * q], v[2 * q + 1]);
+        h[q] = hp;
+        l[q] = pk_bf16(v[2 * q] - __uint_as_float(hp << 16), v[2 * q + 1] - __uint_as_float(hp & 0xffff0000u));
+    }
+    hi = __builtin_bit_cast(bf16x8, h);
+    lo = __builtin_bit_cast(bf16x8, l);
+}
+
+// The hidden layers run on scaled values u = -log2(e) z (pre-activations)
+// and a~ = -log2(e) a (activations): every hidden layer's input and bias
+// carry the factor, so its output is u directly (the product is linear), and
+//   a~ = -log2(e) z sigma(z) = u / (1 + 2^u)
+// with the hardware exp2 and reciprocal (sigma(z) = 1 / (1 + e^-z)).  The
+// factor enters before the hi / lo split, so it costs no precision.  Layer 1
+// scales its output (its inputs hi(y), lo(y) are features of their own, with
+// their own weights, and are taken as they are); the output layer undoes the
+// factor once.
+constexpr float kNegLog2e = -1.4426950408889634f;
+constexpr float kNegLn2 = -0.6931471805599453f;
+
+__device__ __forceinline__ float silu_scaled(float u) { return u * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(u)); }
+
+// SiLU of a layer's four output tiles (scaled), split into the next layer's
+// operands (K slice 0: tiles 0, 1; slice 1: tiles 2, 3).
+__device__ __forceinline__ void act_split(f32x4 (&acc)[4], bf16x8 (&hi)[2], bf16x8 (&lo)[2])
+{
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[nt][i] = silu_scaled(acc[nt][i]);
+    split8(acc[0], acc[1], hi[0], lo[0]);
+    split8(acc[2], acc[3], hi[1], lo[1]);
+}
+
+// LDS copy of the inference weights and biases (-log2(e) b2, -log2(e) b3, -log2(e) b4).
+struct InferLds {
+    bf16x8 W1[4][64];
+    bf16x8 W2[4][2][64];
+    bf16x8 W3[4][2][64];
+    bf16x8 W4[2][64];
+    float b[2 * kHid + kOutPad];
+};
+
+__device__ __forceinline__ void load_infer(const MlpPacked* __restrict__ P, InferLds& L)
+{
+    const uint4* src[4] = {(const uint4*)P->inf.W1, (const uint4*)P->inf.W2, (const uint4*)P->inf.W3,
+                           (const uint4*)P->inf.W4};
+    uint4* dst[4] = {(uint4*)L.W1, (uint4*)L.W2, (uint4*)L.W3, (uint4*)L.W4};
+    const int n[4] = {4 * 64, 8 * 64, 8 * 64, 2 * 64};
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        for (int q = threadIdx.x; q < n[m]; q += blockDim.x) dst[m][q] = src[m][q];
+    for (int q = threadIdx.x; q < 2 * kHid + kOutPad; q += blockDim.x)
+        L.b[q] = kNegLog2e * (q < kHid ? P->b2[q] : q < 2 * kHid ? P->b3[q - kHid] : P->b4[q - 2 * kHid]);
+}
+
+// acc[nt][i] = v[16 nt + 4 (l / 16) + i]: a bias vector in the D layout.
+__device__ __forceinline__ void bias_tiles(const float* v, f32x4 (&acc)[4])
+{
+    const int g = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = *(const f32x4*)&v[16 * nt + 4 * g];
+}
+
+// One hidden layer (64 -> 64) for two tiles; acc in: bias, out: pre-activation.
+__device__ __forceinline__ void hidden_layer2(const bf16x8 (*W)[2][64], const bf16x8 (&h0)[2], const bf16x8 (&l0)[2],
+                                              const bf16x8 (&h1)[2], const bf16x8 (&l1)[2], f32x4 (&a0)[4],
+                                              f32x4 (&a1)[4])
+{
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const bf16x8 w = W[nt][ks][l];
+            a0[nt] = mfma_bf16(w, l0[ks], a0[nt]);
+            a1[nt] = mfma_bf16(w, l1[ks], a1[nt]);
+            a0[nt] = mfma_bf16(w, h0[ks], a0[nt]);
+            a1[nt] = mfma_bf16(w, h1[ks], a1[nt]);
+        }
+}
+
+// The network for two tiles of 16 samples.  yin[t][c]: coordinate c of the
+// lane's sample l % 16 in tile t; c1[t]: layer 1's bias plus its moment part
+// for tile t, in the D layout.  out[t]: D layout of the output tile (lane l,
+// l < 16: components 0..3 of sample l; bias added).
+template <int D>
+__device__ __forceinline__ void mlp_infer_pair(const InferLds& L, const float (&yin)[2][kMaxD], f32x4 (&c1)[2][4],
+                                               f32x4 (&out)[2])
+{
+    const int l = threadIdx.x & 63;
+    const int g = l >> 4;
+    // layer 1: K slice [hi(y), lo(y), 0 ...]; lanes of group 0 hold the entries
+    bf16x8 x[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            __bf16 v = (__bf16)0.0f;
+            if (g == 0 && j < 2 * D) {
+                const float y = yin[t][j < D ? j : j - D];
+                v = j < D ? (__bf16)y : (__bf16)(y - (float)(__bf16)y);
+            }
+            x[t][j] = v;
+        }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const bf16x8 w = L.W1[nt][l];
+        c1[0][nt] = mfma_bf16(w, x[0], c1[0][nt]);
+        c1[1][nt] = mfma_bf16(w, x[1], c1[1][nt]);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) c1[t][nt][i] *= kNegLog2e;
+    bf16x8 h0[2], l0[2], h1[2], l1[2];
+    act_split(c1[0], h0, l0);
+    act_split(c1[1], h1, l1);
+    f32x4 a0[4], a1[4];
+    bias_tiles(&L.b[0], a0);
+    bias_tiles(&L.b[0], a1);
+    hidden_layer2(L.W2, h0, l0, h1, l1, a0, a1);
+    act_split(a0, h0, l0);
+    act_split(a1, h1, l1);
+    bias_tiles(&L.b[kHid], a0);
+    bias_tiles(&L.b[kHid], a1);
+    hidden_layer2(L.W3, h0, l0, h1, l1, a0, a1);
+    act_split(a0, h0, l0);
+    act_split(a1, h1, l1);
+    out[0] = out[1] = *(const f32x4*)&L.b[2 * kHid + 4 * g];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        const bf16x8 w = L.W4[ks][l];
+        out[0] = mfma_bf16(w, l0[ks], out[0]);
+        out[1] = mfma_bf16(w, l1[ks], out[1]);
+        out[0] = mfma_bf16(w, h0[ks], out[0]);
+        out[1] = mfma_bf16(w, h1[ks], out[1]);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[t][i] *= kNegLn2;
+}
+
+// Layer 1's bias plus its moment columns times the moments m (FP32, ascending
+// moment index), for output feature o.
+__device__ __forceinline__ float layer1_const(const MlpPacked* __restrict__ P, int o, const float* m)
+{
+    float a = P->b1[o];
+#pragma unroll 8
+    for (int q = 0; q < 2 * kRff; ++q) a = fmaf(P->inf.W1m[o][q], m[q], a);
+    return a;
+}
+
+// ---------------------------------------------------------------------------
+// k_mlp_infer: surrogate pair term for every particle of the listed blocks
+// (256 particles each): surr[k][slot] (FP32) for k < d.  Wavefront w takes
+// the tiles 4 w .. 4 w + 3 of a block, two at a time.
 // ---------------------------------------------------------------------------
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_mlp_infer(const BlkItem* __restrict__ items, int n_items,
@@ -446,78 +590,88 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const BlkItem* __restrict__ i
                                                    const T* __restrict__ Y, const float* __restrict__ mom,
                                                    const MlpPacked* __restrict__ W, float* __restrict__ surr)
 {
-    __shared__ __align__(16) __bf16 sW1[kHid * kStride];
-    __shared__ __align__(16) __bf16 sW2[kHid * kStride];
-    __shared__ __align__(16) __bf16 sW3[kHid * kStride];
-    __shared__ __align__(16) __bf16 sW4[kOutPad * kStride];
-    __shared__ float sb[3 * kHid + kOutPad];
-    __shared__ __align__(16) __bf16 tiles[4][2][16 * kStride];
-    __shared__ float smom[2 * kRff];
-    load_fwd_weights(W, sW1, sW2, sW3, sW4, sb);
-    __syncthreads();
+    __shared__ InferLds L;
+    __shared__ __align__(16) float c1s[kHid];
+    load_infer(W, L);
     const int wave = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
+    int cur_sys = -1;
     for (int itx = blockIdx.x; itx < n_items; itx += gridDim.x) {
         const BlkItem it = items[itx];
         const SysDev S = sys[it.sys];
+        if (it.sys != cur_sys) {  // block-uniform
+            __syncthreads();
+            if (threadIdx.x < kHid) c1s[threadIdx.x] = layer1_const(W, threadIdx.x, mom + (int64_t)it.sys * (2 * kRff));
+            cur_sys = it.sys;
+        }
         __syncthreads();
-        if (threadIdx.x < 2 * kRff) smom[threadIdx.x] = mom[(int64_t)it.sys * (2 * kRff) + threadIdx.x];
-        __syncthreads();
-        // 256 particles per block item, 16 per wavefront pass
-        for (int sub = wave; sub < kBlk / 16; sub += 4) {
-            const int i0 = it.blk * kBlk + sub * 16;
-            if (i0 >= S.N) continue;  // wave-uniform
-            const int i = i0 + (l & 15);
-            float y[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+        for (int tp = 0; tp < 2; ++tp) {
+            const int i0 = it.blk * kBlk + (4 * wave + 2 * tp) * 16;
+            if (i0 >= S.N) break;  // wave-uniform
+            float yin[2][kMaxD] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
 #pragma unroll
-            for (int k = 0; k < D; ++k) y[k] = (i < S.N) ? (float)Y[k * P + S.off + i] : 0.0f;
-            bf16x8 ah[2], al[2];
-            build_input_split(y[0], y[1], y[2], y[3], smom, D, ah, al);
-            f32x4 out;
-            mlp_forward16_split(sW1, sW2, sW3, sW4, sb, ah, al, tiles[wave][0], tiles[wave][1], out);
-            // out: rows 4 (l/16) + r (samples), column l % 16 (output component)
-            const int comp = l & 15;
-            if (comp < D) {
+            for (int t = 0; t < 2; ++t) {
+                const int i = i0 + 16 * t + (l & 15);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int ii = i0 + 4 * (l >> 4) + r;
-                    if (ii < S.N) surr[(int64_t)comp * P + S.off + ii] = out[r];
+                for (int k = 0; k < D; ++k) yin[t][k] = (i < S.N) ? (float)Y[k * P + S.off + i] : 0.0f;
+            }
+            f32x4 c1[2][4], out[2];
+            bias_tiles(c1s, c1[0]);
+            bias_tiles(c1s, c1[1]);
+            mlp_infer_pair<D>(L, yin, c1, out);
+            if (l < 16) {
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int i = i0 + 16 * t + l;
+                    if (i < S.N)
+#pragma unroll
+                        for (int k = 0; k < D; ++k) surr[(int64_t)k * P + S.off + i] = out[t][k];
                 }
             }
         }
     }
 }
 
-// Inference on explicit raw rows U [n][d + 2K] -> out [n][d].
-__global__ __launch_bounds__(256) void k_mlp_apply(const float* __restrict__ U, int64_t n, int d,
+// Inference on explicit raw rows U [n][d + 2K] -> out [n][d]: the same
+// network, with layer 1's moment part computed per row (each lane for its
+// sample and its 16 output features).
+template <int D>
+__global__ __launch_bounds__(256) void k_mlp_apply(const float* __restrict__ U, int64_t n,
                                                    const MlpPacked* __restrict__ W, float* __restrict__ out)
 {
-    __shared__ __align__(16) __bf16 sW1[kHid * kStride];
-    __shared__ __align__(16) __bf16 sW2[kHid * kStride];
-    __shared__ __align__(16) __bf16 sW3[kHid * kStride];
-    __shared__ __align__(16) __bf16 sW4[kOutPad * kStride];
-    __shared__ float sb[3 * kHid + kOutPad];
-    __shared__ __align__(16) __bf16 tiles[4][2][16 * kStride];
-    load_fwd_weights(W, sW1, sW2, sW3, sW4, sb);
+    __shared__ InferLds L;
+    load_infer(W, L);
     __syncthreads();
     const int wave = threadIdx.x >> 6;
     const int l = threadIdx.x & 63;
-    const int in = raw_in(d);
-    for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 16; r0 < n; r0 += (int64_t)gridDim.x * 64) {
-        const int64_t row = r0 + (l & 15);
-        const float* r = row < n ? U + row * in : nullptr;
-        float yv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int k = 0; k < d && r; ++k) yv[k] = r[k];
-        bf16x8 ah[2], al[2];
-        build_input_split(yv[0], yv[1], yv[2], yv[3], r ? r + d : nullptr, d, ah, al);
-        f32x4 o;
-        mlp_forward16_split(sW1, sW2, sW3, sW4, sb, ah, al, tiles[wave][0], tiles[wave][1], o);
-        const int comp = l & 15;
-        if (comp < d) {
+    const int g = l >> 4;
+    constexpr int in = raw_in(D);
+    for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 32; r0 < n; r0 += (int64_t)gridDim.x * 128) {
+        float yin[2][kMaxD] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+        f32x4 c1[2][4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t rr = r0 + 4 * (l >> 4) + r;
-                if (rr < n) out[rr * d + comp] = o[r];
+        for (int t = 0; t < 2; ++t) {
+            const int64_t row = r0 + 16 * t + (l & 15);
+            float m[2 * kRff];
+#pragma unroll
+            for (int q = 0; q < 2 * kRff; ++q) m[q] = row < n ? U[row * in + D + q] : 0.0f;
+#pragma unroll
+            for (int k = 0; k < D; ++k) yin[t][k] = row < n ? U[row * in + k] : 0.0f;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) c1[t][nt][i] = layer1_const(W, 16 * nt + 4 * g + i, m);
+        }
+        f32x4 o[2];
+        mlp_infer_pair<D>(L, yin, c1, o);
+        if (l < 16) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int64_t row = r0 + 16 * t + l;
+                if (row < n)
+#pragma unroll
+                    for (int k = 0; k < D; ++k) out[row * D + k] = o[t][k];
             }
         }
     }

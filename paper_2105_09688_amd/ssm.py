@@ -125,9 +125,19 @@ class SSM:
     def states(self, which: str = "x"):
         return [self.state(s, which) for s in range(len(self.N))]
 
-    def set_state(self, sys: int, X) -> None:
+    def state_step(self, sys: int = 0, which: str = "x"):
+        """(state [d][N] as float64, steps system sys has taken) (ssm_get_state)."""
+        out = np.zeros((self.d, self.N[sys]))
+        step = C.c_int64()
+        check(_lib.load().ssm_get_state(self._h, sys, 0 if which == "x" else 1,
+                                        out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(step)))
+        return out, step.value
+
+    def set_state(self, sys: int, X, step: int = -1) -> None:
+        """X of system sys (ssm_set_state); step >= 0 also moves the context to
+        that step of system sys (a resume on the same Brownian paths)."""
         X = np.ascontiguousarray(X, dtype=np.float64).reshape(self.d, self.N[sys])
-        check(_lib.load().ssm_set_state(self._h, sys, X.ctypes.data_as(C.POINTER(C.c_double))))
+        check(_lib.load().ssm_set_state(self._h, sys, X.ctypes.data_as(C.POINTER(C.c_double)), int(step)))
 
     def surrogate_train(self, n_samples: int, n_ens: int = 2, ens0: int = 1, N: int = 0, snapshots: int = 32,
                         steps: int = 4000, batch: int = 2048, lr: float = 1e-3, seed: int = 0, init=None):
@@ -205,6 +215,15 @@ class SSM:
         if mode not in modes:
             raise ValueError(f"mode must be one of {sorted(modes)}")
         check(_lib.load().ssm_surrogate_enable(self._h, int(check_every), float(tol), modes[mode]))
+
+    def surrogate_predict(self, sys: int = 0):
+        """(network output s [d][N] float64, RFF moments [2K] float32) at the
+        current Y* of system sys, from the surrogate tick's kernels."""
+        out = np.zeros((self.d, self.N[sys]))
+        mom = np.zeros(32, dtype=np.float32)
+        check(_lib.load().ssm_surrogate_predict(self._h, sys, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                                mom.ctypes.data))
+        return out, mom
 
     def surrogate_samples(self, n: int, seed: int, sys: int = 0):
         """(U [n][d+32], T [n][d]) float32 device tensors from the current state."""

@@ -81,6 +81,143 @@ def test_mfma_forward_matches_oracle(torch_cuda):
     assert rel <= 5e-5
 
 
+# Element-wise bar of the split-precision inference against the oracle's
+# FP64 forward at the same (BF16-rounded) weights: each activation enters the
+# matrix cores as hi + lo BF16 parts (about 16 significant bits, relative
+# rounding <= 2^-17), products accumulate in FP32 over K = 64, and four layers
+# compound it; at unit-size outputs this is a few 1e-6 absolute.  The bar
+# max_i |got_i - ref_i| / max(1, |ref_i|) <= 5e-5 leaves an order of magnitude
+# of room and is still 60x below the error of plain BF16 activations (about
+# 3e-3, which the test also shows the bar would catch).
+ELEMENT_BAR = 5e-5
+
+
+def _elem_err(got, ref):
+    return float(np.max(np.abs(got - ref) / np.maximum(1.0, np.abs(ref))))
+
+
+@pytest.mark.parametrize("n", [1000, 4099])
+def test_mlp_apply_elementwise_matches_oracle(torch_cuda, n):
+    """ssm_mlp_forward (k_mlp_apply) on n raw rows (ragged: not a multiple of
+    the 16-row tile or the 64-row block) against oracle.mlp_forward element
+    by element, with the moments passed unrounded (the split inference carries
+    them to about 16 bits)."""
+    torch = torch_cuda
+    from paper_2105_09688_amd.ssm import mlp_forward, mlp_init
+    p = mlp_init(D, seed=11)
+    p += np.random.default_rng(12).normal(size=p.size).astype(np.float32) * 0.05
+    rng = np.random.default_rng(13)
+    U = np.concatenate([rng.normal(size=(n, D)) * 1.5, rng.uniform(-1, 1, size=(n, 32))], axis=1).astype(np.float32)
+    got = mlp_forward(D, torch.tensor(p, device="cuda"), torch.tensor(U, device="cuda")).cpu().numpy()
+    ref = oracle.mlp_forward(_kernel_params(p), _expand(U, round_moments=False), IN_NET, 64, D)
+    err = _elem_err(got, ref)
+    # what plain BF16 activations would give: the bar separates the two
+    ref_bf = oracle.mlp_forward(_kernel_params(p), _expand(U), IN_NET, 64, D)
+    _say(f"mlp_apply n={n}: element-wise err {err:.3e} (moments rounded to BF16: {_elem_err(ref_bf, ref):.3e})")
+    assert got.shape == (n, D)
+    assert err <= ELEMENT_BAR
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
+def test_mlp_infer_in_step_matches_oracle_elementwise(torch_cuda, precision):
+    """The kernels a surrogate tick runs (RFF moments, then k_mlp_infer over
+    the context's SoA Y*, stored per component) in one context of two systems
+    of ragged sizes (1000 and 4099, ensembles 0 and 1), each set to the
+    oracle's X_3 of its own run (ssm_set_state at step 3), so that Y* is the
+    oracle's F_h(X_3).  Against the oracle:
+      - the RFF moments of mu^Y per system (FP32 sin/cos in the kernel):
+        max abs difference <= 2e-6;
+      - the network output per particle and component, element-wise against
+        oracle.mlp_forward at the oracle's own Y* and moments: <= 1e-4 (the
+        element bar plus the moments' 2e-6 through the first layer);
+      - the same against oracle.mlp_forward at the GPU's moments: the element bar."""
+    from paper_2105_09688_amd.ssm import SSM, mlp_init
+    h = 2.0 ** -9
+    w = W.surrogate_d2(N=1000, h=h, h_fine=h)
+    w["systems"] = [(1000, 0, h), (4099, 1, h)]
+    w["T"] = 8 * h
+    p = mlp_init(D, seed=21)
+    p += np.random.default_rng(22).normal(size=p.size).astype(np.float32) * 0.05
+    om = oracle.rff_omegas(w["seed"], D, 16, w["b"]["ell"])
+    ref_states = []
+    for (N, e, _h) in w["systems"]:
+        X = oracle.init_state(w, e, N)
+        for n in range(3):
+            X, _ = oracle.step(w, e, h, n, X)
+        _, Y = oracle.step(w, e, h, 3, X)
+        ref_states.append((X, Y))
+    with SSM(w, precision=precision) as s:
+        for k, (X, _Y) in enumerate(ref_states):
+            s.set_state(k, X, step=3)
+        s.surrogate_load(p)
+        for k, (N, e, _h) in enumerate(w["systems"]):
+            X, Y = ref_states[k]
+            Yg = s.state(k, "y")
+            out, mom = s.surrogate_predict(k)
+            ydiff = float(np.max(np.abs(Yg - Y)))
+            mref = oracle.rff_moments(Y, om)
+            merr = float(np.max(np.abs(mom.astype(np.float64) - mref)))
+            rows_o = np.concatenate([Y.T, np.broadcast_to(mref, (N, 32))], axis=1)
+            ref_o = oracle.mlp_forward(_kernel_params(p), _expand(rows_o, round_moments=False), IN_NET, 64, D)
+            rows_g = np.concatenate([Yg.T, np.broadcast_to(mom.astype(np.float64), (N, 32))], axis=1)
+            ref_g = oracle.mlp_forward(_kernel_params(p), _expand(rows_g, round_moments=False), IN_NET, 64, D)
+            e_o, e_g = _elem_err(out.T, ref_o), _elem_err(out.T, ref_g)
+            _say(f"infer {precision} sys {k} N={N}: |Y* - oracle| {ydiff:.2e}, moments {merr:.2e}, "
+                 f"output vs oracle (own moments) {e_o:.3e}, (GPU moments) {e_g:.3e}")
+            assert out.shape == (D, N)
+            assert ydiff <= (1e-14 if precision == "fp64" else 1e-6)
+            assert merr <= 2e-6
+            assert e_o <= 1e-4
+            assert e_g <= ELEMENT_BAR
+
+
+def test_adam_steps_match_the_adam_update(torch_cuda):
+    """ssm_mlp_train's optimizer (k_adam) against Adam's update (Kingma & Ba,
+    bias-corrected), for one step and for the second step of a two-step call:
+    one distinct training row, so every minibatch row is that row and each
+    step's gradient is ssm_mlp_loss_grad at the current weights on 64 copies
+    of it.  m_t = b1 m + (1 - b1) g, v_t = b2 v + (1 - b2) g^2,
+    w -= lr (m_t / (1 - b1^t)) / (sqrt(v_t / (1 - b2^t)) + eps), evaluated in
+    FP64 from the FP32 gradients and weights; element-wise within half an FP32
+    ulp of the weight plus 1e-6 lr (the FP32 arithmetic of the update)."""
+    torch = torch_cuda
+    from paper_2105_09688_amd.ssm import mlp_init, mlp_loss_grad, mlp_train
+    p0 = mlp_init(D, seed=31)
+    p0 += np.random.default_rng(32).normal(size=p0.size).astype(np.float32) * 0.05
+    rng = np.random.default_rng(33)
+    U1 = rng.normal(size=(1, IN)).astype(np.float32)
+    T1 = rng.normal(size=(1, D)).astype(np.float32) * 0.3
+    U64, T64 = np.repeat(U1, 64, axis=0), np.repeat(T1, 64, axis=0)
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+
+    def dev(a):
+        return torch.tensor(np.asarray(a, dtype=np.float32), device="cuda")
+
+    def grad(wt):
+        return mlp_loss_grad(D, dev(wt), dev(U64), dev(T64))[1].cpu().numpy().astype(np.float64)
+
+    w1 = dev(p0)
+    mlp_train(D, w1, dev(U1), dev(T1), steps=1, batch=64, lr=lr, seed=1)
+    w1 = w1.cpu().numpy().astype(np.float64)
+    g1 = grad(p0)
+    m1, v1 = (1 - b1) * g1, (1 - b2) * g1 * g1
+    w1_ref = p0.astype(np.float64) - lr * (m1 / (1 - b1)) / (np.sqrt(v1 / (1 - b2)) + eps)
+    err1 = float(np.max(np.abs(w1 - w1_ref))) / lr
+    w2 = dev(p0)
+    mlp_train(D, w2, dev(U1), dev(T1), steps=2, batch=64, lr=lr, seed=2)
+    w2 = w2.cpu().numpy().astype(np.float64)
+    g2 = grad(w1)  # step 2 starts from step 1's weights (the same kernels, deterministic)
+    m2, v2 = b1 * m1 + (1 - b1) * g2, b2 * v1 + (1 - b2) * g2 * g2
+    w2_ref = w1 - lr * (m2 / (1 - b1 ** 2)) / (np.sqrt(v2 / (1 - b2 ** 2)) + eps)
+    err2 = float(np.max(np.abs(w2 - w2_ref))) / lr
+    _say(f"adam: step 1 max |w - w_ref| / lr = {err1:.2e}, step 2 {err2:.2e}; "
+         f"mean |update| / lr {np.mean(np.abs(w1 - p0)) / lr:.3f}, {np.mean(np.abs(w2 - w1)) / lr:.3f}")
+    # the FP32 weight itself rounds to half an ulp (2^-24 relative), the update's own arithmetic adds 1e-6 lr
+    assert np.all(np.abs(w1 - w1_ref) <= 2.0 ** -24 * np.abs(w1_ref) + 1e-6 * lr)
+    assert np.all(np.abs(w2 - w2_ref) <= 2.0 ** -24 * np.abs(w2_ref) + 1e-6 * lr)
+    assert np.mean(np.abs(w2 - w1)) > 0.1 * lr  # the second step moved the weights
+
+
 def test_mfma_gradient_matches_oracle(torch_cuda):
     """GPU BF16/FP32 gradient vs the oracle's FP64 back-propagation at the same
     parameters (BF16 weight matrices, float32 biases) and BF16-rounded inputs:
@@ -289,11 +426,12 @@ def test_surrogate_residual_mode_zero_network_matches_oracle(torch_cuda):
     assert np.max(np.abs(X - X_ex)) > 1e-6
 
 
-def test_surrogate_run_rmse_within_5_percent_of_oracle(torch_cuda):
-    """Strong error at h = 2^-9 against a 2^-13 proxy solution on the same
-    paths (Section 3): the surrogate run (residual mode, checks every 16
-    steps, tolerance 1e-2; most ticks must use the network) is within 5 % of
-    the oracle's exact run."""
+@pytest.fixture(scope="module")
+def rmse_case(torch_cuda):
+    """The reduced surrogate case for the strong-error comparisons: d = 2,
+    N = 1024, h = 2^-9, T = 1/4; the oracle's exact run and its 2^-13 proxy
+    on the same paths (Section 3's strong error), and a network trained on
+    exact runs of ensembles 1 and 2 at N = 4096."""
     torch = torch_cuda
     from paper_2105_09688_amd.ssm import SSM, mlp_init, mlp_train
     h, hf = 2.0 ** -9, 2.0 ** -13
@@ -303,7 +441,6 @@ def test_surrogate_run_rmse_within_5_percent_of_oracle(torch_cuda):
     _say("oracle exact run and 2^-13 proxy")
     o = oracle.run(w)[0]
     o_ref = oracle.run(ref_w)[0]
-    r_oracle = oracle.strong_error(o, o_ref)
     Us, Ts = [], []
     for e in (1, 2):
         with SSM(W.with_systems(w, [(4096, e, h)]), precision="fp32_kahan") as s:
@@ -315,18 +452,139 @@ def test_surrogate_run_rmse_within_5_percent_of_oracle(torch_cuda):
     p = torch.tensor(mlp_init(D, seed=0), device="cuda")
     mlp_train(D, p, torch.cat(Us), torch.cat(Ts), steps=6000, batch=2048, lr=1e-3, seed=1)
     mlp_train(D, p, torch.cat(Us), torch.cat(Ts), steps=3000, batch=2048, lr=2e-4, seed=2)
+    return w, o, o_ref, p.cpu().numpy()
+
+
+def test_surrogate_run_rmse_within_5_percent_of_oracle(rmse_case):
+    """Strong error at h = 2^-9 against a 2^-13 proxy solution on the same
+    paths (Section 3), N = 1024, T = 1/4: the surrogate run (residual mode,
+    checks every 16 steps, tolerance 1e-2; most ticks on the network) is
+    within 5 % of the oracle's exact run.  (At this N the finite-N part of the
+    pair term moves by about 5e-3 between checks, so the 1e-3 tolerance of the
+    surrogate case falls back on every interval; that tolerance is tested at
+    N = 8192 below.)"""
+    from paper_2105_09688_amd.ssm import SSM
+    w, o, o_ref, master = rmse_case
+    r_oracle = oracle.strong_error(o, o_ref)
     with SSM(w, precision="fp32_kahan") as s:
-        s.surrogate_load(p.cpu().numpy())
+        s.surrogate_load(master)
         s.surrogate_enable(check_every=16, tol=1e-2, mode="residual")
         s.run()
         info = s.info()
         X = s.state(0)
     r_gpu = errstats.strong_error(X, o_ref)
-    _say(f"rmse oracle exact {r_oracle:.4e}, gpu surrogate {r_gpu:.4e}; surrogate ticks {info['surr_ticks']}, "
-         f"fallback ticks {info['surr_fallback_ticks']}, last / max check err {info['surr_last_err']:.3e} / "
-         f"{info['surr_max_err']:.3e}")
+    _say(f"rmse oracle exact {r_oracle:.4e}, gpu surrogate {r_gpu:.4e} (ratio {r_gpu / r_oracle:.4f}); "
+         f"surrogate ticks {info['surr_ticks']}, fallback ticks {info['surr_fallback_ticks']}, last / max check err "
+         f"{info['surr_last_err']:.3e} / {info['surr_max_err']:.3e}")
     assert info["surr_ticks"] >= 60  # of 120 non-check ticks
     assert abs(r_gpu - r_oracle) <= 0.05 * r_oracle
+
+
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fixed_rmse.json")) as fh:
+        return json.load(fh)[name]
+
+
+@pytest.fixture(scope="module")
+def fixed_rmse_case(torch_cuda):
+    """The surrogate case's coefficients at N = 8192, T = 1, h = 2^-9 (512
+    steps, 32 checks), with the oracle's strong error against a 2^-13 proxy
+    stored in tests/golden/fixed_rmse.json (written by the oracle alone).  The
+    GPU side takes its proxy from the FP64 path at 2^-13 on the same paths;
+    that the GPU FP64 path reproduces the oracle's strong error (to 1e-6
+    relative, both runs and the proxy being pathwise within about 1e-10 of
+    the oracle's) pins the chain.  The network is trained on exact runs of
+    ensembles 1 and 2 at N = 2^14 (32 states each)."""
+    torch = torch_cuda
+    from paper_2105_09688_amd.ssm import SSM, mlp_init, mlp_train
+    g = _golden("surrogate_reduced")
+    h, hf, N = g["h"], g["proxy_h"], g["N"]
+    w = W.surrogate_d2(N=N, h=h, h_fine=hf)
+    assert w["T"] == g["T"]
+    with SSM(W.with_h(w, hf), precision="fp64") as r:
+        r.run()
+        X_ref = r.state(0)
+    with SSM(w, precision="fp64") as e64:
+        e64.run()
+        r64 = errstats.strong_error(e64.state(0), X_ref)
+    with SSM(w, precision="fp32_kahan") as ex:
+        ex.run()
+        X_ex = ex.state(0)
+    _say(f"N={N}: oracle strong error {g['rmse']:.6e}, GPU FP64 {r64:.6e}, GPU FP32-compensated "
+         f"{errstats.strong_error(X_ex, X_ref):.6e}")
+    assert abs(r64 - g["rmse"]) <= 1e-6 * g["rmse"]
+    Us, Ts = [], []
+    for e in (1, 2):
+        with SSM(W.with_systems(w, [(2 ** 14, e, h)]), precision="fp32_kahan") as s:
+            for t in range(0, 512, 16):
+                U, T = s.surrogate_samples(2 ** 16, seed=1000 * e + t)
+                Us.append(U)
+                Ts.append(T)
+                s.step(16)
+    U, T = torch.cat(Us), torch.cat(Ts)
+    p = torch.tensor(mlp_init(D, seed=0), device="cuda")
+    for steps, lr, seed in ((32000, 1e-3, 1), (16000, 2e-4, 2), (8000, 4e-5, 3)):
+        mlp_train(D, p, U, T, steps=steps, batch=4096, lr=lr, seed=seed)
+    return w, g["rmse"], X_ref, X_ex, p.cpu().numpy()
+
+
+def _surr_run(w, weights, tol, every=16):
+    from paper_2105_09688_amd.ssm import SSM
+    with SSM(w, precision="fp32_kahan") as s:
+        s.surrogate_load(weights)
+        s.surrogate_enable(check_every=every, tol=tol, mode="residual")
+        s.run()
+        return s.state(0), s.info()
+
+
+def test_surrogate_rmse_within_5_percent_of_oracle_at_tolerance_1e3(fixed_rmse_case):
+    """The surrogate case's check rule (exact check every 16 steps, fallback
+    above 1e-3 relative drift error), residual mode: the strong error at
+    h = 2^-9 is within 5 % of the oracle's exact run (Section 3's strong
+    error, the metric's "fixed rMSE"), with at least 200 of the 480 non-check
+    ticks on the network."""
+    w, r_oracle, X_ref, X_ex, master = fixed_rmse_case
+    X, info = _surr_run(w, master, 1e-3)
+    r_gpu = errstats.strong_error(X, X_ref)
+    _say(f"tol 1e-3 at N={w['systems'][0][0]}: rmse oracle {r_oracle:.5e}, surrogate {r_gpu:.5e} (ratio "
+         f"{r_gpu / r_oracle:.4f}); surrogate ticks {info['surr_ticks']}, fallback ticks "
+         f"{info['surr_fallback_ticks']}, check err last / max {info['surr_last_err']:.3e} / {info['surr_max_err']:.3e}, "
+         f"pathwise rms vs exact {_rms(X, X_ex):.3e}")
+    assert info["surr_ticks"] >= 200
+    assert abs(r_gpu - r_oracle) <= 0.05 * r_oracle
+
+
+def test_trained_network_gains_over_the_frozen_exact_term(fixed_rmse_case):
+    """What the trained network adds over the method without it.  In residual
+    mode an all-zero network leaves the exact pair term frozen at the last
+    check (the scheme without a network); the trained network adds its
+    prediction of the term's change since that check.  Same cadence (16) and
+    tolerance (1e-3): the trained network keeps at least 200 ticks on the
+    cheap path where the frozen term keeps at most a tenth of that; with every
+    check accepted (tolerance 1e9) its check errors are at least 5x smaller,
+    its path at least 5x closer to the exact run's, and its strong error
+    within 5 % of the oracle's where the frozen term's is not."""
+    from paper_2105_09688_amd.ssm import mlp_num_params
+    w, r_oracle, X_ref, X_ex, master = fixed_rmse_case
+    zeros = np.zeros(mlp_num_params(D), dtype=np.float32)
+    res = {}
+    for name, weights in (("trained", master), ("frozen", zeros)):
+        for tol in (1e-3, 1e9):
+            X, info = _surr_run(w, weights, tol)
+            r = errstats.strong_error(X, X_ref)
+            res[name, tol] = dict(ticks=info["surr_ticks"], last=info["surr_last_err"], max=info["surr_max_err"],
+                                  rms=_rms(X, X_ex), ratio=r / r_oracle)
+            _say(f"{name} tol {tol:g}: surrogate ticks {info['surr_ticks']}, check err last / max "
+                 f"{info['surr_last_err']:.3e} / {info['surr_max_err']:.3e}, pathwise rms vs exact "
+                 f"{res[name, tol]['rms']:.3e}, rmse ratio vs oracle {r / r_oracle:.4f}")
+    t, f = res["trained", 1e-3], res["frozen", 1e-3]
+    assert t["ticks"] >= 200 and f["ticks"] <= 0.1 * t["ticks"]
+    t, f = res["trained", 1e9], res["frozen", 1e9]
+    assert t["last"] <= 0.2 * f["last"]
+    assert t["rms"] <= 0.2 * f["rms"]
+    assert abs(t["ratio"] - 1.0) <= 0.05 < abs(f["ratio"] - 1.0)
 
 
 def test_trained_surrogate_gains_over_the_exact_method(torch_cuda):
