@@ -532,10 +532,203 @@ def study_surrogate(args, stream):
             "surrogate": runs}
 
 
+def golden_fixed_rmse(name: str) -> dict:
+    """The oracle's strong errors of the reduced workloads, stored by
+    tests/golden/make_fixed_rmse.py (which calls the oracle only)."""
+    with open(os.path.join(ROOT, "tests", "golden", "fixed_rmse.json")) as fh:
+        return json.load(fh)[name]
+
+
+def settle_clocks(SSM, w, precision, stream, seconds: float) -> dict:
+    """Untimed pair-kernel work until `seconds` of wall time have passed.  The
+    kernel's duration falls by about 10 % over the first tens of milliseconds
+    of sustained load (clock ramp: 401 -> 380 us over the first 20 launches
+    at d = 1, N = 2^16, about 357 us from a few hundred on), so the timed
+    steps start at steady clocks."""
+    t0 = time.perf_counter()
+    ticks = 0
+    while time.perf_counter() - t0 < seconds:
+        with SSM(w, precision=precision, stream=stream) as s:
+            total = s.info()["ticks_total"]
+            while time.perf_counter() - t0 < seconds and s.info()["tick"] < total:
+                n = min(64, total - s.info()["tick"])
+                s.step(n)
+                s.sync()
+                ticks += n
+    return {"seconds": time.perf_counter() - t0, "ticks": ticks}
+
+
+def _events(stream):
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _timed_steps(s, n, stream):
+    """GPU time (s) of n ticks of context s, between HIP events on its stream."""
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = _events(stream)
+    e0.record(stream)
+    s.step(n)
+    e1.record(stream)
+    s.sync()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def leg_surrogate(args, stream) -> dict:
+    """The metric's surrogate leg on the surrogate case (d = 2, N = 2^20,
+    h = 2^-9, T = 1, FP32-compensated): a network trained on exact runs of
+    ensembles 1-2 at N = 2^18 (2^22 rows, Adam); the exact O(N^2) tick timed
+    on 16 ticks; the whole surrogate run (residual mode, exact check every 16
+    steps, fallback above 1e-3 relative drift error) timed from X_0 to T; and
+    the fixed-rMSE check at N = 8192 (same network, same rule) against the
+    oracle's strong error stored in tests/golden/fixed_rmse.json, with the
+    GPU's FP64 2^-13 run on the same paths as the proxy."""
+    import numpy as np
+    import torch
+    from paper_2105_09688_amd import workloads as W
+    from paper_2105_09688_amd.ssm import SSM, mlp_init, mlp_train
+    prec = "fp32_kahan"
+    w = W.surrogate_d2(N=2 ** 20)
+    N, _, h = w["systems"][0]
+    d = w["d"]
+    every, tol = 16, 1e-3
+    t0 = time.perf_counter()
+    Us, Ts = [], []
+    for e in (1, 2):
+        with SSM(W.with_systems(w, [(2 ** 18, e, h)]), precision=prec, stream=stream) as s:
+            for t in range(0, s.info()["ticks_total"], every):
+                U, T = s.surrogate_samples(2 ** 16, seed=1000 * e + t)
+                Us.append(U)
+                Ts.append(T)
+                s.step(every)
+    U, T = torch.cat(Us), torch.cat(Ts)
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    p = torch.tensor(mlp_init(d, seed=0), device="cuda")
+    hist = []
+    for steps, lr, seed in ((args.train_steps, 1e-3, 1), (args.train_steps // 2, 2e-4, 2), (args.train_steps // 4, 4e-5, 3)):
+        hist.append(mlp_train(d, p, U, T, steps=steps, batch=4096, lr=lr, seed=seed))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    hist = np.concatenate(hist)
+    master = p.cpu().numpy()
+    del U, T, Us, Ts
+    print(f"[leg surrogate] {2 ** 22} rows in {t_data:.1f} s, {hist.size} Adam steps in {t_train:.1f} s", file=sys.stderr,
+          flush=True)
+    # exact ticks at full size
+    with SSM(w, precision=prec, stream=stream) as ex:
+        ex.step(1)
+        ex.sync()
+        n_ex = 16
+        dt_ex = _timed_steps(ex, n_ex, stream)
+    ms_exact = dt_ex / n_ex * 1e3
+    # the whole surrogate run
+    with SSM(w, precision=prec, stream=stream) as su:
+        su.surrogate_load(master)
+        su.surrogate_enable(check_every=every, tol=tol, mode="residual")
+        total = su.info()["ticks_total"]
+        dt_su = _timed_steps(su, total, stream)
+        info = su.info()
+    print(f"[leg surrogate] exact {ms_exact:.1f} ms per step, surrogate run {dt_su:.2f} s "
+          f"({info['surr_ticks']} network ticks)", file=sys.stderr, flush=True)
+    # fixed rMSE at the reduced size
+    g = golden_fixed_rmse("surrogate_reduced")
+    wr = W.surrogate_d2(N=g["N"], h=g["h"], h_fine=g["proxy_h"])
+    with SSM(W.with_h(wr, g["proxy_h"]), precision="fp64", stream=stream) as r:
+        r.run()
+        X_ref = r.state(0)
+    with SSM(wr, precision=prec, stream=stream) as a:
+        a.surrogate_load(master)
+        a.surrogate_enable(check_every=every, tol=tol, mode="residual")
+        a.run()
+        ia = a.info()
+        Xa = a.state(0)
+    with SSM(wr, precision=prec, stream=stream) as b:
+        b.run()
+        Xb = b.state(0)
+    rm = lambda X: math.sqrt(float(np.sum((X - X_ref) ** 2)) / g["N"])
+    r_s, r_e = rm(Xa), rm(Xb)
+    return {
+        "workload": f"SSM d=2 N={N} T=1 h=2^-9 Gaussian interaction (l=1), radial cubic v, diagonal sigma; {prec}",
+        "training": {"rows": 2 ** 22, "from": "exact runs of ensembles 1-2 at N=2^18, 32 states each",
+                     "rows_seconds": t_data, "adam_steps": int(hist.size), "batch": 4096, "adam_seconds": t_train,
+                     "loss_first": float(hist[:50].mean()), "loss_last": float(hist[-200:].mean())},
+        "exact": {"ms_per_step": ms_exact, "particle_steps_per_s": N / (ms_exact / 1e3), "timed_steps": n_ex},
+        "surrogate": {"rule": f"residual mode, exact check every {every} steps, fallback above {tol:g}",
+                      "seconds": dt_su, "steps": total, "particle_steps_per_s": N * total / dt_su,
+                      "checks": info["surr_checks"], "network_steps": info["surr_ticks"],
+                      "fallback_steps": info["surr_fallback_ticks"], "check_err_last": info["surr_last_err"],
+                      "check_err_max": info["surr_max_err"]},
+        "speedup_vs_exact": (ms_exact / 1e3 * total) / dt_su,
+        "fixed_rmse": {"workload": g["workload"] + f", proxy h={g['proxy_h']:g} (GPU FP64 run)",
+                       "rmse_oracle_exact": g["rmse"], "rmse_gpu_surrogate": r_s, "rmse_gpu_exact_fp32": r_e,
+                       "ratio_surrogate_to_oracle": r_s / g["rmse"],
+                       "within_5_percent": abs(r_s - g["rmse"]) <= 0.05 * g["rmse"],
+                       "network_steps": ia["surr_ticks"], "checks": ia["surr_checks"]},
+    }
+
+
+def leg_batched(args, stream) -> dict:
+    """The metric's batched leg on the batched case (64 ensembles, N_e
+    log-uniform in [2^10, 2^16], h = 2^-4..2^-8 in one context on a 2^-12
+    grid, T = 1, FP32-compensated): whole-run throughput with the library's
+    default tiling and with the autotuner's choice for this workload, and the
+    fixed-rMSE check per step size on a reduced batch (8 ensembles, N_e in
+    [2^8, 2^11]) against the oracle's strong errors stored in
+    tests/golden/fixed_rmse.json, with the GPU's FP64 2^-12 run as the proxy."""
+    import numpy as np
+    from paper_2105_09688_amd import workloads as W
+    from paper_2105_09688_amd.ssm import SSM
+    from paper_2105_09688_amd.tune import autotune
+    prec = "fp32_kahan"
+    w = W.batched(levels=(4, 5, 6, 7, 8))
+    out = {"workload": "64 ensembles, N_e log-uniform in [2^10, 2^16], h=2^-4..2^-8 on a 2^-12 grid, T=1, " + prec}
+    runs = {}
+    t0 = time.perf_counter()
+    tuned = autotune(w, prec, stream=stream, use_cache=False)
+    t_tune = time.perf_counter() - t0
+    for label, kw in (("default", {}), ("autotuned", {k: tuned[k] for k in
+                                                     ("targets_per_lane", "sources_per_item", "pair_scheme")})):
+        with SSM(w, precision=prec, stream=stream, **kw) as s:
+            i = s.info()
+            total = i["ticks_total"]
+            dt = _timed_steps(s, total, stream)
+        runs[label] = {"seconds": dt, "particle_steps_per_s": particle_steps(w, total) / dt,
+                       "targets_per_lane": i["targets_per_lane"], "sources_per_item": i["sources_per_item"],
+                       "pair_scheme": i["pair_scheme"], "pair_work_items_phase0": i["n_pair_items"]}
+    out.update(runs=runs, autotune_seconds=t_tune, particle_steps=particle_steps(w, total))
+    best = max(runs, key=lambda k: runs[k]["particle_steps_per_s"])
+    out["particle_steps_per_s"] = runs[best]["particle_steps_per_s"]
+    out["tiling_used"] = best
+    g = golden_fixed_rmse("batched_reduced")
+    levels = tuple(g["levels"])
+    wr = W.batched(n_ens=len(g["sizes"]), levels=levels, h_fine=g["proxy_h"], sizes=g["sizes"])
+    ref_w = W.with_systems(wr, [(N, e, g["proxy_h"]) for e, N in enumerate(g["sizes"])])
+    with SSM(wr, precision=prec, stream=stream) as a, SSM(ref_w, precision="fp64", stream=stream) as r:
+        a.run()
+        r.run()
+        per = {}
+        for li, l in enumerate(levels):
+            sq, cnt = 0.0, 0
+            for e, N in enumerate(g["sizes"]):
+                sq += a.sqdiff(e * len(levels) + li, r, e)
+                cnt += N
+            per[f"2^-{l}"] = math.sqrt(sq / cnt)
+    ratios = {k: per[k] / g["rmse"][k] for k in per}
+    out["fixed_rmse"] = {"workload": g["workload"] + f", proxy h={g['proxy_h']:g} (GPU FP64 run)",
+                         "rmse_oracle": g["rmse"], "rmse_gpu": per, "ratio": ratios,
+                         "within_5_percent": all(abs(r - 1.0) <= 0.05 for r in ratios.values())}
+    print(f"[leg batched] {out['particle_steps_per_s']:.3e} particle-steps/s ({best}), autotune {t_tune:.1f} s",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1024)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--precision", default="fp32_kahan", choices=["fp64", "fp32", "fp32_kahan"])
     ap.add_argument("--N", type=int, default=0)
@@ -544,6 +737,11 @@ def main():
                                         "stability"],
                     default="none",
                     help="run a study of another workload instead of the throughput line")
+    ap.add_argument("--legs", default="surrogate,batched",
+                    help="the metric's other legs to add to the line: comma-separated subset of "
+                         "'surrogate,batched', or 'none'")
+    ap.add_argument("--settle-s", type=float, default=1.0,
+                    help="seconds of untimed pair-kernel work before the timed context (steady clocks)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -576,8 +774,13 @@ def main():
     N, _, h = w["systems"][0]
     d = w["d"]
     total_steps = int(round(w["T"] / h))
-    if not (1 <= args.steps <= total_steps):
-        raise SystemExit(f"--steps must be in 1..{total_steps} (T/h)")
+    if args.steps < 1 or args.warmup < 0 or args.warmup + args.steps > total_steps:
+        raise SystemExit(f"--warmup + --steps must be at most {total_steps} (T/h) and --steps >= 1: the timed "
+                         f"steps run in the same context after the warm-up steps")
+    legs = [] if args.legs == "none" else [x for x in args.legs.split(",") if x]
+    for x in legs:
+        if x not in ("surrogate", "batched"):
+            raise SystemExit(f"unknown leg {x!r}")
 
     stream = torch.cuda.Stream()
     tiling = {}
@@ -585,17 +788,18 @@ def main():
         from paper_2105_09688_amd.tune import autotune
         t = autotune(w, args.precision, stream=stream)
         tiling = {k: t[k] for k in ("targets_per_lane", "sources_per_item", "pair_scheme")}
-    # warm-up (separate context: the timed one starts at t = 0)
-    with SSM(w, precision=args.precision, stream=stream, **tiling) as s:
-        s.step(min(args.warmup, total_steps))
-        s.sync()
+    settle = settle_clocks(SSM, w, args.precision, stream, args.settle_s)
+    # the timed context: warm-up steps, then the timed steps
     s = SSM(w, precision=args.precision, stream=stream, **tiling)
+    if args.warmup:
+        s.step(args.warmup)
     s.sync()
-    # HIP events around the pair and update launches of every PROFILE_EVERY-th
-    # tick of the timed run (an event pair on every tick costs ~4 % of the step)
-    s.profile(True, every=PROFILE_EVERY)
+    # HIP events around the pair and update launches of every k-th tick of the
+    # timed steps (an event pair costs a few microseconds of stream time per tick)
+    every = 8 if args.steps >= 256 else 4 if args.steps >= 64 else 2 if args.steps >= 8 else 1
+    s.profile(True, every=every)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0, ev1 = _events(stream)
     ev0.record(stream)
     t0 = time.perf_counter()
     s.step(args.steps)
@@ -630,6 +834,10 @@ def main():
                                f"affine sigma; {args.precision}",
                    "d": d, "N": N, "h": h, "T": w["T"], "precision": args.precision},
         "wall_s": wall,
+        "clock_settle": {"seconds": settle["seconds"], "untimed_steps": settle["ticks"],
+                         "note": "untimed steps of other contexts of the same workload before the timed "
+                                 "context, so that the timed steps run at steady clocks; the timed context "
+                                 "then takes its --warmup steps and the --steps timed ones"},
         "roofline": {
             "bound": "alu",
             "kernel": "k_pair (O(N^2) interaction sums)",
@@ -645,7 +853,7 @@ def main():
             "pairs_per_launch": pairs,
             "avg_launch_ms": pair_avg_s * 1e3,
             "launches": info["pair_launches"],
-            "launches_timed_every": PROFILE_EVERY,
+            "launches_timed_every": every,
         },
         "update_kernel_avg_ms": info["update_ms"] / max(1, info["update_launches"]),
         "tiling": {"targets_per_lane": info["targets_per_lane"], "sources_per_item": info["sources_per_item"],
@@ -654,12 +862,13 @@ def main():
     }
     if not args.no_check and args.precision != "fp64":
         # pathwise agreement of the timed run with the FP64 path after the same steps
+        n_chk = args.warmup + args.steps
         with SSM(w, precision="fp64", stream=stream) as ref:
-            ref.step(args.steps)
+            ref.step(n_chk)
             ref.sync()
             a, b = s.state(0), ref.state(0)
         out["check"] = {"max_pathwise_err_vs_fp64": float(np.max(np.abs(a - b) / np.maximum(1.0, np.abs(b)))),
-                        "steps": args.steps}
+                        "steps": n_chk}
     s.close()
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -669,6 +878,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = {"read": 4 * n, "write": 4 * n}
+    if legs:
+        out["legs"] = {}
+        if "surrogate" in legs:
+            out["legs"]["surrogate"] = leg_surrogate(args, stream)
+        if "batched" in legs:
+            out["legs"]["batched"] = leg_batched(args, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)
