@@ -402,6 +402,20 @@ ssm_status ssm_surrogate_samples(ssm_ctx *ctx, int32_t sys, int64_t n, uint64_t 
 ssm_status ssm_mlp_forward(int32_t d, const float *master, const float *U, int64_t n, float *out,
                            void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ssm_mlp_forward without any allocation.  The packed weights go to a device
+ * buffer of the library (one per GPU, about 85 KB, held until the process
+ * ends) in place of memory allocated for the call.  Same arguments and
+ * results as ssm_mlp_forward (bitwise); d in 1..4 (the buffer holds a network
+ * for d <= 4) and n in 1..2^31, else SSM_ERR_INVALID.  Asynchronous on stream:
+ * it does not synchronize, so out is ready once the stream has reached the
+ * call.  Every call on one GPU shares that GPU's buffer and it keeps the last
+ * call's weights: calls whose kernels overlap on one GPU (other streams,
+ * other threads) race; calls in order on one stream do not. */
+ssm_status ssm_mlp_forward_noalloc(int32_t d, const float *master, const float *U, int64_t n, float *out,
+                                   void *stream);
+
 /* Loss L = (1/n) sum_rows |net(U_r) - T_r|^2 and dL/dparams (device float,
  * flat layout) for the n rows in order (n a multiple of 64), computed with
  * the training kernels.  *loss (host, may be NULL).  Synchronizes stream. */

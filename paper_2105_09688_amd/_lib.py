@@ -19,7 +19,7 @@ EXPORTS = (
     "ssm_set_state", "ssm_state_layout", "ssm_bind_state", "ssm_state_refresh", "ssm_rmse", "ssm_sqdiff", "ssm_info", "ssm_profile", "ssm_destroy", "ssm_last_error",
     "ssm_pair_sum", "ssm_pair_workspace_bytes", "ssm_implicit_solve", "ssm_brownian",
     "ssm_philox_blocks", "ssm_mlp_num_params", "ssm_surrogate_load", "ssm_surrogate_enable",
-    "ssm_surrogate_samples", "ssm_surrogate_predict", "ssm_mlp_forward", "ssm_mlp_loss_grad", "ssm_mlp_train", "ssm_surrogate_train",
+    "ssm_surrogate_samples", "ssm_surrogate_predict", "ssm_mlp_forward", "ssm_mlp_forward_noalloc", "ssm_mlp_loss_grad", "ssm_mlp_train", "ssm_surrogate_train",
 )
 
 
@@ -113,6 +113,7 @@ def load():
         "ssm_surrogate_samples": (st, [vp, i32, i64, u64, vp, vp]),
         "ssm_surrogate_predict": (st, [vp, i32, dp, vp]),
         "ssm_mlp_forward": (st, [i32, vp, vp, i64, vp, vp]),
+        "ssm_mlp_forward_noalloc": (st, [i32, vp, vp, i64, vp, vp]),
         "ssm_mlp_loss_grad": (st, [i32, vp, vp, vp, i64, vp, dp, vp]),
         "ssm_mlp_train": (st, [i32, vp, vp, i64, C.POINTER(TrainCfg), vp, vp, vp]),
         "ssm_surrogate_train": (st, [vp, C.POINTER(SurrTrainCfg), vp, vp, vp]),

@@ -9,6 +9,7 @@
 #include <new>
 #include <string>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/ssm.h"
@@ -1797,6 +1798,56 @@ extern "C" ssm_status ssm_mlp_forward(int32_t d, const float* master, const floa
     }
     (void)hipFree(W);
     return s;
+}
+
+// ---------------------------------------------------------------------------
+// Network output without allocation: the packed weights go to a file-scope
+// device buffer (one per GPU, held until the process ends) instead of a
+// hipMalloc'd one.  Host code never passes `scratch` itself (in host code it
+// names a host-side stand-in, not the device copy): the device address comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) MlpPacked scratch;
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static ssm_status scratch_for_current_device(MlpPacked** out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SSM_ERR_INVALID, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SSM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (MlpPacked*)g_scratch_ptr[dev];
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_mlp_forward_noalloc(int32_t d, const float* master, const float* U, int64_t n, float* out,
+                                              void* stream)
+{
+    if (d < 1 || d > SSM_MAX_D)
+        return fail(SSM_ERR_INVALID, "d must be in 1..4 (the static weight buffer holds a network for d <= 4)");
+    if (n < 1 || n > ((int64_t)1 << 31))
+        return fail(SSM_ERR_INVALID, "n must be in 1..2^31 rows");
+    if (!master || !U || !out) return fail(SSM_ERR_INVALID, "NULL pointer");
+    MlpPacked* W = nullptr;
+    ssm_status s = scratch_for_current_device(&W);
+    if (s != SSM_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    s = pack_weights(master, d, W, st);
+    if (s != SSM_OK) return s;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 127) / 128, 4096);
+    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_mlp_apply<D>), dim3(grid), dim3(256), 0, st, U, n, W, out));
+    HIP_TRY(hipGetLastError());
+    return SSM_OK;
 }
 
 struct TrainWork {

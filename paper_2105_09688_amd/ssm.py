@@ -334,6 +334,15 @@ def mlp_forward(d: int, master, U):
     return out
 
 
+def mlp_forward_noalloc(d: int, master, U, out):
+    """mlp_forward into a caller-allocated float32 device tensor out [n][d], with
+    no allocation in the library (ssm_mlp_forward_noalloc); asynchronous on the
+    current stream."""
+    check(_lib.load().ssm_mlp_forward_noalloc(d, master.data_ptr(), U.data_ptr(), U.shape[0], out.data_ptr(),
+                                              _cur_stream()))
+    return out
+
+
 def mlp_loss_grad(d: int, master, U, T):
     """(loss, grad) for the rows of U, T in order (row count a multiple of 64)."""
     torch = _torch()
