@@ -85,6 +85,10 @@ typedef enum {
  * the sum of its r = h / h_fine fine increments:
  *   dW_{n,k}^i = sqrt(h_fine) sum_{m < r} (stream normal (n r + m) d + k).
  * X_0^i = x0_mean + x0_std * Z(1, i, 0, ens) (component k uses normal k).
+ * The FP64 mode transforms the words in double precision; the FP32 modes take
+ * the same u rounded once to float and the hardware log2, square root, sine
+ * and cosine (normals within about 1e-6 of the double-precision ones, the
+ * precision of their FP32 state); increments are summed in double.
  *
  * Time: every h[s] must divide T and be an integer multiple of h_fine.  Let
  * h_min = min h[s]; a "tick" advances time by h_min, and system s takes a step

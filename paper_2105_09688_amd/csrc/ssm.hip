@@ -559,8 +559,8 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
         // the path groups' Brownian windows for ticks tick .. tick + max_stride - 1
         const dim3 gw((unsigned)(c->win_items * c->win_lanes), (unsigned)c->max_stride);
 #define SSM_WIN(LPV)                                                                                                   \
-    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_bm_window<D, LPV>), gw, dim3(kBlk), 0, c->stream, c->dwin_items, c->dsys, \
-                                         c->coef, c->r_min, c->tick, tdev, c->win))
+    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_bm_window<D, LPV, (sizeof(T) == 4)>), gw, dim3(kBlk), 0, c->stream,      \
+                                         c->dwin_items, c->dsys, c->coef, c->r_min, c->tick, tdev, c->win))
         switch (c->win_lanes) {
             case 16: SSM_WIN(16); break;
             case 8: SSM_WIN(8); break;
@@ -615,7 +615,8 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
                                              items, c->dsys, c->coef, c->P, (const T*)c->Bp, (const T*)c->Bpj,        \
                                              c->pairsum, c->tick, tdev, (const double*)c->win, c->dW, job));          \
     } else {                                                                                                          \
-        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_brownian_sum<D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, n_main,   \
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_brownian_sum<D, LPV, (sizeof(T) == 4)>), dim3(gb), dim3(kBlk), 0,    \
+                                             c->stream, n_main,                                                       \
                                              items, c->dsys, c->coef, c->P, c->tick, tdev, (const double*)c->win,     \
                                              c->dW, job));                                                            \
     }

@@ -578,13 +578,21 @@ __global__ __launch_bounds__(kBlk) void k_update(const BlkItem* __restrict__ ite
 // stream_sum adds the normals of [q0, q1) that fall in the blocks
 // b = b_first, b_first + stride, ... (a lane's share), per component.
 // ---------------------------------------------------------------------------
-template <int D>
+// F32: the FP32 transform (the FP32 precision modes); the sums stay in double.
+template <int D, bool F32 = false>
 __device__ __forceinline__ void stream_sum(uint64_t seed, uint64_t i, uint64_t e, uint64_t q0, uint64_t q1,
                                            uint64_t b_first, uint64_t stride, double zs[kMaxD])
 {
     for (uint64_t b = b_first; b * 4 < q1; b += stride) {
         double z[kMaxD];
-        normals(seed, 0u, i, b, e, 4, z);
+        if constexpr (F32) {
+            float zf[4];
+            normals4_f32(seed, 0u, i, b, e, zf);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) z[s] = (double)zf[s];
+        } else {
+            normals(seed, 0u, i, b, e, 4, z);
+        }
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const uint64_t q = 4 * b + s;
@@ -620,7 +628,7 @@ __device__ __forceinline__ void lane_butterfly(double (&zs)[kMaxD])
         for (int k = 0; k < D; ++k) zs[k] += __shfl_xor(zs[k], w, 64);
 }
 
-template <int D, int LP>
+template <int D, int LP, bool F32>
 __device__ __forceinline__ void brownian_block(int vb, const BlkItem* __restrict__ items,
                                                const SysDev* __restrict__ sys, const Coef& cf, int64_t P,
                                                int64_t tick_arg, const int64_t* __restrict__ tick_dev,
@@ -644,7 +652,7 @@ __device__ __forceinline__ void brownian_block(int vb, const BlkItem* __restrict
         } else {
             const uint64_t q0 = (uint64_t)n * (uint64_t)S.r * D;
             const uint64_t q1 = q0 + (uint64_t)S.r * D;
-            stream_sum<D>(cf.seed, (uint64_t)i, (uint64_t)S.ens, q0, q1, q0 / 4 + q, LP, zs);
+            stream_sum<D, F32>(cf.seed, (uint64_t)i, (uint64_t)S.ens, q0, q1, q0 / 4 + q, LP, zs);
         }
     }
     lane_butterfly<LP, D>(zs);
@@ -682,7 +690,7 @@ __device__ __forceinline__ void ymean_block(int q, const YMeanJob& job, const Sy
 }
 
 // n_main blocks of Brownian sums, then job.n blocks of system means.
-template <int D, int LP>
+template <int D, int LP, bool F32>
 __global__ __launch_bounds__(kBlk) void k_brownian_sum(int n_main, const BlkItem* __restrict__ items,
                                                        const SysDev* __restrict__ sys, Coef cf,
                                                        int64_t P, int64_t tick_arg,
@@ -691,7 +699,7 @@ __global__ __launch_bounds__(kBlk) void k_brownian_sum(int n_main, const BlkItem
                                                        YMeanJob job)
 {
     if ((int)blockIdx.x < n_main)
-        brownian_block<D, LP>(blockIdx.x, items, sys, cf, P, tick_arg, tick_dev, win, dW);
+        brownian_block<D, LP, F32>(blockIdx.x, items, sys, cf, P, tick_arg, tick_dev, win, dW);
     else
         ymean_block<D>(blockIdx.x - n_main, job, sys, tick_arg, tick_dev);
 }
@@ -702,7 +710,7 @@ __global__ __launch_bounds__(kBlk) void k_brownian_sum(int n_main, const BlkItem
 // stream normals [((t0 + p) r_min + m) d + k, m < r_min] with r_min fine
 // steps per tick.  Items are the blocks of one member system per group;
 // blockIdx.y = p; LP lanes per particle as in k_brownian_sum.
-template <int D, int LP>
+template <int D, int LP, bool F32>
 __global__ __launch_bounds__(kBlk) void k_bm_window(const BlkItem* __restrict__ items,
                                                     const SysDev* __restrict__ sys, Coef cf, int64_t r_min,
                                                     int64_t tick_arg, const int64_t* __restrict__ tick_dev,
@@ -719,7 +727,7 @@ __global__ __launch_bounds__(kBlk) void k_bm_window(const BlkItem* __restrict__ 
     if (i < S.N) {
         const uint64_t q0 = (uint64_t)t * (uint64_t)r_min * D;
         const uint64_t q1 = q0 + (uint64_t)r_min * D;
-        stream_sum<D>(cf.seed, (uint64_t)i, (uint64_t)S.ens, q0, q1, q0 / 4 + q, LP, zs);
+        stream_sum<D, F32>(cf.seed, (uint64_t)i, (uint64_t)S.ens, q0, q1, q0 / 4 + q, LP, zs);
     }
     lane_butterfly<LP, D>(zs);
     if (q == 0 && i < S.N) {
@@ -745,7 +753,7 @@ __global__ __launch_bounds__(kBlk) void k_prep(int n_combine, int n_main, const 
     if ((int)blockIdx.x < n_combine)
         combine_block<PT, D>(blockIdx.x, items, sys, P, Bp, Bpj, pairsum, part);
     else if ((int)blockIdx.x < n_main)
-        brownian_block<D, LP>(blockIdx.x - n_combine, items, sys, cf, P, tick_arg, tick_dev, win, dW);
+        brownian_block<D, LP, (sizeof(PT) == 4)>(blockIdx.x - n_combine, items, sys, cf, P, tick_arg, tick_dev, win, dW);
     else
         ymean_block<D>(blockIdx.x - n_main, job, sys, tick_arg, tick_dev);
 }

@@ -70,6 +70,31 @@ def test_brownian_increments_match_oracle(torch_cuda, d, r):
     assert err <= 8 * 2.0 ** -52 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("d,r,prec", [(1, 16, "fp32_kahan"), (2, 16, "fp32"), (3, 4, "fp32_kahan"), (2, 16, "fp64")])
+def test_context_increments_match_oracle(torch_cuda, d, r, prec):
+    """The increments a context draws, seen through a pure Brownian motion
+    (v = 0, b = 0, sigma = 1, X_0 = 0, so X_n = dW_0 + ... + dW_{n-1}), after
+    5 steps of r fine increments, against the oracle's increments.  FP32
+    modes draw their normals with the FP32 transform: within 1e-6 of the
+    largest |X| (the transform's own error plus five roundings of the FP32
+    state; measured at most 2.3e-7 of it); FP64 within 8 ulps."""
+    N, hf = 2500, 2.0 ** -12
+    h = r * hf
+    w = dict(d=d, T=8 * h, seed=3, h_fine=hf, systems=[(N, 4, h)],
+             v=dict(rho=0.0, a=0.0, kappa=0.0, lam=0.0), b=dict(c0=0.0, lam=0.0, g=0.0, ell=1.0),
+             sigma=dict(s0=[1.0] * d, s1=[0.0] * d, s2=[0.0] * d), x0_mean=[0.0] * d, x0_std=[0.0] * d)
+    with _ssm(w, prec) as s:
+        s.step(5)
+        got = s.state(0)
+    ref = np.zeros((d, N))
+    for i in range(N):
+        ref[:, i] = sum(oracle.brownian(w["seed"], d, i, 4, n * r, r, hf) for n in range(5))
+    err = float(np.max(np.abs(got - ref)))
+    scale = float(np.max(np.abs(ref)))
+    _say(f"context increments d={d} r={r} {prec}: max abs diff {err:.3e} (|X| up to {scale:.3f})")
+    assert err <= (8 * 2.0 ** -52 if prec == "fp64" else 1e-6) * scale
+
+
 # --------------------------------------------------------------------------- implicit step (2.3)
 @pytest.mark.parametrize("d", [1, 2, 3, 4])
 def test_implicit_solve_matches_oracle(torch_cuda, d):
