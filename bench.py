@@ -431,7 +431,10 @@ def study_batched(args, stream):
 def study_surrogate(args, stream):
     """Learned surrogate (d=2, N=2^20, h=2^-9, T=1): training pairs from exact
     runs of other ensembles, Adam on the GPU, then the exact run and surrogate
-    runs (exact check every 16 steps) of the same paths."""
+    runs (exact check every 16 steps) of the same paths; beside the trained
+    network, the same cadence and tolerances with an all-zero network in
+    residual mode (the exact pair term frozen at the last check: the scheme
+    without a network)."""
     import numpy as np
     import torch
     from paper_2105_09688_amd import workloads as W
@@ -475,9 +478,15 @@ def study_surrogate(args, stream):
     ex.close()
     print(f"[surrogate] exact run {dt_ex:.1f} s", file=sys.stderr, flush=True)
     runs = {}
-    for mode, tol in (("gain", 1e-3), ("gain", 1e-2), ("gain", 1e9), ("residual", 1e-3), ("residual", 1e9)):
-        def setup(s, tol=tol, mode=mode):
-            s.surrogate_load(master)
+    # the trained network, and (the scheme without a network) an all-zero
+    # network in residual mode: the exact pair term frozen at the last check
+    zeros = np.zeros_like(master)
+    cases = (("gain", 1e-3, master, ""), ("gain", 1e-2, master, ""), ("gain", 1e9, master, ""),
+             ("residual", 1e-3, master, ""), ("residual", 1e9, master, ""),
+             ("residual", 1e-3, zeros, "frozen exact term, "), ("residual", 1e9, zeros, "frozen exact term, "))
+    for mode, tol, weights, tag in cases:
+        def setup(s, tol=tol, mode=mode, weights=weights):
+            s.surrogate_load(weights)
             s.surrogate_enable(check_every=every, tol=tol, mode=mode)
         su, dt_su, _ = timed_run(SSM, w, prec, stream, setup=setup)
         info = su.info()
@@ -485,7 +494,7 @@ def study_surrogate(args, stream):
         m, v = su.moments(0)
         su.close()
         D = X - X_ex
-        runs[f"{mode} tol={tol:g}"] = {
+        runs[f"{tag}{mode} tol={tol:g}"] = {
             "seconds": dt_su, "particle_steps_per_s": N * n / dt_su, "speedup_vs_exact": dt_ex / dt_su,
             "checks": info["surr_checks"], "surrogate_ticks": info["surr_ticks"],
             "fallback_ticks": info["surr_fallback_ticks"], "check_rel_err_last": info["surr_last_err"],
@@ -494,7 +503,7 @@ def study_surrogate(args, stream):
             "pathwise_rms_vs_exact": float(np.sqrt(np.sum(D * D) / N)),
             "mean_diff": [float(x) for x in m - m_ex], "var_diff": [float(x) for x in v - v_ex],
         }
-        print(f"[surrogate] {mode} tol {tol:g}: {dt_su:.2f} s, {info['surr_ticks']} surrogate ticks, "
+        print(f"[surrogate] {tag}{mode} tol {tol:g}: {dt_su:.2f} s, {info['surr_ticks']} surrogate ticks, "
               f"last err {info['surr_last_err']:.3e}, max err {info['surr_max_err']:.3e}", file=sys.stderr, flush=True)
     # strong error at fixed h against a 2^-13 proxy solution on the same paths,
     # at N = min(N, 2^18), the size the network was trained at (the proxy run
@@ -505,12 +514,15 @@ def study_surrogate(args, stream):
     ref = SSM(W.with_h(wr, 2.0 ** -13), precision=prec, stream=stream)
     ref.run()
     rm = {}
-    variants = (("exact", None, None), ("gain tol=1e-2", "gain", 1e-2), ("gain always", "gain", 1e9),
-                ("residual tol=1e-3", "residual", 1e-3), ("residual always", "residual", 1e9))
-    for label, mode, tol in variants:
+    variants = (("exact", None, None, None), ("gain tol=1e-2", "gain", 1e-2, master),
+                ("gain always", "gain", 1e9, master), ("residual tol=1e-3", "residual", 1e-3, master),
+                ("residual always", "residual", 1e9, master),
+                ("frozen exact term tol=1e-3", "residual", 1e-3, zeros),
+                ("frozen exact term always", "residual", 1e9, zeros))
+    for label, mode, tol, weights in variants:
         with SSM(wr, precision=prec, stream=stream) as a:
             if tol is not None:
-                a.surrogate_load(master)
+                a.surrogate_load(weights)
                 a.surrogate_enable(check_every=every, tol=tol, mode=mode)
             a.run()
             rm[label] = math.sqrt(a.sqdiff(0, ref, 0) / Nr)
@@ -518,7 +530,7 @@ def study_surrogate(args, stream):
                 i = a.info()
                 rm[label + " surrogate ticks"] = i["surr_ticks"]
     ref.close()
-    for label, _m, tol in variants[1:]:
+    for label, _m, tol, _w in variants[1:]:
         rm[f"ratio {label} / exact"] = rm[label] / rm["exact"]
     pair_avg = info_ex["pair_ms"] / 1e3 / max(1, info_ex["pair_launches"])
     return {"study": "surrogate", f"rmse_vs_2^-13_at_N={Nr}": rm, "workload": f"d=2 N={N} T=1 h=2^-9, exact check every {every} steps, {prec}",
