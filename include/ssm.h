@@ -139,6 +139,17 @@ typedef struct {
     double b_const[SSM_MAX_D];
     double b_mat[SSM_MAX_D * SSM_MAX_D];
     double b_mean[SSM_MAX_D];
+    /* Symmetric scheme: target groups per band of j-side rows.  0: all groups
+     * at once while their rows (one per target group, d x P elements each) fit
+     * 40 % of the free device memory, else bands of as many groups as fit
+     * 16 GiB (or that 40 %, if less).
+     * > 0: bands of this many groups (capped at the group count).  Banded, the
+     * pair sums run band by band and after each band every particle adds the
+     * band's rows it has to a running total (fixed order: runs stay bitwise
+     * reproducible), so the j-side memory is one band's rows; the results
+     * differ from unbanded ones by summation order only. */
+    int32_t jside_band_groups;
+    int32_t pad_end;
 } ssm_config;
 
 typedef struct {
@@ -153,7 +164,7 @@ typedef struct {
     int32_t targets_per_lane;
     int32_t sources_per_item;
     int32_t symmetric;       /* 1: symmetric pair scheme, 0: ordered pairs */
-    int32_t pad;
+    int32_t jside_band_groups; /* target groups per band of j-side rows (0: not banded) */
     int64_t device_bytes;    /* device memory the context holds */
     /* Kernel timing (ssm_profile enabled): HIP events recorded on the context's
      * stream around the launches of the sampled ticks since the last ssm_profile. */

@@ -38,7 +38,7 @@ class Config(C.Structure):
         ("graphs", C.c_int32),
         ("v_componentwise", C.c_int32), ("kahan_span", C.c_int32),
         ("v_ak", C.c_double * MAX_D), ("b_const", C.c_double * MAX_D), ("b_mat", C.c_double * (MAX_D * MAX_D)),
-        ("b_mean", C.c_double * MAX_D),
+        ("b_mean", C.c_double * MAX_D), ("jside_band_groups", C.c_int32), ("pad_end", C.c_int32),
     ]
 
 
@@ -47,7 +47,7 @@ class Info(C.Structure):
         ("tick", C.c_int64), ("ticks_total", C.c_int64), ("newton_max_seen", C.c_int32),
         ("newton_failures", C.c_int32), ("nonfinite", C.c_int32), ("n_pair_items", C.c_int32),
         ("targets_per_lane", C.c_int32), ("sources_per_item", C.c_int32), ("symmetric", C.c_int32),
-        ("pad", C.c_int32), ("device_bytes", C.c_int64),
+        ("jside_band_groups", C.c_int32), ("device_bytes", C.c_int64),
         ("pair_launches", C.c_int64), ("pair_ms", C.c_double),
         ("update_launches", C.c_int64), ("update_ms", C.c_double),
         ("surr_checks", C.c_int64), ("surr_ticks", C.c_int64), ("surr_fallback_ticks", C.c_int64),

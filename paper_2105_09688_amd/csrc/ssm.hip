@@ -90,25 +90,27 @@ __global__ void k_implicit_plain(int64_t N, const double* __restrict__ X, double
 // Symmetric scheme: one workgroup per item.
 template <typename T, int D>
 static void launch_pair_sym_D(int R, bool kahan, int n, hipStream_t st, const PairItem* items, const SysDev* sys,
-                              const T* Ys, int64_t P, T* Bp, T* Bpj)
+                              const T* Ys, int64_t P, T* Bp, T* Bpj, int jrow_base)
 {
     dim3 grid((unsigned)n), block(64 * kWaves);
     if constexpr (sizeof(T) == sizeof(double)) {
         // FP64: no compensation; R * d bounded by the LDS row
         (void)kahan;
         switch (R) {
-            case 1: hipLaunchKernelGGL((k_pair_sym<T, D, 1, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj); break;
-            case 2: if constexpr (D <= 3) hipLaunchKernelGGL((k_pair_sym<T, D, 2, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj); break;
-            case 4: if constexpr (D == 1) hipLaunchKernelGGL((k_pair_sym<T, D, 4, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj); break;
+            case 1: hipLaunchKernelGGL((k_pair_sym<T, D, 1, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj, jrow_base); break;
+            case 2: if constexpr (D <= 3) hipLaunchKernelGGL((k_pair_sym<T, D, 2, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj, jrow_base); break;
+            case 4: if constexpr (D == 1) hipLaunchKernelGGL((k_pair_sym<T, D, 4, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj, jrow_base); break;
             default: break;
         }
     } else {
 #define SSM_SYM_CASE(RR)                                                                                      \
     case RR:                                                                                                  \
         if (kahan)                                                                                            \
-            hipLaunchKernelGGL((k_pair_sym<T, D, RR, true>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj);  \
+            hipLaunchKernelGGL((k_pair_sym<T, D, RR, true>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj,   \
+                               jrow_base);                                                                    \
         else                                                                                                  \
-            hipLaunchKernelGGL((k_pair_sym<T, D, RR, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj); \
+            hipLaunchKernelGGL((k_pair_sym<T, D, RR, false>), grid, block, 0, st, items, sys, Ys, P, Bp, Bpj,  \
+                               jrow_base);                                                                    \
         break;
         switch (R) {
             SSM_SYM_CASE(1)
@@ -148,7 +150,7 @@ static void launch_pair_T(int R, bool kahan, dim3 grid, hipStream_t st, const Pa
 template <typename T>
 static void launch_pair(int d, int R, bool kahan, dim3 grid, hipStream_t st, const PairItem* items,
                         int n, const SysDev* sys, const T* Ys, int64_t P, T* Bp, T* Bpj, bool sym,
-                        bool kpair = false)
+                        bool kpair = false, int jrow_base = 0)
 {
     if constexpr (sizeof(T) == sizeof(float)) {
         if (kpair) {
@@ -168,10 +170,10 @@ static void launch_pair(int d, int R, bool kahan, dim3 grid, hipStream_t st, con
     }
     if (sym) {
         switch (d) {
-            case 1: launch_pair_sym_D<T, 1>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
-            case 2: launch_pair_sym_D<T, 2>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
-            case 3: launch_pair_sym_D<T, 3>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
-            case 4: launch_pair_sym_D<T, 4>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj); break;
+            case 1: launch_pair_sym_D<T, 1>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj, jrow_base); break;
+            case 2: launch_pair_sym_D<T, 2>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj, jrow_base); break;
+            case 3: launch_pair_sym_D<T, 3>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj, jrow_base); break;
+            case 4: launch_pair_sym_D<T, 4>(R, kahan, n, st, items, sys, Ys, P, Bp, Bpj, jrow_base); break;
             default: break;
         }
         return;
@@ -242,6 +244,10 @@ struct ssm_ctx {
     void* Bpj = nullptr;       // symmetric scheme: j-side partials [nb_max][d][P] (pair precision)
     double* pairsum = nullptr; // [d][P] scaled pair term of the last exact tick (k_combine)
     bool sym = false;          // symmetric pair scheme
+    int64_t band = 0;          // symmetric scheme: target groups per band of j-side rows (0: not banded)
+    int64_t n_bands = 1;
+    double* jtot = nullptr;    // banded: [d][P] running total of a particle's j-side sums (k_jfold)
+    std::vector<std::vector<int64_t>> pair_band_off;  // per phase: first item of each band, and the end
     bool kpair = false;        // FP32-compensated with every pair term compensated (kahan_span = 1)
     int64_t nb_max = 0;
     double* psumX = nullptr;
@@ -357,7 +363,8 @@ static void free_ctx(ssm_ctx* c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* bufs[] = {c->x_bound ? nullptr : c->X, c->Y, c->Ys, c->Bp, c->Bpj, c->pairsum, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
                     c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list, c->smean_part, c->smean,
-                    c->dtick, c->dW, c->surr_res, c->dnmax, c->dred, c->dsq, c->win, c->dwin_items, c->ymean};
+                    c->dtick, c->dW, c->surr_res, c->dnmax, c->dred, c->dsq, c->win, c->dwin_items, c->ymean,
+                    c->jtot};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     recycle_events(c, c->ev_pair);
@@ -453,11 +460,30 @@ static void order_items(std::vector<std::pair<int64_t, PairItem>>& tmp, std::vec
     for (auto& p : tmp) out.push_back(p.second);
 }
 
-static void build_pair_items(const ssm_ctx* c, const std::vector<int>& systems, std::vector<PairItem>& out)
+// The items of the listed systems, longest first; banded (symmetric scheme
+// with j-side bands), band by band: band_off receives the first item of each
+// band and the end.
+static void build_pair_items(const ssm_ctx* c, const std::vector<int>& systems, std::vector<PairItem>& out,
+                             std::vector<int64_t>* band_off)
 {
     std::vector<std::pair<int64_t, PairItem>> tmp;
     for (int s : systems) plan_system(s, c->sys[s].N, c->R, c->sym, c->L, tmp, nullptr);
-    order_items(tmp, out);
+    if (!band_off) {
+        order_items(tmp, out);
+        return;
+    }
+    const int64_t group = 64 * (int64_t)c->R * kWaves;
+    std::vector<std::vector<std::pair<int64_t, PairItem>>> per(c->n_bands);
+    for (auto& p : tmp) {
+        const int64_t a = p.second.jrow >= 0 ? p.second.jrow : p.second.tgt0 / group;
+        per[a / c->band].push_back(p);
+    }
+    band_off->clear();
+    for (auto& v : per) {
+        band_off->push_back((int64_t)out.size());
+        order_items(v, out);
+    }
+    band_off->push_back((int64_t)out.size());
 }
 
 // Default sources per item: about 16384 wavefront items per tick (16 per
@@ -511,6 +537,40 @@ static void build_blk_items(const ssm_ctx* c, const std::vector<int>& systems, s
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->sys[a].N > c->sys[b].N; });
     for (int s : order)
         for (int64_t b = 0; b < c->sys[s].nblk; ++b) out.push_back(BlkItem{s, (int32_t)b});
+}
+
+// The pair sums of phase ph's items into the partial-sum buffers: one launch,
+// or (banded j-side rows) one launch per band followed by the fold of that
+// band's rows into jtot for every stepping particle.
+template <typename T>
+static ssm_status launch_pairs(ssm_ctx* c, int64_t ph)
+{
+    const int d = c->d;
+    const int64_t np = c->pair_cnt[ph];
+    const PairItem* items = c->dpair + c->pair_off[ph];
+    if (c->band == 0) {
+        const dim3 grid((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves));
+        launch_pair<T>(d, c->R, c->prec == SSM_FP32_KAHAN, grid, c->stream, items, (int)np, c->dsys, (const T*)c->Ys,
+                       c->P, (T*)c->Bp, (T*)c->Bpj, c->sym, c->kpair);
+        HIP_TRY(hipGetLastError());
+        return SSM_OK;
+    }
+    const std::vector<int64_t>& off = c->pair_band_off[ph];
+    const BlkItem* blks = c->dblk + c->blk_off[ph];
+    const unsigned nb = (unsigned)c->blk_cnt[ph];
+    for (int64_t b = 0; b < c->n_bands; ++b) {
+        const int64_t n = off[b + 1] - off[b];
+        if (n == 0) continue;  // no system has groups in this band: no particle reads its rows
+        const int a0 = (int)(b * c->band), a1 = (int)((b + 1) * c->band);
+        // off[] holds positions in the whole item list (dpair)
+        launch_pair<T>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)n), c->stream, c->dpair + off[b], (int)n,
+                       c->dsys, (const T*)c->Ys, c->P, (T*)c->Bp, (T*)c->Bpj, true, false, a0);
+        HIP_TRY(hipGetLastError());
+        SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_jfold<T, D>), dim3(nb), dim3(kBlk), 0, c->stream, blks, c->dsys, c->P,
+                                             (const T*)c->Bpj, a0, a1, b == 0 ? 1 : 0, c->jtot));
+        HIP_TRY(hipGetLastError());
+    }
+    return SSM_OK;
 }
 
 template <typename T>
@@ -574,16 +634,14 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
         HIP_TRY(hipGetLastError());
     }
     if (c->has_pair && np > 0 && run_exact) {
-        dim3 grid((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves));
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (prof) {
             e0 = take_event(c);
             e1 = take_event(c);
             if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
         }
-        launch_pair<T>(d, c->R, c->prec == SSM_FP32_KAHAN, grid, c->stream, c->dpair + c->pair_off[ph],
-                       (int)np, c->dsys, Ys, c->P, (T*)c->Bp, (T*)c->Bpj, c->sym, c->kpair);
-        HIP_TRY(hipGetLastError());
+        ssm_status st = launch_pairs<T>(c, ph);
+        if (st != SSM_OK) return st;
         if (prof) {
             if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
             c->ev_pair.push_back({e0, e1});
@@ -615,7 +673,8 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
     if (comb) {                                                                                                       \
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_prep<T, D, LPV>), dim3(gb), dim3(kBlk), 0, c->stream, ncb, n_main,    \
                                              items, c->dsys, c->coef, c->P, (const T*)c->Bp, (const T*)c->Bpj,        \
-                                             c->pairsum, c->tick, tdev, (const double*)c->win, c->dW, job));          \
+                                             (const double*)c->jtot, c->pairsum, c->tick, tdev, (const double*)c->win, \
+                                             c->dW, job));                                                            \
     } else {                                                                                                          \
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_brownian_sum<D, LPV, (sizeof(T) == 4)>), dim3(gb), dim3(kBlk), 0,    \
                                              c->stream, n_main,                                                       \
@@ -796,6 +855,7 @@ static ssm_status validate(const ssm_config* cfg)
         return fail(SSM_ERR_INVALID, "targets_per_lane must be 0, 1, 2, 4 or 8");
     if (cfg->sources_per_item != 0 && cfg->sources_per_item < 64)
         return fail(SSM_ERR_INVALID, "sources_per_item must be 0 or >= 64");
+    if (cfg->jside_band_groups < 0) return fail(SSM_ERR_INVALID, "jside_band_groups must be >= 0");
     for (int s = 0; s < cfg->n_sys; ++s) {
         const double h = cfg->h[s];
         if (cfg->N[s] < 1 || cfg->N[s] > 0x7fffffff - 1024) return fail(SSM_ERR_INVALID, "N out of range");
@@ -942,10 +1002,43 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     for (int attempt = 0; attempt < 2; ++attempt) {
         std::vector<int64_t> Ns;
         for (auto& S : c->sys) Ns.push_back(S.N);
+        // the symmetric scheme's j-side partials: one row of d x P elements of
+        // the pair precision per target group (the groups of the largest
+        // system); past 40 % of the device's free memory (115 GB of an idle
+        // MI355X's 288 GB; 32 GiB when it cannot be queried) they run in bands
+        // (k_jfold) of as many groups as fit 16 GiB (every row is read once per
+        // tick either way, so larger bands would save only launches), or in
+        // the requested bands
+        c->band = 0;
+        c->n_bands = 1;
+        if (c->sym) {
+            const int64_t group = 64 * (int64_t)c->R * kWaves;
+            int64_t groups = 0;
+            for (int64_t N : Ns) groups = std::max(groups, (N + group - 1) / group);
+            const double row_bytes = (double)c->d * (double)c->P * elt(c->prec);
+            int64_t band = 0;
+            if (cfg->jside_band_groups > 0) {
+                band = std::min<int64_t>(cfg->jside_band_groups, groups);
+            } else if ((double)groups * row_bytes > jside_cap()) {
+                band = (int64_t)(std::min(jside_cap(), 16.0 * (double)(1ull << 30)) / row_bytes);
+                if (band < 1) {
+                    if (cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "symmetric scheme: one j-side row does not fit 40 % of the free device memory; use ordered pairs"); }
+                    c->sym = false;
+                    continue;
+                }
+            }
+            if (band > 0 && band < groups) {
+                c->band = band;
+                c->n_bands = (groups + band - 1) / band;
+            }
+        }
         if (cfg->sources_per_item > 0) {
             c->L = c->sym ? (cfg->sources_per_item + 15) / 16 * 16 : cfg->sources_per_item;
         } else {
             c->L = default_L(Ns, c->R, c->sym, c->d);
+            // banded, each band's launch takes about the item count of an
+            // unbanded one (enough workgroups to fill the chip)
+            if (c->n_bands > 1) c->L = std::max<int64_t>(128, (c->L / c->n_bands + 15) / 16 * 16);
         }
         c->max_splits = 1;
         c->nb_max = 0;
@@ -956,13 +1049,7 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
             c->max_splits = std::max(c->max_splits, c->sys[s].splits);
             c->nb_max = std::max(c->nb_max, nb);
         }
-        // the symmetric scheme's j-side partials take groups x d x P elements of the pair precision; past
-        // 40 % of the device's free memory (115 GB of an idle MI355X's 288 GB;
-        // 32 GiB when it cannot be queried) the default falls back to ordered pairs
-        const double jbytes = (double)c->nb_max * c->d * (double)c->P * elt(c->prec);
-        if (!c->sym || jbytes <= jside_cap()) break;
-        if (cfg->pair_scheme == 2) { free_ctx(c); return fail(SSM_ERR_INVALID, "symmetric scheme needs more than 40 % of the free device memory for its partial sums; raise targets_per_lane or use ordered pairs"); }
-        c->sym = false;
+        break;
     }
 
     // stream
@@ -996,8 +1083,10 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
         for (int s = 0; s < (int)c->sys.size(); ++s)
             if (ph % c->sys[s].stride == 0) act.push_back(s);
         c->pair_off[ph] = (int64_t)pairs.size();
-        if (c->has_pair) build_pair_items(c, act, pairs);
+        std::vector<int64_t> boff;
+        if (c->has_pair) build_pair_items(c, act, pairs, c->band > 0 ? &boff : nullptr);
         c->pair_cnt[ph] = (int64_t)pairs.size() - c->pair_off[ph];
+        c->pair_band_off.push_back(boff);
         c->blk_off[ph] = (int64_t)blks.size();
         build_blk_items(c, act, blks);
         c->blk_cnt[ph] = (int64_t)blks.size() - c->blk_off[ph];
@@ -1045,7 +1134,8 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     ALLOC(c->Ys, field);
     ALLOC(c->Bp, c->has_pair ? (size_t)c->max_splits * c->d * c->P * elt(c->prec) : 0);
     ALLOC(c->pairsum, c->has_pair ? (size_t)c->d * c->P * sizeof(double) : 0);
-    ALLOC(c->Bpj, (c->has_pair && c->sym) ? (size_t)c->nb_max * c->d * c->P * elt(c->prec) : 0);
+    ALLOC(c->Bpj, (c->has_pair && c->sym) ? (size_t)(c->band > 0 ? c->band : c->nb_max) * c->d * c->P * elt(c->prec) : 0);
+    if (c->band > 0) ALLOC(c->jtot, (size_t)c->d * c->P * sizeof(double));
     ALLOC(c->psumX, 2 * (size_t)(c->d + 1) * c->nblk_tot * sizeof(double));
     ALLOC(c->psumY, 2 * (size_t)c->d * c->nblk_tot * sizeof(double));
     ALLOC(c->dsys, sd.size() * sizeof(SysDev));
@@ -1454,6 +1544,7 @@ extern "C" ssm_status ssm_info(ssm_ctx* c, ssm_info_t* out)
     out->targets_per_lane = c->R;
     out->sources_per_item = (int32_t)c->L;
     out->symmetric = c->sym ? 1 : 0;
+    out->jside_band_groups = (int32_t)c->band;
     out->device_bytes = c->bytes;
     out->pair_launches = (int64_t)c->ev_pair.size();
     out->pair_ms = elapsed_ms(c->ev_pair);
@@ -1568,10 +1659,12 @@ extern "C" ssm_status ssm_pair_sum(int32_t d, int64_t N, int32_t precision, cons
     const dim3 gc((unsigned)(4 * ((N + kBlk - 1) / kBlk)));
     if (precision == SSM_FP64) {
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<double, D>), gc, dim3(64 * kCombineWaves), 0, st,
-                                             (const BlkItem*)nullptr, dS, N, (const double*)dBp, (const double*)dBpj, K));
+                                             (const BlkItem*)nullptr, dS, N, (const double*)dBp, (const double*)dBpj,
+                                             (const double*)nullptr, K));
     } else {
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<float, D>), gc, dim3(64 * kCombineWaves), 0, st,
-                                             (const BlkItem*)nullptr, dS, N, (const float*)dBp, (const float*)dBpj, K));
+                                             (const BlkItem*)nullptr, dS, N, (const float*)dBp, (const float*)dBpj,
+                                             (const double*)nullptr, K));
     }
     HIP_TRY(hipGetLastError());
     // the host-side plan must outlive the asynchronous copies
@@ -1755,22 +1848,25 @@ extern "C" ssm_status ssm_surrogate_samples(ssm_ctx* c, int32_t sys, int64_t n, 
     // exact pair sums and RFF moments of the current Y* of every system (phase-0 lists hold all)
     const int64_t np = c->pair_cnt[0], nb = c->blk_cnt[0];
     const int d = c->d;
+    (void)np;
     if (c->prec == SSM_FP64) {
-        launch_pair<double>(d, c->R, false, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const double*)c->Ys, c->P, (double*)c->Bp, (double*)c->Bpj, c->sym);
+        st = launch_pairs<double>(c, 0);
+        if (st != SSM_OK) return st;
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<double, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const double*)c->Y, c->rff, c->rff_part));
     } else {
-        launch_pair<float>(d, c->R, c->prec == SSM_FP32_KAHAN, dim3((unsigned)(c->sym ? np : (np + kWaves - 1) / kWaves)), c->stream, c->dpair + c->pair_off[0], (int)np, c->dsys, (const float*)c->Ys, c->P, (float*)c->Bp, (float*)c->Bpj, c->sym, c->kpair);
+        st = launch_pairs<float>(c, 0);
+        if (st != SSM_OK) return st;
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_rff_partial<float, D>), dim3((unsigned)nb), dim3(kBlk), 0, c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const float*)c->Y, c->rff, c->rff_part));
     }
     HIP_TRY(hipGetLastError());
     if (c->prec == SSM_FP64) {
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<double, D>), dim3((unsigned)(nb * 4)), dim3(64 * kCombineWaves), 0,
                                              c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const double*)c->Bp,
-                                             (const double*)c->Bpj, c->pairsum));
+                                             (const double*)c->Bpj, (const double*)c->jtot, c->pairsum));
     } else {
         SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_combine<float, D>), dim3((unsigned)(nb * 4)), dim3(64 * kCombineWaves), 0,
                                              c->stream, c->dblk + c->blk_off[0], c->dsys, c->P, (const float*)c->Bp,
-                                             (const float*)c->Bpj, c->pairsum));
+                                             (const float*)c->Bpj, (const double*)c->jtot, c->pairsum));
     }
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_rff_final, dim3((unsigned)c->sys_list_cnt[0], 2 * kRff), dim3(kBlk), 0, c->stream, c->dsys_list + c->sys_list_off[0], c->dsys, c->rff_part, c->mom);

@@ -203,11 +203,13 @@ __device__ __forceinline__ double sum_rows(const PT* __restrict__ Bp, const PT* 
 // ---------------------------------------------------------------------------
 constexpr int kCombineWaves = 4;
 
+// jtot (banded j-side, see k_jfold): when given, the particle's j-side sums
+// are that one double instead of its j-side rows; it is added last.
 template <typename PT, int D>
 __device__ __forceinline__ void combine_block(int vb, const BlkItem* __restrict__ items,
                                               const SysDev* __restrict__ sys, int64_t P, const PT* __restrict__ Bp,
-                                              const PT* __restrict__ Bpj, double* __restrict__ out,
-                                              double (*part)[D][64])
+                                              const PT* __restrict__ Bpj, const double* __restrict__ jtot,
+                                              double* __restrict__ out, double (*part)[D][64])
 {
     const int q4 = vb & 3;
     const BlkItem it = items ? items[vb >> 2] : BlkItem{0, (int32_t)(vb >> 2)};
@@ -217,7 +219,8 @@ __device__ __forceinline__ void combine_block(int vb, const BlkItem* __restrict_
     const int i = it.blk * kBlk + q4 * 64 + lane;
     const bool valid = i < S.N;
     const int64_t slot = S.off + i;
-    const PairRows pr = valid ? pair_rows(S, i) : PairRows{0, 0};
+    PairRows pr = valid ? pair_rows(S, i) : PairRows{0, 0};
+    if (jtot) pr.nj = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) part[wave][k][lane] = sum_rows<D, kCombineWaves, PT>(Bp, Bpj, pr, k, P, slot, wave);
     __syncthreads();
@@ -227,8 +230,38 @@ __device__ __forceinline__ void combine_block(int vb, const BlkItem* __restrict_
             double t = part[0][k][lane];
 #pragma unroll
             for (int w = 1; w < kCombineWaves; ++w) t += part[w][k][lane];
+            if (jtot) t += jtot[k * P + slot];
             out[k * P + slot] = t * S.pair_scale;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_jfold: banded j-side sums.  When the symmetric scheme's j-side rows (one
+// per target group) would not fit the memory budget, the pair sums run in
+// bands of target groups [a0, a1), each band writing its rows to rows
+// a - a0 of Bpj; after each band, every particle adds the rows its own band
+// holds for it (groups a0 .. min(a1, g + 1) - 1, g the particle's group, in
+// ascending order) to its running total jtot (first band: from zero).  The
+// order of the additions is fixed, so runs stay bitwise reproducible.
+// One thread per particle of the listed blocks.
+// ---------------------------------------------------------------------------
+template <typename PT, int D>
+__global__ __launch_bounds__(kBlk) void k_jfold(const BlkItem* __restrict__ items, const SysDev* __restrict__ sys,
+                                                int64_t P, const PT* __restrict__ Bpj, int a0, int a1, int first,
+                                                double* __restrict__ jtot)
+{
+    const BlkItem it = items[blockIdx.x];
+    const SysDev S = sys[it.sys];
+    const int i = it.blk * kBlk + threadIdx.x;
+    if (i >= S.N || !S.sym_B) return;
+    const int64_t slot = S.off + i;
+    const int hi = min(a1, i / S.sym_B + 1);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double t = first ? 0.0 : jtot[k * P + slot];
+        for (int a = a0; a < hi; ++a) t += (double)Bpj[((int64_t)(a - a0) * D + k) * P + slot];
+        jtot[k * P + slot] = t;
     }
 }
 
@@ -237,10 +270,11 @@ __global__ __launch_bounds__(64 * kCombineWaves) void k_combine(const BlkItem* _
                                                                const SysDev* __restrict__ sys, int64_t P,
                                                                const PT* __restrict__ Bp,
                                                                const PT* __restrict__ Bpj,
+                                                               const double* __restrict__ jtot,
                                                                double* __restrict__ out)
 {
     __shared__ double part[kCombineWaves][D][64];
-    combine_block<PT, D>(blockIdx.x, items, sys, P, Bp, Bpj, out, part);
+    combine_block<PT, D>(blockIdx.x, items, sys, P, Bp, Bpj, jtot, out, part);
 }
 
 // The tick a per-tick kernel works on: the context's device counter when
@@ -744,6 +778,7 @@ template <typename PT, int D, int LP>
 __global__ __launch_bounds__(kBlk) void k_prep(int n_combine, int n_main, const BlkItem* __restrict__ items,
                                                const SysDev* __restrict__ sys, Coef cf, int64_t P,
                                                const PT* __restrict__ Bp, const PT* __restrict__ Bpj,
+                                               const double* __restrict__ jtot,
                                                double* __restrict__ pairsum, int64_t tick_arg,
                                                const int64_t* __restrict__ tick_dev, const double* __restrict__ win,
                                                double* __restrict__ dW, YMeanJob job)
@@ -751,7 +786,7 @@ __global__ __launch_bounds__(kBlk) void k_prep(int n_combine, int n_main, const 
     static_assert(64 * kCombineWaves == kBlk, "one block shape for both parts");
     __shared__ double part[kCombineWaves][D][64];
     if ((int)blockIdx.x < n_combine)
-        combine_block<PT, D>(blockIdx.x, items, sys, P, Bp, Bpj, pairsum, part);
+        combine_block<PT, D>(blockIdx.x, items, sys, P, Bp, Bpj, jtot, pairsum, part);
     else if ((int)blockIdx.x < n_main)
         brownian_block<D, LP, (sizeof(PT) == 4)>(blockIdx.x - n_combine, items, sys, cf, P, tick_arg, tick_dev, win, dW);
     else
@@ -1017,7 +1052,9 @@ __device__ __forceinline__ void sym_chunk(const T* __restrict__ base, int64_t P,
 //  - a later source range (jrow = a): unordered pairs with every block of
 //    the group; i-side partial `split`, j-side row a.
 // j-side sums pass through LDS (sym_lds(d) / d sources at a time) and are added
-// over the wavefronts in a fixed order before they are written.
+// over the wavefronts in a fixed order before they are written.  With banded
+// j-side rows (k_jfold) the launch covers the groups of one band and row a
+// is stored at a - jrow_base.
 template <typename T, int D, int R, bool KAHAN>
 __device__ __forceinline__ void kahan_fold(T (&acc)[R][D], T (&hi)[R][D], T (&lo)[R][D])
 {
@@ -1056,7 +1093,7 @@ template <typename T, int D, int R, bool KAHAN>
 __global__ __launch_bounds__(64 * kWaves) void k_pair_sym(const PairItem* __restrict__ items,
                                                           const SysDev* __restrict__ sys,
                                                           const T* __restrict__ Ys, int64_t P,
-                                                          T* __restrict__ Bp, T* __restrict__ Bpj)
+                                                          T* __restrict__ Bp, T* __restrict__ Bpj, int jrow_base)
 {
     constexpr int stride = sym_lds_t<T, D>() / D;  // LDS j-side capacity (sources) per component
     __shared__ T jred[kWaves][(sym_row_t<T, D>())];
@@ -1114,14 +1151,15 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sym(const PairItem* __rest
         }
         if (!diag) {
             __syncthreads();
-            jside_flush<T, D>(jred, Bpj, (int64_t)it.jrow, P, S.off, u0, u1 - u0, u0);
+            jside_flush<T, D>(jred, Bpj, (int64_t)(it.jrow - jrow_base), P, S.off, u0, u1 - u0, u0);
             if (u1 < end) __syncthreads();  // the next piece reuses the LDS
         }
     }
     if constexpr (KAHAN) kahan_fold<T, D, R, KAHAN>(acc, hi, lo);
     if (diag) {
         __syncthreads();
-        jside_flush<T, D>(jred, Bpj, (int64_t)(it.tgt0 / (blk * kWaves)), P, S.off, it.tgt0, it.nsrc, it.tgt0);
+        jside_flush<T, D>(jred, Bpj, (int64_t)(it.tgt0 / (blk * kWaves) - jrow_base), P, S.off, it.tgt0, it.nsrc,
+                          it.tgt0);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {

@@ -212,23 +212,68 @@ def test_full_size_first_step_sampled(torch_cuda, case):
 
 
 def test_maximum_size_symmetric_step_sampled(torch_cuda):
-    """d = 2, N = 2^21 (twice the surrogate case), the largest size the
-    symmetric scheme takes here: 64 GiB of j-side partial rows, within the
-    40 %-of-free-memory cap.  The first exact step at 128 sampled particles
-    against the oracle's step there, FP32-compensated."""
-    w = W.surrogate_d2(N=2 ** 21)
+    """d = 2, N = 2^22 (four times the surrogate case) in the symmetric
+    scheme: its 8192 target groups would need 256 GiB of j-side rows (more
+    than 40 % of the free device memory), so the library runs them in bands
+    of 512 groups (16 GiB, k_jfold).  The first exact step at 128 sampled particles against the
+    oracle's step there, FP32-compensated."""
+    w = W.surrogate_d2(N=2 ** 22)
     N, ens, h = w["systems"][0]
     idx = _sample(N, 128, 21)
-    _say("oracle step at 128 particles, d=2 N=2^21")
+    _say("oracle step at 128 particles, d=2 N=2^22")
     ref = oracle.step_at(w, ens, h, 0, oracle.init_state(w, ens, N), idx)
     with _ssm(w, "fp32_kahan") as s:
         info = s.info()
-        _say(f"d=2 N=2^21: {info['pair_scheme']}, {info['device_bytes'] / 2 ** 30:.1f} GiB")
-        assert info["pair_scheme"] == "symmetric" and info["device_bytes"] > 64 * 2 ** 30
+        _say(f"d=2 N=2^22: {info['pair_scheme']}, bands of {info['jside_band_groups']} groups, "
+             f"{info['device_bytes'] / 2 ** 30:.1f} GiB")
+        assert info["pair_scheme"] == "symmetric" and info["jside_band_groups"] == 512
+        assert info["device_bytes"] < 20 * 2 ** 30
         s.step(1)
         err = _err(s.state(0)[:, idx], ref)
     _say(f"  max rel err {err:.3e}")
     assert err <= FP32_TOL
+
+
+def _banded_case(d):
+    """Three systems of ragged sizes (6, 3 and 2 target groups of 256 at one
+    target per lane) with the coefficients of the workload of that d."""
+    base = {1: W.small_parity(n_ens=1, N=8, h=2.0 ** -6, h_fine=2.0 ** -6),
+            2: W.surrogate_d2(N=8, h=2.0 ** -6, h_fine=2.0 ** -6),
+            3: W.precision_d3(N=8, h=2.0 ** -6)}[d]
+    w = W.with_systems(base, [(1500, 0, 2.0 ** -6), (700, 1, 2.0 ** -6), (300, 2, 2.0 ** -6)])
+    w["T"] = 4 * 2.0 ** -6
+    return w
+
+
+@pytest.mark.parametrize("d,prec", [(1, "fp64"), (1, "fp32_kahan"), (2, "fp32_kahan"), (3, "fp64")])
+def test_banded_jside_matches_oracle_and_unbanded(torch_cuda, d, prec):
+    """The symmetric scheme with its j-side rows in bands of 1, 2 and 4
+    target groups (forced; the fold adds each band's rows to a running total
+    per particle) against the oracle (FP64 1e-10, FP32 1e-4), against the
+    unbanded run (summation order only: FP64 1e-13, FP32 1e-6), and bitwise
+    reproducible."""
+    w = _banded_case(d)
+    ref = oracle.run(w)
+    tol = FP64_TOL if prec == "fp64" else FP32_TOL
+    with _ssm(w, prec, targets_per_lane=1, pair_scheme="symmetric") as u:
+        u.run()
+        assert u.info()["jside_band_groups"] == 0
+        plain = u.states()
+    for band in (1, 2, 4):
+        runs = []
+        for rep in range(2 if band == 2 else 1):
+            with _ssm(w, prec, targets_per_lane=1, pair_scheme="symmetric", jside_band_groups=band) as b:
+                assert b.info()["jside_band_groups"] == band
+                b.run()
+                runs.append(b.states())
+        got = runs[0]
+        e_or = max(_err(g, r) for g, r in zip(got, ref))
+        e_un = max(_err(g, r) for g, r in zip(got, plain))
+        _say(f"banded j-side d={d} {prec} band={band}: vs oracle {e_or:.3e}, vs unbanded {e_un:.3e}")
+        assert e_or <= tol
+        assert e_un <= (1e-13 if prec == "fp64" else 1e-6)
+        if len(runs) == 2:
+            assert all(np.array_equal(a, b) for a, b in zip(runs[0], runs[1]))
 
 
 def test_full_size_batched_first_tick_sampled(torch_cuda):
