@@ -149,7 +149,29 @@ typedef struct {
      * reproducible), so the j-side memory is one band's rows; the results
      * differ from unbanded ones by summation order only. */
     int32_t jside_band_groups;
-    int32_t pad_end;
+    /* Persistent runs of small systems: one cooperative launch runs every
+     * tick of an ssm_step call.  Each workgroup owns 64 particles of one
+     * system, stages the system's positions in LDS, sums the interaction
+     * over every ordered pair of its particles, draws their increments and
+     * updates them; the workgroups of a system then wait at that system's
+     * barrier (one per tick, two when v depends on mu^X).  Needs a single
+     * step size (h equal for all systems), d x N (rounded up to 4) elements
+     * of the precision within 32 KiB per system, the compensated-sum default
+     * (kahan_span = 0) and co-resident workgroups for every 64 particles.
+     * Ticks with the surrogate enabled, with profiling or with graphs run the
+     * multi-launch path.  Every barrier wait is bounded (4 s; the environment
+     * variable SSM_PERSISTENT_WAIT_US, read by ssm_init, sets another limit
+     * in microseconds): a wait that runs out ends the launch in every
+     * workgroup, ssm_sync returns SSM_ERR_HIP and the context refuses
+     * further steps.  Results differ from the multi-launch path by
+     * summation order only (ordered pairs, per-tile sums of the measures).
+     *   0: on when eligible, the systems total at most one tile of 64
+     *      particles per compute unit (where the multi-launch tick is bound
+     *      by launch latency) and no tiling of the multi-launch pair kernels
+     *      (targets_per_lane, sources_per_item, pair_scheme,
+     *      jside_band_groups) is given;  1: on whenever eligible (ssm_init
+     *      fails if the configuration never is);  -1: off. */
+    int32_t persistent;
 } ssm_config;
 
 typedef struct {
@@ -180,6 +202,11 @@ typedef struct {
     double surr_max_err;         /* largest such error seen */
     double surr_last_raw_err;    /* relative error of the last check's bare network output s - mean s */
     double surr_gain[SSM_MAX_D]; /* per-component gain fitted at the last check */
+    /* persistent runs of small systems (ssm_config.persistent) */
+    int32_t persistent;          /* 1: eligible (ticks without surrogate, profiling or graphs use it) */
+    int32_t persistent_tiles;    /* workgroups of a persistent launch (64 particles each) */
+    int64_t persistent_launches; /* cooperative launches so far */
+    int64_t persistent_ticks;    /* ticks they ran */
 } ssm_info_t;
 
 /* Training settings of ssm_mlp_train (Adam; zeros select the defaults in brackets). */

@@ -38,7 +38,7 @@ class Config(C.Structure):
         ("graphs", C.c_int32),
         ("v_componentwise", C.c_int32), ("kahan_span", C.c_int32),
         ("v_ak", C.c_double * MAX_D), ("b_const", C.c_double * MAX_D), ("b_mat", C.c_double * (MAX_D * MAX_D)),
-        ("b_mean", C.c_double * MAX_D), ("jside_band_groups", C.c_int32), ("pad_end", C.c_int32),
+        ("b_mean", C.c_double * MAX_D), ("jside_band_groups", C.c_int32), ("persistent", C.c_int32),
     ]
 
 
@@ -53,6 +53,8 @@ class Info(C.Structure):
         ("surr_checks", C.c_int64), ("surr_ticks", C.c_int64), ("surr_fallback_ticks", C.c_int64),
         ("surr_last_err", C.c_double), ("surr_max_err", C.c_double),
         ("surr_last_raw_err", C.c_double), ("surr_gain", C.c_double * MAX_D),
+        ("persistent", C.c_int32), ("persistent_tiles", C.c_int32),
+        ("persistent_launches", C.c_int64), ("persistent_ticks", C.c_int64),
     ]
 
 

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -14,6 +15,7 @@
 
 #include "../../include/ssm.h"
 #include "ssm_surrogate.hpp"
+#include "ssm_small.hpp"
 
 using namespace ssm;
 
@@ -309,6 +311,18 @@ struct ssm_ctx {
     int32_t profile_every = 1;     // bracket the launches of ticks with tick % profile_every == 0
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pair, ev_update;
     std::vector<hipEvent_t> ev_pool;
+    // persistent runs of small systems (ssm_small.hpp)
+    bool small_ok = false;          // eligible: ticks without surrogate, profiling or graphs use it
+    SmallTile* dtiles = nullptr;    // [small_grid] workgroup -> (system, tile)
+    int64_t small_grid = 0;         // tiles of 64 particles = workgroups per launch
+    double* sumY = nullptr;         // [2][d][small_grid] tile sums of Y*
+    double* sumX = nullptr;         // [d + 1][small_grid] tile sums of the new X and |X|^2
+    uint64_t* dbar = nullptr;       // [n_sys][kBarLine] barrier counters
+    uint64_t small_epoch = 0;       // barriers every system has passed
+    int64_t small_wait_limit = 0;   // wall-clock counts a barrier wait may take
+    int64_t small_launches = 0, small_ticks = 0;
+    bool psum_stale = false;        // the block sums psumY lag Y* (after persistent ticks)
+    bool broken = false;            // a persistent run was aborted
 };
 
 static hipEvent_t take_event(ssm_ctx* c)
@@ -364,7 +378,7 @@ static void free_ctx(ssm_ctx* c)
     void* bufs[] = {c->x_bound ? nullptr : c->X, c->Y, c->Ys, c->Bp, c->Bpj, c->pairsum, c->psumX, c->psumY, c->dsys, c->dpair, c->dblk, c->dflags, c->dstage,
                     c->dmlp, c->surr, c->rff_part, c->mom, c->err_part, c->dsys_list, c->smean_part, c->smean,
                     c->dtick, c->dW, c->surr_res, c->dnmax, c->dred, c->dsq, c->win, c->dwin_items, c->ymean,
-                    c->jtot};
+                    c->jtot, c->dtiles, c->sumY, c->sumX, c->dbar};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     recycle_events(c, c->ev_pair);
@@ -821,6 +835,119 @@ static ssm_status run_tick(ssm_ctx* c)
     return SSM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// persistent runs of small systems (ssm_small.hpp)
+// ---------------------------------------------------------------------------
+static const void* small_kernel(int prec, int d)
+{
+#define SSM_SMALL_K(T, KH)                                                  \
+    switch (d) {                                                            \
+        case 1: return reinterpret_cast<const void*>(&k_small<T, 1, KH>);   \
+        case 2: return reinterpret_cast<const void*>(&k_small<T, 2, KH>);   \
+        case 3: return reinterpret_cast<const void*>(&k_small<T, 3, KH>);   \
+        case 4: return reinterpret_cast<const void*>(&k_small<T, 4, KH>);   \
+        default: return nullptr;                                            \
+    }
+    if (prec == SSM_FP64) { SSM_SMALL_K(double, false) }
+    if (prec == SSM_FP32) { SSM_SMALL_K(float, false) }
+    SSM_SMALL_K(float, true)
+#undef SSM_SMALL_K
+}
+
+// Why a context can never run persistent ticks ("" if it can): one step size,
+// the default compensation, each system's staged positions within the LDS
+// budget, and every tile's workgroup co-resident with the others.
+static std::string small_ineligible(const ssm_ctx* c, int64_t tiles)
+{
+    if (c->max_stride != 1) return "several step sizes (h / h_min > 1)";
+    if (c->kpair) return "kahan_span = 1";
+    for (auto& S : c->sys)
+        if ((int64_t)c->d * small_row(S.N) * (int64_t)elt(c->prec) > kSmallLdsBytes)
+            return "a system's positions (d x N) exceed " + std::to_string(kSmallLdsBytes / 1024) + " KiB";
+    int dev = 0, cus = 0, coop = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, small_kernel(c->prec, c->d), kSmallThreads, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return "device query failed";
+    }
+    if (!coop) return "the device has no cooperative launch";
+    if (tiles > (int64_t)occ * cus)
+        return std::to_string(tiles) + " tiles of 64 particles, more than the " + std::to_string((int64_t)occ * cus) +
+               " co-resident workgroups";
+    return "";
+}
+
+static int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return cus;
+}
+
+static bool small_usable(const ssm_ctx* c)
+{
+    return c->small_ok && c->surr_check_every == 0 && !c->profiling && !c->use_graphs;
+}
+
+// n ticks in one cooperative launch.
+template <typename T>
+static ssm_status launch_small(ssm_ctx* c, int64_t n)
+{
+    SmallArgs<T> a{};
+    a.tiles = c->dtiles;
+    a.sys = c->dsys;
+    a.cf = c->coef;
+    a.P = c->P;
+    a.t0 = c->tick;
+    a.n = n;
+    a.ntile_tot = c->small_grid;
+    a.X = (T*)c->X;
+    a.Y = (T*)c->Y;
+    a.Ys = (T*)c->Ys;
+    a.sumY = c->sumY;
+    a.sumX = c->sumX;
+    a.bar = c->dbar;
+    a.epoch0 = c->small_epoch;
+    a.flags = c->dflags;
+    a.nmax = c->dnmax;
+    a.bm_lanes = c->bm_lanes;
+    a.needs_ybar = c->needs_ybar ? 1 : 0;
+    a.wait_limit = c->small_wait_limit;
+    void* args[] = {&a};
+    HIP_TRY(hipLaunchCooperativeKernel(small_kernel(c->prec, c->d), dim3((unsigned)c->small_grid), dim3(kSmallThreads),
+                                       args, 0, c->stream));
+    c->small_epoch += small_barriers(c->fused, n);
+    c->small_launches++;
+    c->small_ticks += n;
+    for (int64_t t = 0; t < n; ++t) advance_host(c);
+    c->dtick_valid = false;
+    c->psum_stale = true;
+    return SSM_OK;
+}
+
+// The block sums of Y* that the multi-launch path reads, after persistent
+// ticks (which keep tile sums of their own).
+static ssm_status refresh_ysums(ssm_ctx* c)
+{
+    const BlkItem* items = c->dblk + c->all_blk_off[0];
+    const dim3 g((unsigned)c->all_blk_cnt);
+    const int64_t tick_arg = c->tick - 1;  // one step size: tick = steps done
+    if (c->prec == SSM_FP64) {
+        SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_ysums<double, D>), g, dim3(kBlk), 0, c->stream, items, c->dsys,
+                                                c->P, tick_arg, (const double*)c->Y, c->psumY, c->nblk_tot));
+    } else {
+        SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_ysums<float, D>), g, dim3(kBlk), 0, c->stream, items, c->dsys,
+                                                c->P, tick_arg, (const float*)c->Y, c->psumY, c->nblk_tot));
+    }
+    HIP_TRY(hipGetLastError());
+    c->psum_stale = false;
+    return SSM_OK;
+}
+
 template <typename T>
 static ssm_status launch_init(ssm_ctx* c)
 {
@@ -856,6 +983,7 @@ static ssm_status validate(const ssm_config* cfg)
     if (cfg->sources_per_item != 0 && cfg->sources_per_item < 64)
         return fail(SSM_ERR_INVALID, "sources_per_item must be 0 or >= 64");
     if (cfg->jside_band_groups < 0) return fail(SSM_ERR_INVALID, "jside_band_groups must be >= 0");
+    if (cfg->persistent < -1 || cfg->persistent > 1) return fail(SSM_ERR_INVALID, "persistent must be -1, 0 or 1");
     for (int s = 0; s < cfg->n_sys; ++s) {
         const double h = cfg->h[s];
         if (cfg->N[s] < 1 || cfg->N[s] > 0x7fffffff - 1024) return fail(SSM_ERR_INVALID, "N out of range");
@@ -1060,6 +1188,39 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
         c->own_stream = true;
     }
 
+    // persistent runs of small systems: one workgroup per tile of 64 particles
+    std::vector<SmallTile> tiles;
+    if (cfg->persistent >= 0) {
+        int64_t ntiles = 0;
+        for (auto& S : c->sys) ntiles += (S.N + kSmallTile - 1) / kSmallTile;
+        const std::string why = small_ineligible(c, ntiles);
+        if (cfg->persistent == 1 && !why.empty()) { free_ctx(c); return fail(SSM_ERR_INVALID, "persistent = 1: " + why); }
+        // default: where the multi-launch tick is bound by launch latency
+        // (at most one tile per compute unit), unless a tiling of the
+        // multi-launch pair kernels was asked for
+        const bool tiled = cfg->targets_per_lane != 0 || cfg->sources_per_item != 0 || cfg->pair_scheme != 0 ||
+                           cfg->jside_band_groups != 0;
+        c->small_ok = why.empty() && (cfg->persistent == 1 || (!tiled && ntiles <= device_cus()));
+        if (c->small_ok) {
+            for (int s = 0; s < (int)c->sys.size(); ++s) {
+                const int32_t nt = (int32_t)((c->sys[s].N + kSmallTile - 1) / kSmallTile);
+                const int32_t g0 = (int32_t)tiles.size();
+                for (int32_t q = 0; q < nt; ++q) tiles.push_back(SmallTile{s, q, g0, nt});
+            }
+            c->small_grid = (int64_t)tiles.size();
+            int dev = 0, khz = 0;
+            if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) {
+                (void)hipGetLastError();
+                khz = 100000;  // the 100 MHz counter of gfx9
+            }
+            c->small_wait_limit = (int64_t)khz * 1000 * 4;  // 4 s per barrier wait
+            if (const char* env = std::getenv("SSM_PERSISTENT_WAIT_US")) {
+                const long long us = std::atoll(env);
+                if (us >= 0) c->small_wait_limit = (int64_t)khz * us / 1000;
+            }
+        }
+    }
+
     // work lists per phase
     std::vector<PairItem> pairs;
     std::vector<BlkItem> blks;
@@ -1156,6 +1317,12 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     }
     ALLOC(c->dsq, c->sys.size() * sizeof(double));
     ALLOC(c->ymean, c->sys.size() * kMaxD * sizeof(double));
+    if (c->small_ok) {
+        ALLOC(c->dtiles, tiles.size() * sizeof(SmallTile));
+        ALLOC(c->sumY, 2 * (size_t)c->d * c->small_grid * sizeof(double));
+        ALLOC(c->sumX, (size_t)(c->d + 1) * c->small_grid * sizeof(double));
+        ALLOC(c->dbar, c->sys.size() * kBarLine * sizeof(uint64_t));
+    }
 #undef ALLOC
     hipError_t he = hipMemcpyAsync(c->dsys, sd.data(), sd.size() * sizeof(SysDev), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess && !pairs.empty()) he = hipMemcpyAsync(c->dpair, pairs.data(), pairs.size() * sizeof(PairItem), hipMemcpyHostToDevice, c->stream);
@@ -1166,6 +1333,8 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
     if (he == hipSuccess) he = hipMemsetAsync(c->dflags, 0, sizeof(Flags), c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(c->dnmax, 0, (size_t)c->nblk_tot * kSlotsPerBlk * sizeof(int32_t), c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(c->dtick, 0, sizeof(int64_t), c->stream);
+    if (he == hipSuccess && c->small_ok) he = hipMemcpyAsync(c->dtiles, tiles.data(), tiles.size() * sizeof(SmallTile), hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess && c->small_ok) he = hipMemsetAsync(c->dbar, 0, c->sys.size() * kBarLine * sizeof(uint64_t), c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);  // host vectors go out of scope
     if (he != hipSuccess) { std::string m = hipGetErrorString(he); free_ctx(c); return fail(SSM_ERR_HIP, "upload: " + m); }
 
@@ -1178,8 +1347,15 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
 extern "C" ssm_status ssm_step(ssm_ctx* c, int64_t n_ticks)
 {
     if (!c) return fail(SSM_ERR_INVALID, "ctx is NULL");
+    if (c->broken) return fail(SSM_ERR_STATE, "a persistent run of this context was aborted; the context is unusable");
     if (n_ticks < 0) return fail(SSM_ERR_INVALID, "n_ticks < 0");
     if (c->tick + n_ticks > c->ticks_total) return fail(SSM_ERR_STATE, "stepping past T");
+    if (n_ticks == 0) return SSM_OK;
+    if (small_usable(c)) return (c->prec == SSM_FP64) ? launch_small<double>(c, n_ticks) : launch_small<float>(c, n_ticks);
+    if (c->psum_stale) {
+        ssm_status st = refresh_ysums(c);
+        if (st != SSM_OK) return st;
+    }
     for (int64_t t = 0; t < n_ticks; ++t) {
         ssm_status st = (c->prec == SSM_FP64) ? run_tick<double>(c) : run_tick<float>(c);
         if (st != SSM_OK) return st;
@@ -1193,6 +1369,10 @@ extern "C" ssm_status ssm_sync(ssm_ctx* c)
     HIP_TRY(hipStreamSynchronize(c->stream));
     Flags f{};
     HIP_TRY(hipMemcpy(&f, c->dflags, sizeof(Flags), hipMemcpyDeviceToHost));
+    if (f.abort) {
+        c->broken = true;
+        return fail(SSM_ERR_HIP, "a persistent run was aborted: a barrier wait ran out of time");
+    }
     if (f.newton_fail) return fail(SSM_ERR_NEWTON, std::to_string(f.newton_fail) + " implicit solves did not converge");
     if (f.nonfinite) return fail(SSM_ERR_NONFINITE, std::to_string(f.nonfinite) + " particles became non-finite");
     return SSM_OK;
@@ -1557,6 +1737,10 @@ extern "C" ssm_status ssm_info(ssm_ctx* c, ssm_info_t* out)
     out->surr_max_err = c->surr_max_err;
     out->surr_last_raw_err = c->surr_last_raw_err;
     for (int k = 0; k < SSM_MAX_D; ++k) out->surr_gain[k] = c->surr_gain[k];
+    out->persistent = c->small_ok ? 1 : 0;
+    out->persistent_tiles = (int32_t)(c->small_ok ? c->small_grid : 0);
+    out->persistent_launches = c->small_launches;
+    out->persistent_ticks = c->small_ticks;
     return SSM_OK;
 }
 

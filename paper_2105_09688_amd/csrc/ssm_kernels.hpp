@@ -103,7 +103,8 @@ struct Coef {
 struct Flags {
     int32_t newton_fail;
     int32_t nonfinite;
-    int32_t pad[2];
+    int32_t abort;  // a persistent run's barrier wait ran out of time (ssm_small.hpp)
+    int32_t pad;
 };
 
 // Largest Newton iteration count per wavefront slot: slot gb * kSlotsPerBlk + w

@@ -33,7 +33,8 @@ class SSM:
 
     def __init__(self, workload: dict, precision: str = "fp64", stream=None,
                  targets_per_lane: int = 0, sources_per_item: int = 0, graphs: bool = False,
-                 pair_scheme: str = "default", kahan_span: int = 0, jside_band_groups: int = 0):
+                 pair_scheme: str = "default", kahan_span: int = 0, jside_band_groups: int = 0,
+                 persistent: int = 0):
         lib = _lib.load()
         w = workload
         d = int(w["d"])
@@ -65,6 +66,7 @@ class SSM:
         c.pair_scheme = {"default": 0, "ordered": 1, "symmetric": 2}[pair_scheme]
         c.kahan_span = int(kahan_span)  # 1: every pair term compensated (fp32_kahan, ordered pairs)
         c.jside_band_groups = int(jside_band_groups)  # symmetric scheme: j-side rows in bands of this many groups
+        c.persistent = int(persistent)  # small systems in one launch per step call: 0 default, 1 on, -1 off
         # coefficient extensions: component-wise cubic in v, b += b_const + b_mat y + b_mean o ybar
         c.v_componentwise = int(bool(v.get("componentwise", False)))
         ak, bc, bm, bmean = v.get("a_k"), b.get("const"), b.get("mat"), b.get("mean")

@@ -741,7 +741,8 @@ def test_profile_stride_times_the_sampled_ticks_only(torch_cuda):
     tick % k == 0; every = 0 switches timing off; the run itself is unchanged."""
     from paper_2105_09688_amd import SSMError
     w = W.small_parity(n_ens=1, N=700)
-    with _ssm(w, "fp32_kahan") as a, _ssm(w, "fp32_kahan") as b:
+    # both on the multi-launch path (a profiling context runs it)
+    with _ssm(w, "fp32_kahan", persistent=-1) as a, _ssm(w, "fp32_kahan", persistent=-1) as b:
         a.profile(True, every=4)
         a.step(16)
         b.step(16)
