@@ -173,20 +173,30 @@ def study_precision(args, stream):
 
 
 def study_small(args, stream):
-    """Small parity case (10 ensembles x N=1000, d=1, 256 steps, FP64):
-    whole-run time with eager launches and with per-tick graph replays."""
+    """Small parity case (10 ensembles x N=1000, d=1, 256 steps, FP64; also
+    FP32-compensated): whole-run time of the persistent launch (the library
+    default at this size), of the multi-launch path with eager launches, and
+    of the multi-launch path with per-tick graph replays; the first tick is
+    not timed (it captures the graph)."""
+    import numpy as np
     from paper_2105_09688_amd import workloads as W
     from paper_2105_09688_amd.ssm import SSM
     w = W.small_parity()
     out = {"study": "small", "workload": "10 ensembles x N=1000, d=1, h=2^-8, 256 steps"}
+    modes = (("persistent", dict(persistent=1)), ("eager", dict(persistent=-1)),
+             ("graphs", dict(persistent=-1, graphs=True)))
     for prec in ("fp64", "fp32_kahan"):
-        for graphs in (False, True):
-            # the first tick (which captures the graph) is not timed
-            s, dt, n = timed_run(SSM, w, prec, stream, steps=255, profile=False, graphs=graphs,
-                                 setup=lambda c: c.step(1))
+        finals = {}
+        for name, kw in modes:
+            s, dt, n = timed_run(SSM, w, prec, stream, steps=255, profile=False, setup=lambda c: c.step(1), **kw)
+            finals[name] = s.states()
             s.close()
-            out[f"{prec} {'graphs' if graphs else 'eager'}"] = {
-                "seconds": dt, "particle_steps_per_s": 10 * 1000 * n / dt, "us_per_step": dt / n * 1e6}
+            out[f"{prec} {name}"] = {"seconds": dt, "particle_steps_per_s": 10 * 1000 * n / dt,
+                                     "us_per_step": dt / n * 1e6}
+        # the two paths differ by summation order only
+        out[f"{prec} persistent vs eager, max pathwise difference"] = max(
+            float(np.max(np.abs(a - b) / np.maximum(1.0, np.abs(b))))
+            for a, b in zip(finals["persistent"], finals["eager"]))
     return out
 
 

@@ -166,11 +166,13 @@ typedef struct {
      * further steps.  Results differ from the multi-launch path by
      * summation order only (ordered pairs, per-tile sums of the measures).
      *   0: on when eligible, the systems total at most one tile of 64
-     *      particles per compute unit (where the multi-launch tick is bound
-     *      by launch latency) and no tiling of the multi-launch pair kernels
-     *      (targets_per_lane, sources_per_item, pair_scheme,
-     *      jside_band_groups) is given;  1: on whenever eligible (ssm_init
-     *      fails if the configuration never is);  -1: off. */
+     *      particles per compute unit, a cost estimate of the two paths (from
+     *      MI355X measurements) favours it (the multi-launch tick is bound by
+     *      launch latency for small systems, while a persistent tile sums its
+     *      particles' pairs on one compute unit), and no tiling of the
+     *      multi-launch pair kernels (targets_per_lane, sources_per_item,
+     *      pair_scheme, jside_band_groups) is given;  1: on whenever
+     *      eligible (ssm_init fails if the configuration never is);  -1: off. */
     int32_t persistent;
 } ssm_config;
 

@@ -888,6 +888,33 @@ static int device_cus()
     return cus;
 }
 
+// The default's choice between the two paths: estimated tick times in
+// microseconds, coefficients from MI355X measurements.  Persistent: a fixed
+// latency (staging, update, the barrier) plus the ordered pairs of the
+// largest system's tile, 64 targets x N sources on one compute unit (64
+// lane-slots per clock at 2.4 GHz, about 77 % issued), at 3d + 2 issue slots
+// per pair (FP64: 16 more for its exponential).  Multi-launch: three
+// dependent launches plus the symmetric pair sums over the whole chip
+// (3.93e13 lane-slots/s, about 90 % issued), 2d + 1 slots per unordered pair
+// (FP64: about 2d + 20).  Small case, FP32: 9.2 against 17.4 (measured 8.9
+// and 18.2); FP64: 19.4 against 33 (18.8 and 31.7).
+static bool small_preferred(const ssm_ctx* c)
+{
+    const bool f64 = c->prec == SSM_FP64;
+    const double d = (double)c->d;
+    double maxN = 0.0, sumN2 = 0.0;
+    for (auto& S : c->sys) {
+        maxN = std::max(maxN, (double)S.N);
+        sumN2 += (double)S.N * (double)S.N;
+    }
+    double pers = f64 ? 8.0 : 6.5, multi = f64 ? 30.0 : 17.0;
+    if (c->has_pair) {
+        pers += maxN * (3.0 * d + 2.0 + (f64 ? 16.0 : 0.0)) / 1850.0;
+        multi += 0.5 * sumN2 * (f64 ? 2.0 * d + 20.0 : 2.0 * d + 1.0) / 3.5e7;
+    }
+    return pers < multi;
+}
+
 static bool small_usable(const ssm_ctx* c)
 {
     return c->small_ok && c->surr_check_every == 0 && !c->profiling && !c->use_graphs;
@@ -1195,12 +1222,13 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
         for (auto& S : c->sys) ntiles += (S.N + kSmallTile - 1) / kSmallTile;
         const std::string why = small_ineligible(c, ntiles);
         if (cfg->persistent == 1 && !why.empty()) { free_ctx(c); return fail(SSM_ERR_INVALID, "persistent = 1: " + why); }
-        // default: where the multi-launch tick is bound by launch latency
-        // (at most one tile per compute unit), unless a tiling of the
-        // multi-launch pair kernels was asked for
+        // default: at most one tile per compute unit, where the estimate
+        // says the multi-launch tick is slower (bound by launch latency),
+        // unless a tiling of the multi-launch pair kernels was asked for
         const bool tiled = cfg->targets_per_lane != 0 || cfg->sources_per_item != 0 || cfg->pair_scheme != 0 ||
                            cfg->jside_band_groups != 0;
-        c->small_ok = why.empty() && (cfg->persistent == 1 || (!tiled && ntiles <= device_cus()));
+        c->small_ok = why.empty() &&
+                      (cfg->persistent == 1 || (!tiled && ntiles <= device_cus() && small_preferred(c)));
         if (c->small_ok) {
             for (int s = 0; s < (int)c->sys.size(); ++s) {
                 const int32_t nt = (int32_t)((c->sys[s].N + kSmallTile - 1) / kSmallTile);

@@ -220,13 +220,14 @@ __device__ __forceinline__ void small_brownian(const SysDev& S, const Coef& cf, 
 }
 
 // Implicit step (2.3) of one particle (wavefront 0 of the tile), as
-// solve_and_store; the tile's Y* sums go to sumY_out[k][gt].
+// solve_and_store; the tile's Y* sums go to sumY_out[k][gt], the stored Y*
+// (as double) to yout, and the wavefront's largest Newton count into nrun.
 template <typename T, int D>
 __device__ __forceinline__ void small_solve(const SysDev& S, const Coef& cf, bool valid, const double (&x)[kMaxD],
                                             const double (&xbar)[kMaxD], double m2, int64_t slot, int64_t P,
                                             T* __restrict__ Y, T* __restrict__ Ys, double* __restrict__ sumY_out,
-                                            int64_t ntile_tot, int64_t gt, int64_t nslot, Flags* flags,
-                                            int32_t* __restrict__ nmax)
+                                            int64_t ntile_tot, int64_t gt, Flags* flags, int& nrun,
+                                            double (&yout)[kMaxD])
 {
     double w[D], y[D];
 #pragma unroll
@@ -261,9 +262,8 @@ __device__ __forceinline__ void small_solve(const SysDev& S, const Coef& cf, boo
     if ((threadIdx.x & 63) == 0) {
         if (fails) atomicAdd(&flags->newton_fail, (int)__popcll(fails));
         if (bad) atomicAdd(&flags->nonfinite, (int)__popcll(bad));
-        int32_t* sl = nmax + nslot;
-        if (itmax > *sl) *sl = itmax;
     }
+    nrun = max(nrun, itmax);
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         const T yt = (T)y[k];
@@ -271,7 +271,8 @@ __device__ __forceinline__ void small_solve(const SysDev& S, const Coef& cf, boo
             Y[k * P + slot] = yt;
             Ys[k * P + slot] = (T)(cf.coord_scale * (double)yt);
         }
-        const double s = wave_sum(valid ? (double)yt : 0.0);
+        yout[k] = valid ? (double)yt : 0.0;
+        const double s = wave_sum(yout[k]);
         if ((threadIdx.x & 63) == 0) sumY_out[(int64_t)k * ntile_tot + gt] = s;
     }
 }
@@ -321,6 +322,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs<T> a)
     const int64_t gt = tl.gtile + tl.tile;    // global tile
     const int64_t nslot = (int64_t)(S.blk0 + tl.tile / kSlotsPerBlk) * kSlotsPerBlk + tl.tile % kSlotsPerBlk;
     const int64_t row = small_row(S.N);
+    // wavefront 0 keeps its particles' Y* and its largest Newton count in
+    // registers for the whole launch (the slot is stored at the end)
+    double yv[kMaxD] = {0.0, 0.0, 0.0, 0.0};
+    int nrun = 0;
+    if (wave == 0) nrun = a.nmax[nslot];
     uint64_t* ctr = a.bar + (int64_t)tl.sys * kBarLine;
     uint64_t epoch = a.epoch0;
     const uint64_t members = (uint64_t)tl.ntile;
@@ -367,13 +373,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs<T> a)
                 for (int k = 0; k < D; ++k) x[k] = (double)a.X[k * a.P + slot];
             }
             small_solve<T, D>(S, cf, valid, x, xbar, m2, slot, a.P, a.Y, a.Ys,
-                              a.sumY + (int64_t)(a.t0 & 1) * D * a.ntile_tot, a.ntile_tot, gt, nslot, a.flags, a.nmax);
+                              a.sumY + (int64_t)(a.t0 & 1) * D * a.ntile_tot, a.ntile_tot, gt, a.flags, nrun, yv);
         }
     } else if (wave == 0) {
         const int par = (int)(a.t0 & 1);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const double s = wave_sum(valid ? (double)a.Y[k * a.P + slot] : 0.0);
+            yv[k] = valid ? (double)a.Y[k * a.P + slot] : 0.0;
+            const double s = wave_sum(yv[k]);
             if (lane == 0) a.sumY[((int64_t)par * D + k) * a.ntile_tot + gt] = s;
         }
     }
@@ -405,13 +412,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs<T> a)
                 }
             }
         }
-        double yv[kMaxD] = {0.0, 0.0, 0.0, 0.0};
         double ypart[kMaxD] = {0.0, 0.0, 0.0, 0.0};
         if (wave == 0) {
-            if (valid) {
-#pragma unroll
-                for (int k = 0; k < D; ++k) yv[k] = (double)a.Y[k * a.P + slot];
-            }
             if (a.needs_ybar) {
                 const double* sy = a.sumY + (int64_t)par * D * a.ntile_tot + tl.gtile;
 #pragma unroll
@@ -471,8 +473,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs<T> a)
             if (cf.fused) {
                 const double zero[kMaxD] = {0.0, 0.0, 0.0, 0.0};
                 small_solve<T, D>(S, cf, valid, xn, zero, 0.0, slot, a.P, a.Y, a.Ys,
-                                  a.sumY + (int64_t)(par ^ 1) * D * a.ntile_tot, a.ntile_tot, gt, nslot, a.flags,
-                                  a.nmax);
+                                  a.sumY + (int64_t)(par ^ 1) * D * a.ntile_tot, a.ntile_tot, gt, a.flags, nrun, yv);
             } else {
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
@@ -503,11 +504,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs<T> a)
                     for (int k = 0; k < D; ++k) x[k] = (double)a.X[k * a.P + slot];
                 }
                 small_solve<T, D>(S, cf, valid, x, xbar, m2, slot, a.P, a.Y, a.Ys,
-                                  a.sumY + (int64_t)(par ^ 1) * D * a.ntile_tot, a.ntile_tot, gt, nslot, a.flags,
-                                  a.nmax);
+                                  a.sumY + (int64_t)(par ^ 1) * D * a.ntile_tot, a.ntile_tot, gt, a.flags, nrun, yv);
             }
         }
-        if (last) break;  // the end of the launch orders the last tick
+        if (last) {
+            // the end of the launch orders the last tick
+            if (wave == 0 && lane == 0) a.nmax[nslot] = nrun;
+            break;
+        }
         // the next tick's increments are drawn while the other tiles arrive
         small_arrive(ctr);
         small_draw<D, F32>(a.bm_lanes, S, cf, tile0, t + 1, dw);
