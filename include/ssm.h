@@ -154,10 +154,11 @@ typedef struct {
      * system, stages the system's positions in LDS, sums the interaction
      * over every ordered pair of its particles, draws their increments and
      * updates them; the workgroups of a system then wait at that system's
-     * barrier (one per tick, two when v depends on mu^X).  Needs a single
-     * step size (h equal for all systems), d x N (rounded up to 4) elements
-     * of the precision within 32 KiB per system, the compensated-sum default
-     * (kahan_span = 0) and co-resident workgroups for every 64 particles.
+     * barrier (one per tick, two when v depends on mu^X; a system steps on
+     * its own ticks and draws its own increments).  Needs d x N (rounded up
+     * to 4) elements of the precision within 32 KiB per system, the
+     * compensated-sum default (kahan_span = 0) and co-resident workgroups for
+     * every 64 particles.
      * Ticks with the surrogate enabled, with profiling or with graphs run the
      * multi-launch path.  Every barrier wait is bounded (4 s; the environment
      * variable SSM_PERSISTENT_WAIT_US, read by ssm_init, sets another limit

@@ -321,7 +321,8 @@ struct ssm_ctx {
     uint64_t small_epoch = 0;       // barriers every system has passed
     int64_t small_wait_limit = 0;   // wall-clock counts a barrier wait may take
     int64_t small_launches = 0, small_ticks = 0;
-    bool psum_stale = false;        // the block sums psumY lag Y* (after persistent ticks)
+    int small_lanes = 1;            // lanes per particle of the persistent draws (every system draws its own)
+    bool psum_stale = false;        // after persistent ticks: psumY and the current window lag
     bool broken = false;            // a persistent run was aborted
 };
 
@@ -614,6 +615,28 @@ static ssm_status launch_surrogate(ssm_ctx* c, int64_t ph)
     return SSM_OK;
 }
 
+// The path groups' Brownian windows for ticks t0 .. t0 + max_stride - 1
+// (t0 = *tdev when tdev is given).
+template <typename T>
+static ssm_status launch_window(ssm_ctx* c, int64_t t0, const int64_t* tdev)
+{
+    const int d = c->d;
+    const dim3 gw((unsigned)(c->win_items * c->win_lanes), (unsigned)c->max_stride);
+#define SSM_WIN(LPV)                                                                                                   \
+    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_bm_window<D, LPV, (sizeof(T) == 4)>), gw, dim3(kBlk), 0, c->stream,      \
+                                         c->dwin_items, c->dsys, c->coef, c->r_min, t0, tdev, c->win))
+    switch (c->win_lanes) {
+        case 16: SSM_WIN(16); break;
+        case 8: SSM_WIN(8); break;
+        case 4: SSM_WIN(4); break;
+        case 2: SSM_WIN(2); break;
+        default: SSM_WIN(1); break;
+    }
+#undef SSM_WIN
+    HIP_TRY(hipGetLastError());
+    return SSM_OK;
+}
+
 template <typename T>
 static ssm_status launch_tick(ssm_ctx* c, bool capture)
 {
@@ -632,20 +655,8 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
     const bool run_surr = surr_on && (check || !c->surr_fallback);
     const bool prof = c->profiling && c->tick % c->profile_every == 0;
     if (ph == 0 && c->win_items > 0 && nb > 0) {
-        // the path groups' Brownian windows for ticks tick .. tick + max_stride - 1
-        const dim3 gw((unsigned)(c->win_items * c->win_lanes), (unsigned)c->max_stride);
-#define SSM_WIN(LPV)                                                                                                   \
-    SSM_DISPATCH_D(d, hipLaunchKernelGGL((k_bm_window<D, LPV, (sizeof(T) == 4)>), gw, dim3(kBlk), 0, c->stream,      \
-                                         c->dwin_items, c->dsys, c->coef, c->r_min, c->tick, tdev, c->win))
-        switch (c->win_lanes) {
-            case 16: SSM_WIN(16); break;
-            case 8: SSM_WIN(8); break;
-            case 4: SSM_WIN(4); break;
-            case 2: SSM_WIN(2); break;
-            default: SSM_WIN(1); break;
-        }
-#undef SSM_WIN
-        HIP_TRY(hipGetLastError());
+        ssm_status st = launch_window<T>(c, c->tick, tdev);
+        if (st != SSM_OK) return st;
     }
     if (c->has_pair && np > 0 && run_exact) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -854,12 +865,11 @@ static const void* small_kernel(int prec, int d)
 #undef SSM_SMALL_K
 }
 
-// Why a context can never run persistent ticks ("" if it can): one step size,
-// the default compensation, each system's staged positions within the LDS
-// budget, and every tile's workgroup co-resident with the others.
+// Why a context can never run persistent ticks ("" if it can): the default
+// compensation, each system's staged positions within the LDS budget, and
+// every tile's workgroup co-resident with the others.
 static std::string small_ineligible(const ssm_ctx* c, int64_t tiles)
 {
-    if (c->max_stride != 1) return "several step sizes (h / h_min > 1)";
     if (c->kpair) return "kahan_span = 1";
     for (auto& S : c->sys)
         if ((int64_t)c->d * small_row(S.N) * (int64_t)elt(c->prec) > kSmallLdsBytes)
@@ -902,10 +912,10 @@ static bool small_preferred(const ssm_ctx* c)
 {
     const bool f64 = c->prec == SSM_FP64;
     const double d = (double)c->d;
-    double maxN = 0.0, sumN2 = 0.0;
+    double maxN = 0.0, sumN2 = 0.0;  // pairs per tick: each system steps every stride ticks
     for (auto& S : c->sys) {
         maxN = std::max(maxN, (double)S.N);
-        sumN2 += (double)S.N * (double)S.N;
+        sumN2 += (double)S.N * (double)S.N / (double)S.stride;
     }
     double pers = f64 ? 8.0 : 6.5, multi = f64 ? 30.0 : 17.0;
     if (c->has_pair) {
@@ -941,7 +951,7 @@ static ssm_status launch_small(ssm_ctx* c, int64_t n)
     a.epoch0 = c->small_epoch;
     a.flags = c->dflags;
     a.nmax = c->dnmax;
-    a.bm_lanes = c->bm_lanes;
+    a.bm_lanes = c->small_lanes;
     a.needs_ybar = c->needs_ybar ? 1 : 0;
     a.wait_limit = c->small_wait_limit;
     void* args[] = {&a};
@@ -956,13 +966,22 @@ static ssm_status launch_small(ssm_ctx* c, int64_t n)
     return SSM_OK;
 }
 
-// The block sums of Y* that the multi-launch path reads, after persistent
-// ticks (which keep tile sums of their own).
-static ssm_status refresh_ysums(ssm_ctx* c)
+// What the multi-launch path reads from earlier ticks, after persistent ticks
+// (which keep tile sums of their own and draw their increments directly): the
+// block sums of Y*, and, in the middle of a window of path groups, the
+// window's normal sums.
+template <typename T>
+static ssm_status refresh_after_small(ssm_ctx* c)
 {
+    const int64_t ph = c->tick % c->max_stride;
+    if (ph != 0 && c->win_items > 0) {
+        ssm_status st = launch_window<T>(c, c->tick - ph, nullptr);
+        if (st != SSM_OK) return st;
+    }
     const BlkItem* items = c->dblk + c->all_blk_off[0];
     const dim3 g((unsigned)c->all_blk_cnt);
-    const int64_t tick_arg = c->tick - 1;  // one step size: tick = steps done
+    // k_ysums takes the steps done from the tick before: (tick - 1) / stride + 1
+    const int64_t tick_arg = c->tick - 1;
     if (c->prec == SSM_FP64) {
         SSM_DISPATCH_D(c->d, hipLaunchKernelGGL((k_ysums<double, D>), g, dim3(kBlk), 0, c->stream, items, c->dsys,
                                                 c->P, tick_arg, (const double*)c->Y, c->psumY, c->nblk_tot));
@@ -1236,6 +1255,9 @@ extern "C" ssm_status ssm_init(const ssm_config* cfg, ssm_ctx** out)
                 for (int32_t q = 0; q < nt; ++q) tiles.push_back(SmallTile{s, q, g0, nt});
             }
             c->small_grid = (int64_t)tiles.size();
+            int64_t bmax = 1;
+            for (auto& S : c->sys) bmax = std::max<int64_t>(bmax, (S.r * c->d + 3) / 4);
+            c->small_lanes = bmax >= 16 ? 16 : bmax >= 8 ? 8 : bmax >= 4 ? 4 : bmax >= 2 ? 2 : 1;
             int dev = 0, khz = 0;
             if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) {
                 (void)hipGetLastError();
@@ -1381,7 +1403,7 @@ extern "C" ssm_status ssm_step(ssm_ctx* c, int64_t n_ticks)
     if (n_ticks == 0) return SSM_OK;
     if (small_usable(c)) return (c->prec == SSM_FP64) ? launch_small<double>(c, n_ticks) : launch_small<float>(c, n_ticks);
     if (c->psum_stale) {
-        ssm_status st = refresh_ysums(c);
+        ssm_status st = (c->prec == SSM_FP64) ? refresh_after_small<double>(c) : refresh_after_small<float>(c);
         if (st != SSM_OK) return st;
     }
     for (int64_t t = 0; t < n_ticks; ++t) {

@@ -18,7 +18,9 @@
 // When v depends on mu^X the update and the implicit step are separated by a
 // second barrier (the moments of the new X are needed first).  The means of
 // mu^Y and mu^X are the tile sums added in ascending tile order.  Systems are
-// independent: each waits only for its own tiles.
+// independent: each waits only for its own tiles.  A system steps on the
+// ticks t with t % stride == 0 and draws its own increments (no shared
+// windows); on its other ticks its workgroups only take part in the barriers.
 //
 // Every barrier wait is bounded in wall-clock time; a wait that runs out sets
 // the abort flag, every workgroup leaves at its next barrier, and the host
@@ -62,7 +64,7 @@ struct SmallArgs {
     uint64_t epoch0;         // barriers every system has passed before this launch
     Flags* flags;
     int32_t* nmax;
-    int bm_lanes;            // lanes per particle of the Brownian sums (as the multi-launch path)
+    int bm_lanes;            // lanes per particle of the Brownian sums (each system draws its own)
     int needs_ybar;
     int64_t wait_limit;      // wall-clock counts a barrier wait may take
 };
@@ -334,6 +336,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs<T> a)
     const int Ls = (int)((((int64_t)S.N + kSmallWaves - 1) / kSmallWaves + 3) & ~3);
     const int j0 = min(S.N, wave * Ls), j1 = min(S.N, (wave + 1) * Ls);
 
+    // The system steps on ticks t with t % stride == 0, as step t / stride;
+    // its tile sums of Y* alternate between two slots by the parity of the
+    // step (par0: the slot its first step in this launch reads).
+    const int par0 = (int)(((a.t0 + S.stride - 1) / S.stride) & 1);
+
     // Y* of the first tick and its tile sums.  When v depends on mu^X, Y* is
     // solved again here at the tile sums' moments of X, so that a run split
     // over several launches (or resumed from a saved state) takes the same
@@ -373,10 +380,10 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs<T> a)
                 for (int k = 0; k < D; ++k) x[k] = (double)a.X[k * a.P + slot];
             }
             small_solve<T, D>(S, cf, valid, x, xbar, m2, slot, a.P, a.Y, a.Ys,
-                              a.sumY + (int64_t)(a.t0 & 1) * D * a.ntile_tot, a.ntile_tot, gt, a.flags, nrun, yv);
+                              a.sumY + (int64_t)par0 * D * a.ntile_tot, a.ntile_tot, gt, a.flags, nrun, yv);
         }
     } else if (wave == 0) {
-        const int par = (int)(a.t0 & 1);
+        const int par = par0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             yv[k] = valid ? (double)a.Y[k * a.P + slot] : 0.0;
@@ -386,102 +393,107 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs<T> a)
     }
     // the first tick's increments are drawn while the other tiles arrive
     small_arrive(ctr);
-    small_draw<D, F32>(a.bm_lanes, S, cf, tile0, a.t0, dw);
+    if (a.t0 % S.stride == 0) small_draw<D, F32>(a.bm_lanes, S, cf, tile0, a.t0, dw);
     if (!small_wait(ctr, members * ++epoch, a.flags, a.wait_limit, &ok_lds)) return;
 
     for (int64_t t = a.t0; t < a.t0 + a.n; ++t) {
-        const int par = (int)(t & 1);
-        // 1. stage the system's scaled positions (loads issued four at a time);
-        //    wavefront 0 also loads its particles' Y* and its share of the tile
-        //    sums of mu^Y
-        if (cf.has_pair) {
-            const int64_t tot = (int64_t)D * row;
-            for (int64_t q0 = threadIdx.x; q0 < tot; q0 += 4 * kSmallThreads) {
-                T v[4];
+        // every system takes part in every barrier; one that does not step
+        // on this tick only waits
+        const bool stepping = t % S.stride == 0;
+        const int par = (int)((t / S.stride) & 1);
+        if (stepping) {
+            // 1. stage the system's scaled positions (loads issued four at a time);
+            //    wavefront 0 also loads its particles' Y* and its share of the tile
+            //    sums of mu^Y
+            if (cf.has_pair) {
+                const int64_t tot = (int64_t)D * row;
+                for (int64_t q0 = threadIdx.x; q0 < tot; q0 += 4 * kSmallThreads) {
+                    T v[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int64_t q = q0 + (int64_t)u * kSmallThreads;
-                    const int c = (int)(q / row);
-                    const int j = (int)(q - (int64_t)c * row);
-                    v[u] = (q < tot && j < S.N) ? a.Ys[c * a.P + S.off + j] : (T)0;
-                }
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t q = q0 + (int64_t)u * kSmallThreads;
+                        const int c = (int)(q / row);
+                        const int j = (int)(q - (int64_t)c * row);
+                        v[u] = (q < tot && j < S.N) ? a.Ys[c * a.P + S.off + j] : (T)0;
+                    }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int64_t q = q0 + (int64_t)u * kSmallThreads;
-                    if (q < tot) src[q] = v[u];
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t q = q0 + (int64_t)u * kSmallThreads;
+                        if (q < tot) src[q] = v[u];
+                    }
                 }
             }
-        }
-        double ypart[kMaxD] = {0.0, 0.0, 0.0, 0.0};
-        if (wave == 0) {
-            if (a.needs_ybar) {
-                const double* sy = a.sumY + (int64_t)par * D * a.ntile_tot + tl.gtile;
+            double ypart[kMaxD] = {0.0, 0.0, 0.0, 0.0};
+            if (wave == 0) {
+                if (a.needs_ybar) {
+                    const double* sy = a.sumY + (int64_t)par * D * a.ntile_tot + tl.gtile;
 #pragma unroll
-                for (int k = 0; k < D; ++k)
-                    for (int q = lane; q < tl.ntile; q += 64) ypart[k] += sy[(int64_t)k * a.ntile_tot + q];
+                    for (int k = 0; k < D; ++k)
+                        for (int q = lane; q < tl.ntile; q += 64) ypart[k] += sy[(int64_t)k * a.ntile_tot + q];
+                }
             }
-        }
-        __syncthreads();
-        // 2. ordered-pair sums of the tile's targets over the wavefront's source range
-        if (cf.has_pair) {
-            T yi[D], ps[D];
-#pragma unroll
-            for (int c = 0; c < D; ++c) yi[c] = valid ? src[c * row + i] : (T)0;
-            small_pairs<T, D, KAHAN>(src, row, j0, j1, yi, ps);
-#pragma unroll
-            for (int c = 0; c < D; ++c) part[wave][c][lane] = ps[c];
             __syncthreads();
-        }
-        // 3. update (2.4) and the next implicit step, wavefront 0
-        if (wave == 0) {
-            double ybar[kMaxD] = {0.0, 0.0, 0.0, 0.0};
-            if (a.needs_ybar) {
+            // 2. ordered-pair sums of the tile's targets over the wavefront's source range
+            if (cf.has_pair) {
+                T yi[D], ps[D];
 #pragma unroll
-                for (int k = 0; k < D; ++k) ybar[k] = wave_sum(ypart[k]) / (double)S.N;
+                for (int c = 0; c < D; ++c) yi[c] = valid ? src[c * row + i] : (T)0;
+                small_pairs<T, D, KAHAN>(src, row, j0, j1, yi, ps);
+#pragma unroll
+                for (int c = 0; c < D; ++c) part[wave][c][lane] = ps[c];
+                __syncthreads();
             }
-            double xn[kMaxD] = {0.0, 0.0, 0.0, 0.0};
-            if (valid) {
+            // 3. update (2.4) and the next implicit step, wavefront 0
+            if (wave == 0) {
+                double ybar[kMaxD] = {0.0, 0.0, 0.0, 0.0};
+                if (a.needs_ybar) {
+#pragma unroll
+                    for (int k = 0; k < D; ++k) ybar[k] = wave_sum(ypart[k]) / (double)S.N;
+                }
+                double xn[kMaxD] = {0.0, 0.0, 0.0, 0.0};
+                if (valid) {
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const double y = yv[k];
+                        double pair = 0.0;
+                        if (cf.has_pair) {
+                            double tot = 0.0;
+#pragma unroll
+                            for (int w = 0; w < kSmallWaves; ++w) tot += (double)part[w][k][lane];
+                            pair = tot * S.pair_scale;
+                        }
+                        double b = cf.b_c0 * y + cf.b_lam * ybar[k] + pair;
+                        if (cf.has_lin) {
+                            b += cf.b_const[k];
+#pragma unroll
+                            for (int l = 0; l < D; ++l) b += cf.b_mat[k * kMaxD + l] * yv[l];
+                            b += cf.b_mean[k] * ybar[k];
+                        }
+                        const double sig = cf.s0[k] + cf.s1[k] * y + cf.s2[k] * ybar[k];
+                        xn[k] = (y + S.h * b) + sig * dw[k][lane];
+                    }
+                }
+                double n2 = 0.0;
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    const double y = yv[k];
-                    double pair = 0.0;
-                    if (cf.has_pair) {
-                        double tot = 0.0;
-#pragma unroll
-                        for (int w = 0; w < kSmallWaves; ++w) tot += (double)part[w][k][lane];
-                        pair = tot * S.pair_scale;
-                    }
-                    double b = cf.b_c0 * y + cf.b_lam * ybar[k] + pair;
-                    if (cf.has_lin) {
-                        b += cf.b_const[k];
-#pragma unroll
-                        for (int l = 0; l < D; ++l) b += cf.b_mat[k * kMaxD + l] * yv[l];
-                        b += cf.b_mean[k] * ybar[k];
-                    }
-                    const double sig = cf.s0[k] + cf.s1[k] * y + cf.s2[k] * ybar[k];
-                    xn[k] = (y + S.h * b) + sig * dw[k][lane];
+                    const T xs = (T)xn[k];
+                    if (valid) a.X[k * a.P + slot] = xs;
+                    xn[k] = (double)xs;
+                    n2 += xn[k] * xn[k];
                 }
-            }
-            double n2 = 0.0;
+                if (cf.fused) {
+                    const double zero[kMaxD] = {0.0, 0.0, 0.0, 0.0};
+                    small_solve<T, D>(S, cf, valid, xn, zero, 0.0, slot, a.P, a.Y, a.Ys,
+                                      a.sumY + (int64_t)(par ^ 1) * D * a.ntile_tot, a.ntile_tot, gt, a.flags, nrun, yv);
+                } else {
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const T xs = (T)xn[k];
-                if (valid) a.X[k * a.P + slot] = xs;
-                xn[k] = (double)xs;
-                n2 += xn[k] * xn[k];
-            }
-            if (cf.fused) {
-                const double zero[kMaxD] = {0.0, 0.0, 0.0, 0.0};
-                small_solve<T, D>(S, cf, valid, xn, zero, 0.0, slot, a.P, a.Y, a.Ys,
-                                  a.sumY + (int64_t)(par ^ 1) * D * a.ntile_tot, a.ntile_tot, gt, a.flags, nrun, yv);
-            } else {
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const double s = wave_sum(valid ? xn[k] : 0.0);
-                    if (lane == 0) a.sumX[(int64_t)k * a.ntile_tot + gt] = s;
+                    for (int k = 0; k < D; ++k) {
+                        const double s = wave_sum(valid ? xn[k] : 0.0);
+                        if (lane == 0) a.sumX[(int64_t)k * a.ntile_tot + gt] = s;
+                    }
+                    const double s2 = wave_sum(valid ? n2 : 0.0);
+                    if (lane == 0) a.sumX[(int64_t)D * a.ntile_tot + gt] = s2;
                 }
-                const double s2 = wave_sum(valid ? n2 : 0.0);
-                if (lane == 0) a.sumX[(int64_t)D * a.ntile_tot + gt] = s2;
             }
         }
         const bool last = t + 1 == a.t0 + a.n;
@@ -489,7 +501,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs<T> a)
             // the implicit step at mu^X of the new cloud
             small_arrive(ctr);
             if (!small_wait(ctr, members * ++epoch, a.flags, a.wait_limit, &ok_lds)) return;
-            if (wave == 0) {
+            if (stepping && wave == 0) {
                 double xbar[kMaxD] = {0.0, 0.0, 0.0, 0.0};
                 double m2 = 0.0;
                 if (cf.v_lam != 0.0) {
@@ -514,7 +526,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(SmallArgs<T> a)
         }
         // the next tick's increments are drawn while the other tiles arrive
         small_arrive(ctr);
-        small_draw<D, F32>(a.bm_lanes, S, cf, tile0, t + 1, dw);
+        if ((t + 1) % S.stride == 0) small_draw<D, F32>(a.bm_lanes, S, cf, tile0, t + 1, dw);
         if (!small_wait(ctr, members * ++epoch, a.flags, a.wait_limit, &ok_lds)) return;
     }
 }

@@ -613,7 +613,8 @@ def test_graph_replays_match_eager_bitwise(torch_cuda):
     sizes = [300, 1000, 65]
     w = W.batched(n_ens=3, levels=(4, 5, 6), h_fine=2.0 ** -8, sizes=sizes)
     w["T"] = 0.5
-    with _ssm(w, "fp32_kahan") as eager, _ssm(w, "fp32_kahan", graphs=True) as g:
+    # the multi-launch path both times (graph replays never run the persistent path)
+    with _ssm(w, "fp32_kahan", persistent=-1) as eager, _ssm(w, "fp32_kahan", graphs=True) as g:
         ticks = eager.info()["ticks_total"]
         for t in range(ticks):
             eager.step(1)

@@ -153,6 +153,49 @@ def test_split_launches_are_bitwise_one_launch(torch_cuda, family, precision):
         assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_kahan"])
+def test_several_step_sizes(torch_cuda, precision):
+    """A batch of ensembles of uneven N at three step sizes on one fine grid
+    (strides 1, 2, 4) and the polynomial family at three levels: each system
+    steps on its own ticks and draws its increments directly; against the
+    oracle, and against the multi-launch path (shared Brownian windows,
+    another association of the same sums)."""
+    cases = [W.batched(n_ens=3, levels=(5, 6, 7), h_fine=2.0 ** -9, sizes=[300, 1000, 65]),
+             W.polynomial_drift(n_ens=2, N=400, h_fine=2.0 ** -9, levels=(5, 6, 7))]
+    for w in cases:
+        w["T"] = 0.25
+        ref = oracle.run(w)
+        got, info = _run(w, precision, persistent=1)
+        assert info["persistent_ticks"] == 32
+        multi, _ = _run(w, precision, persistent=-1)
+        e_or = max(_err(g, r) for g, r in zip(got, ref))
+        e_ml = max(_err(g, m) for g, m in zip(got, multi))
+        _say(f"several h {precision}: vs oracle {e_or:.3e}, vs multi-launch {e_ml:.3e}")
+        assert e_or <= TOL[precision]
+        assert e_ml <= (1e-13 if precision == "fp64" else 1e-5)
+
+
+def test_switch_to_multi_launch_inside_a_window(torch_cuda):
+    """Strides 1, 2, 4 with shared windows: persistent ticks end in the middle
+    of a window, profiled (multi-launch) ticks continue (the window of the
+    current period is drawn first), then persistent ticks again."""
+    w = W.batched(n_ens=2, levels=(5, 6, 7), h_fine=2.0 ** -9, sizes=[300, 129])
+    w["T"] = 0.25
+    ref = oracle.run(w)
+    with _ssm(w, "fp64", persistent=1) as s:
+        s.step(5)
+        s.profile(True, every=1)
+        s.step(6)
+        s.profile(False)
+        s.run()
+        got = s.states()
+        info = s.info()
+    assert info["persistent_launches"] == 2 and info["persistent_ticks"] == 26
+    err = max(_err(g, r) for g, r in zip(got, ref))
+    _say(f"window switch: {err:.3e}")
+    assert err <= FP64_TOL
+
+
 def test_mixed_with_multi_launch_ticks(torch_cuda, small_case):
     """Persistent ticks, then profiled ticks (the multi-launch path, whose
     block sums of Y* are refreshed first), then persistent ticks again: the
@@ -191,12 +234,12 @@ def test_brownian_increments_bitwise_as_multi_launch(torch_cuda):
 
 
 def test_required_mode_is_refused_where_ineligible(torch_cuda):
-    """persistent = 1 fails at init for several step sizes and for a system
-    whose positions exceed the LDS budget; persistent = 0 then falls back."""
+    """persistent = 1 fails at init for a system whose positions exceed the
+    LDS budget and for the per-pair compensated study variant; persistent = 0
+    then falls back."""
     from paper_2105_09688_amd import SSMError
-    two_h = W.batched(n_ens=1, levels=(6, 7), h_fine=2.0 ** -8, sizes=[300])
-    with pytest.raises(SSMError, match="step sizes"):
-        _ssm(two_h, "fp64", persistent=1)
+    with pytest.raises(SSMError, match="kahan_span"):
+        _ssm(W.small_parity(n_ens=1, N=300), "fp32_kahan", persistent=1, kahan_span=1)
     big = W.small_parity(n_ens=1, N=8192, h=2.0 ** -6, h_fine=2.0 ** -8)
     with pytest.raises(SSMError, match="KiB"):
         _ssm(big, "fp64", persistent=1)
