@@ -78,10 +78,16 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // Split-phase barrier of the `members` workgroups of one system.  Arrive:
-// after every wavefront's writes, one release increment of the system's
-// counter.  Wait: until the counter reaches members x epoch (acquire).  Work
-// between the two must not write what other workgroups read.  Wait returns
-// false (in every thread) when the run is being aborted.
+// one release increment of the system's counter by thread 0.  Wait: until the
+// counter reaches members x epoch, then an acquire fence by thread 0 (it
+// invalidates the compute unit's caches for every wavefront) and a workgroup
+// barrier.  Work between the two must not write what other workgroups read.
+// Wait returns false (in every thread) when the run is being aborted.
+// The release covers the global writes of thread 0's own wavefront only (the
+// workgroup barrier before it waits for LDS traffic, not for other
+// wavefronts' stores): in k_small every global write that another workgroup
+// reads (Ys, Y*, X, the tile sums) is made by wavefront 0; the other
+// wavefronts write only LDS.
 __device__ __forceinline__ void small_arrive(uint64_t* ctr)
 {
     __syncthreads();
