@@ -42,3 +42,15 @@ def test_cpu_baseline_line_shape():
     out = bench.cpu_baseline(w, 0.0)
     assert out["kind"] == "oracle" and out["unit"] == "particle-steps/s"
     assert out["value"] > 0 and out["cores"] >= 1 and "1 full time steps" in out["sample"]
+
+
+def test_training_snapshots_are_dense_early():
+    """The surrogate's training states: every 2 ticks over the first 1/16 of
+    the run, every 8 up to 1/4, every 32 after; strictly increasing, inside
+    the run, 40 of them at the surrogate case's 512 ticks."""
+    import bench
+    s = bench.training_snapshots(512)
+    assert s[:3] == [0, 2, 4] and s[15:18] == [30, 32, 40] and s[27:30] == [120, 128, 160]
+    assert len(s) == 40 and s[-1] == 480
+    assert all(a < b for a, b in zip(s, s[1:])) and all(0 <= t < 512 for t in s)
+    assert bench.training_snapshots(16) == list(range(16))
