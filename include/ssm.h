@@ -164,7 +164,11 @@ typedef struct {
      * variable SSM_PERSISTENT_WAIT_US, read by ssm_init, sets another limit
      * in microseconds): a wait that runs out ends the launch in every
      * workgroup, ssm_sync returns SSM_ERR_HIP and the context refuses
-     * further steps.  Results differ from the multi-launch path by
+     * further steps.  Persistent launches of several contexts on different
+     * streams run side by side only while their workgroups fit the GPU
+     * together (one per compute unit for each); a launch whose workgroups
+     * cannot all start waits on the others and is aborted if that takes
+     * longer than the limit.  Results differ from the multi-launch path by
      * summation order only (ordered pairs, per-tile sums of the measures).
      *   0: on when eligible, the systems total at most one tile of 64
      *      particles per compute unit, a cost estimate of the two paths (from
