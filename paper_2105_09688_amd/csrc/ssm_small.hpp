@@ -69,12 +69,50 @@ struct SmallArgs {
     int64_t wait_limit;      // wall-clock counts a barrier wait may take
 };
 
-// Sum over the 64 lanes of a wavefront, fixed order; every lane gets it.
+// Lane permutations within each row of 16 lanes (gfx9 DPP controls):
+// exchange with lane ^ 1 and lane ^ 2 (quad_perm), mirror within 8 and 16.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double readlane64(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wavefront in a fixed order; every lane gets it.
+// Within each row of 16 lanes, four DPP steps (pairs, quads, eights,
+// sixteens) leave the row's sum in all its lanes; the four row sums are then
+// read and added as (row 0 + row 1) + (row 2 + row 3).  DPP instead of LDS
+// shuffles: this sum sits on the latency chain of the update.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp64<kDppXor1>(v);
+    v += dpp64<kDppXor2>(v);
+    v += dpp64<kDppHalfMirror>(v);
+    v += dpp64<kDppMirror>(v);
+    return (readlane64(v, 0) + readlane64(v, 16)) + (readlane64(v, 32) + readlane64(v, 48));
+}
+
+// Largest value over the lanes of a wavefront, the same way.
+__device__ __forceinline__ int wave_max(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppXor1, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppXor2, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppHalfMirror, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppMirror, 0xF, 0xF, false));
+    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // Split-phase barrier of the `members` workgroups of one system.  Arrive:
@@ -264,9 +302,7 @@ __device__ __forceinline__ void small_solve(const SysDev& S, const Coef& cf, boo
     }
     const uint64_t fails = __ballot(it < 0);
     const uint64_t bad = __ballot(nonfin);
-    int itmax = it;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) itmax = max(itmax, __shfl_xor(itmax, off, 64));
+    const int itmax = wave_max(it);
     if ((threadIdx.x & 63) == 0) {
         if (fails) atomicAdd(&flags->newton_fail, (int)__popcll(fails));
         if (bad) atomicAdd(&flags->nonfinite, (int)__popcll(bad));
