@@ -9,12 +9,12 @@
 //   2. sums the interaction over every ordered pair (i, j) of its targets,
 //      the 8 wavefronts taking 8 consecutive source ranges, the ranges'
 //      partial sums added in double in ascending order (the self term is 0);
-//   3. draws the tile's Brownian increments (the same stream sums as the
-//      multi-launch path: bitwise the same increments);
-//   4. applies the update (2.4) and the implicit step (2.3) of the next step,
-//      and writes the tile's sums of Y* (fixed-order wavefront tree);
-//   5. waits at its system's barrier (all tiles of the system), so that the
-//      next tick sees the whole new cloud.
+//   3. applies the update (2.4) and the implicit step (2.3) of the next step,
+//      and writes the tile's sums of Y* (fixed-order wavefront reduction);
+//   4. arrives at its system's barrier (all tiles of the system), draws the
+//      next tick's Brownian increments (the same stream sums as the
+//      multi-launch path draws for a system without a shared window), and
+//      waits, so that the next tick sees the whole new cloud.
 // When v depends on mu^X the update and the implicit step are separated by a
 // second barrier (the moments of the new X are needed first).  The means of
 // mu^Y and mu^X are the tile sums added in ascending tile order.  Systems are
@@ -58,7 +58,7 @@ struct SmallArgs {
     T* X;
     T* Y;
     T* Ys;
-    double* sumY;            // [2][D][ntile_tot]: tile sums of Y* at the start of tick t (slot t & 1)
+    double* sumY;            // [2][D][ntile_tot]: tile sums of Y* before step n of a system (slot n & 1)
     double* sumX;            // [D + 1][ntile_tot]: tile sums of the new X and |X|^2 (v depends on mu^X)
     uint64_t* bar;           // per system: counter at bar[s * kBarLine]
     uint64_t epoch0;         // barriers every system has passed before this launch
