@@ -249,6 +249,27 @@ def test_required_mode_is_refused_where_ineligible(torch_cuda):
         assert s.info()["persistent"] == 0  # an explicit pair tiling keeps the multi-launch path
 
 
+def test_default_choice_and_a_full_lds_system(torch_cuda):
+    """One system of N = 8192 (d = 1, FP32-compensated): its positions fill
+    the 32 KiB of LDS and it takes 128 tiles.  The default keeps it on the
+    multi-launch path (the estimate: 28.6 us persistent against 19.9 us, the
+    ordered pairs of a tile on one compute unit against the symmetric pairs
+    over the chip); persistent = 1 runs it, against the oracle.  The small
+    case takes the persistent path by default."""
+    w = W.small_parity(n_ens=1, N=8192, h=2.0 ** -6, h_fine=2.0 ** -8)
+    w["T"] = 4 * 2.0 ** -6
+    with _ssm(w, "fp32_kahan") as s:
+        assert s.info()["persistent"] == 0
+    ref = oracle.run(w)
+    got, info = _run(w, "fp32_kahan", persistent=1)
+    assert info["persistent_tiles"] == 128 and info["persistent_ticks"] == 4
+    err = _err(got[0], ref[0])
+    _say(f"N=8192 persistent: {err:.3e}")
+    assert err <= FP32_TOL
+    with _ssm(W.small_parity(), "fp64") as s:
+        assert s.info()["persistent"] == 1
+
+
 def test_barrier_timeout_aborts_cleanly(torch_cuda):
     """A barrier wait limit of zero, set from the host for one context
     (SSM_PERSISTENT_WAIT_US=0 at ssm_init): the first wait that is not
