@@ -20,6 +20,7 @@
 using namespace ssm;
 
 static constexpr int kRedBlocks = 256;  // blocks of the fixed-order moment / rMSE reductions
+static constexpr int64_t kSmallTicksPerLaunch = 4096;  // ticks per persistent launch, at most
 static constexpr double kLog2e = 1.4426950408889634073599246810018921;  // log2(e)
 
 // ---------------------------------------------------------------------------
@@ -1401,7 +1402,18 @@ extern "C" ssm_status ssm_step(ssm_ctx* c, int64_t n_ticks)
     if (n_ticks < 0) return fail(SSM_ERR_INVALID, "n_ticks < 0");
     if (c->tick + n_ticks > c->ticks_total) return fail(SSM_ERR_STATE, "stepping past T");
     if (n_ticks == 0) return SSM_OK;
-    if (small_usable(c)) return (c->prec == SSM_FP64) ? launch_small<double>(c, n_ticks) : launch_small<float>(c, n_ticks);
+    if (small_usable(c)) {
+        // launches of at most kSmallTicksPerLaunch ticks, so that one call
+        // does not hold the GPU for an unbounded time (a run split over
+        // launches equals one launch bit for bit)
+        for (int64_t done = 0; done < n_ticks;) {
+            const int64_t n = std::min<int64_t>(n_ticks - done, kSmallTicksPerLaunch);
+            ssm_status st = (c->prec == SSM_FP64) ? launch_small<double>(c, n) : launch_small<float>(c, n);
+            if (st != SSM_OK) return st;
+            done += n;
+        }
+        return SSM_OK;
+    }
     if (c->psum_stale) {
         ssm_status st = (c->prec == SSM_FP64) ? refresh_after_small<double>(c) : refresh_after_small<float>(c);
         if (st != SSM_OK) return st;

@@ -196,6 +196,19 @@ def test_switch_to_multi_launch_inside_a_window(torch_cuda):
     assert err <= FP64_TOL
 
 
+def test_long_calls_are_split_into_launches(torch_cuda):
+    """A call of 8192 ticks runs as two launches of at most 4096 ticks (so
+    that one call does not hold the GPU for an unbounded time), against the
+    oracle."""
+    w = W.small_parity(n_ens=2, N=100, h=2.0 ** -13, h_fine=2.0 ** -13)
+    ref = oracle.run(w)
+    got, info = _run(w, "fp64", persistent=1)
+    assert info["persistent_ticks"] == 8192 and info["persistent_launches"] == 2
+    err = max(_err(g, r) for g, r in zip(got, ref))
+    _say(f"8192 ticks in two launches: {err:.3e}")
+    assert err <= FP64_TOL
+
+
 def test_mixed_with_multi_launch_ticks(torch_cuda, small_case):
     """Persistent ticks, then profiled ticks (the multi-launch path, whose
     block sums of Y* are refreshed first), then persistent ticks again: the
