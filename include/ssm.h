@@ -150,7 +150,7 @@ typedef struct {
      * differ from unbanded ones by summation order only. */
     int32_t jside_band_groups;
     /* Persistent runs of small systems: one cooperative launch runs every
-     * tick of an ssm_step call.  Each workgroup owns 64 particles of one
+     * tick of an ssm_step call (up to 4096 ticks per launch).  Each workgroup owns 64 particles of one
      * system, stages the system's positions in LDS, sums the interaction
      * over every ordered pair of its particles, draws their increments and
      * updates them; the workgroups of a system then wait at that system's
