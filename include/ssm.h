@@ -322,9 +322,11 @@ ssm_status ssm_sqdiff(ssm_ctx *a, int32_t sys_a, ssm_ctx *b, int32_t sys_b, doub
 /* Per-kernel timing with HIP events on the context's stream: every = 0
  * disables it; every = k >= 1 records one event before and one after the
  * pairwise launch and the update launches of each tick with tick % k == 0
- * (k = 1: every tick).  Enabling resets the accumulated times.  Each event
- * pair costs a few microseconds of stream time, so a stride k > 1 keeps a
- * timed run close to an untimed one while still averaging over the whole run. */
+ * (k = 1: every tick).  Enabling resets the accumulated times.  The events
+ * are for timing only (created without a system-scope fence; their times are
+ * read after the stream is synchronized).  Each event pair costs about 3
+ * microseconds of stream time, so a stride k > 1 keeps a timed run close to
+ * an untimed one while still averaging over the whole run. */
 ssm_status ssm_profile(ssm_ctx *ctx, int32_t every);
 
 /* Counters, tiling and (if enabled) kernel times of a context.  Synchronizes. */

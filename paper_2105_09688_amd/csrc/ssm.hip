@@ -334,8 +334,11 @@ static hipEvent_t take_event(ssm_ctx* c)
         c->ev_pool.pop_back();
         return e;
     }
+    // timing only (read after the stream is synchronized): no system-scope
+    // fence, whose cache writeback cost about 3 us per timed tick and slowed
+    // the launch after it
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
