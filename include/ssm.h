@@ -214,6 +214,7 @@ typedef struct {
     int32_t persistent_tiles;    /* workgroups of a persistent launch (64 particles each) */
     int64_t persistent_launches; /* cooperative launches so far */
     int64_t persistent_ticks;    /* ticks they ran */
+    int64_t surr_rechecks;       /* checks made during a fallback (ssm_surrogate_recheck) */
 } ssm_info_t;
 
 /* Training settings of ssm_mlp_train (Adam; zeros select the defaults in brackets). */
@@ -433,6 +434,19 @@ ssm_status ssm_surrogate_load(ssm_ctx *ctx, const float *master, int64_t n);
  * Check ticks synchronize the stream.  check_every = 0 turns the surrogate
  * off.  Enabling (again) forgets the gain and the residuals. */
 ssm_status ssm_surrogate_enable(ssm_ctx *ctx, int32_t check_every, double tol, int32_t mode);
+
+/* Rechecks during a fallback (an extension; off by default).  With on = 1,
+ * after a failed check every following tick on which all systems step is a
+ * check as well: its exact sums are computed anyway (the fallback uses them),
+ * so the prediction is compared with them at the cost of one inference, and
+ * a passing recheck ends the fallback before the next scheduled check.  The
+ * scheduled checks every check_every ticks stay, so no tick uses the
+ * prediction more than check_every - 1 ticks after a passing check.  In
+ * residual mode a recheck stores the residuals of its tick, so the error it
+ * compares is that of one tick's drift.  Rechecks count in surr_checks and in
+ * surr_rechecks, and not in surr_fallback_ticks; they synchronize the stream
+ * like the other checks.  SSM_ERR_INVALID unless on is 0 or 1. */
+ssm_status ssm_surrogate_recheck(ssm_ctx *ctx, int32_t on);
 
 /* The surrogate's raw output at the current Y* of system sys, from the
  * kernels a surrogate tick runs: moments (host float [2K], may be NULL)

@@ -19,6 +19,7 @@ EXPORTS = (
     "ssm_set_state", "ssm_state_layout", "ssm_bind_state", "ssm_state_refresh", "ssm_rmse", "ssm_sqdiff", "ssm_info", "ssm_profile", "ssm_destroy", "ssm_last_error",
     "ssm_pair_sum", "ssm_pair_workspace_bytes", "ssm_implicit_solve", "ssm_brownian",
     "ssm_philox_blocks", "ssm_mlp_num_params", "ssm_surrogate_load", "ssm_surrogate_enable",
+    "ssm_surrogate_recheck",
     "ssm_surrogate_samples", "ssm_surrogate_predict", "ssm_mlp_forward", "ssm_mlp_forward_noalloc", "ssm_mlp_loss_grad", "ssm_mlp_train", "ssm_surrogate_train",
 )
 
@@ -55,6 +56,7 @@ class Info(C.Structure):
         ("surr_last_raw_err", C.c_double), ("surr_gain", C.c_double * MAX_D),
         ("persistent", C.c_int32), ("persistent_tiles", C.c_int32),
         ("persistent_launches", C.c_int64), ("persistent_ticks", C.c_int64),
+        ("surr_rechecks", C.c_int64),
     ]
 
 
@@ -112,6 +114,7 @@ def load():
         "ssm_mlp_num_params": (i64, [i32]),
         "ssm_surrogate_load": (st, [vp, vp, i64]),
         "ssm_surrogate_enable": (st, [vp, i32, C.c_double, i32]),
+        "ssm_surrogate_recheck": (st, [vp, i32]),
         "ssm_surrogate_samples": (st, [vp, i32, i64, u64, vp, vp]),
         "ssm_surrogate_predict": (st, [vp, i32, dp, vp]),
         "ssm_mlp_forward": (st, [i32, vp, vp, i64, vp, vp]),

@@ -275,6 +275,8 @@ struct ssm_ctx {
     double surr_tol = 1e-3;
     bool surr_fallback = false;
     int64_t surr_checks = 0, surr_fallback_ticks = 0, surr_ticks = 0;
+    bool surr_recheck = false;     // in a fallback, every tick where all systems step is a check
+    int64_t surr_rechecks = 0;     // checks made by that rule
     double surr_last_err = 0.0, surr_max_err = 0.0, surr_last_raw_err = 0.0;
     double surr_gain[kMaxD] = {1.0, 1.0, 1.0, 1.0};
     int32_t surr_mode = SSM_SURR_GAIN;
@@ -654,7 +656,12 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
     T* Ys = (T*)c->Ys;
     const int d = c->d;
     const bool surr_on = c->surr_check_every > 0 && c->has_pair;
-    const bool check = surr_on && (c->tick % c->surr_check_every == 0);
+    // scheduled checks every surr_check_every ticks; with surr_recheck, a
+    // fallback tick on which every system steps is a check too (its exact
+    // term is computed anyway, and the network is judged on it)
+    const bool recheck = surr_on && c->surr_recheck && c->surr_fallback && c->tick % c->surr_check_every != 0 &&
+                         c->tick % c->max_stride == 0;
+    const bool check = surr_on && (c->tick % c->surr_check_every == 0 || recheck);
     const bool run_exact = !surr_on || check || c->surr_fallback;
     const bool run_surr = surr_on && (check || !c->surr_fallback);
     const bool prof = c->profiling && c->tick % c->profile_every == 0;
@@ -796,6 +803,7 @@ static ssm_status launch_tick(ssm_ctx* c, bool capture)
         c->surr_last_err = err;
         c->surr_max_err = std::max(c->surr_max_err, err);
         c->surr_checks++;
+        if (recheck) c->surr_rechecks++;
         c->surr_fallback = !(err <= c->surr_tol);
     }
     return SSM_OK;
@@ -1798,6 +1806,7 @@ extern "C" ssm_status ssm_info(ssm_ctx* c, ssm_info_t* out)
     out->surr_checks = c->surr_checks;
     out->surr_ticks = c->surr_ticks;
     out->surr_fallback_ticks = c->surr_fallback_ticks;
+    out->surr_rechecks = c->surr_rechecks;
     out->surr_last_err = c->surr_last_err;
     out->surr_max_err = c->surr_max_err;
     out->surr_last_raw_err = c->surr_last_raw_err;
@@ -2065,6 +2074,14 @@ extern "C" ssm_status ssm_surrogate_enable(ssm_ctx* c, int32_t check_every, doub
     c->surr_fallback = false;
     c->surr_res_valid = false;
     for (int k = 0; k < kMaxD; ++k) c->surr_gain[k] = 1.0;
+    return SSM_OK;
+}
+
+extern "C" ssm_status ssm_surrogate_recheck(ssm_ctx* c, int32_t on)
+{
+    if (!c) return fail(SSM_ERR_INVALID, "ctx is NULL");
+    if (on != 0 && on != 1) return fail(SSM_ERR_INVALID, "on must be 0 or 1");
+    c->surr_recheck = on == 1;
     return SSM_OK;
 }
 

@@ -212,12 +212,15 @@ class SSM:
         m = np.ascontiguousarray(np.asarray(master, dtype=np.float32).ravel())
         check(_lib.load().ssm_surrogate_load(self._h, m.ctypes.data, m.size))
 
-    def surrogate_enable(self, check_every: int = 16, tol: float = 1e-3, mode: str = "gain") -> None:
-        """mode "gain": g (s - mean s); "residual": (s - mean s) + the residual of the last check."""
+    def surrogate_enable(self, check_every: int = 16, tol: float = 1e-3, mode: str = "gain",
+                         recheck: bool = False) -> None:
+        """mode "gain": g (s - mean s); "residual": (s - mean s) + the residual of the last check.
+        recheck: during a fallback every tick on which all systems step is a check too."""
         modes = {"gain": 0, "residual": 1}
         if mode not in modes:
             raise ValueError(f"mode must be one of {sorted(modes)}")
         check(_lib.load().ssm_surrogate_enable(self._h, int(check_every), float(tol), modes[mode]))
+        check(_lib.load().ssm_surrogate_recheck(self._h, 1 if recheck else 0))
 
     def surrogate_predict(self, sys: int = 0):
         """(network output s [d][N] float64, RFF moments [2K] float32) at the

@@ -427,6 +427,70 @@ def test_surrogate_residual_mode_zero_network_matches_oracle(torch_cuda):
     assert np.max(np.abs(X - X_ex)) > 1e-6
 
 
+def test_recheck_with_failing_checks_is_the_exact_run(trained_small):
+    """With rechecks on and an impossible tolerance every tick is a check
+    (scheduled or recheck), every update uses the exact sums, and the run is
+    the exact one bitwise."""
+    w, master, X_exact = trained_small
+    X_fb, info = _surrogate_run(w, master, check_every=4, tol=1e-12, recheck=True)
+    _say(f"recheck fallback run: {info['surr_checks']} checks ({info['surr_rechecks']} rechecks)")
+    assert info["surr_checks"] == 32 and info["surr_rechecks"] == 32 - 8
+    assert info["surr_ticks"] == 0 and info["surr_fallback_ticks"] == 0
+    assert np.array_equal(X_fb, X_exact)
+    # an accepting tolerance never falls back, so it never rechecks
+    _, info = _surrogate_run(w, master, check_every=4, tol=1e9, recheck=True)
+    assert info["surr_rechecks"] == 0 and info["surr_ticks"] == 32 - 8
+
+
+def test_recheck_zero_network_matches_oracle(torch_cuda):
+    """Residual mode with an all-zero network and rechecks: the prediction
+    is the exact term frozen at the last check, so a check's error is the
+    relative change of the exact term since that check.  With the tolerance
+    between the one-tick and the three-tick change, each scheduled check
+    (every 4 ticks, three ticks after the last recheck) fails, the recheck on
+    the next tick passes, and the two ticks after it use the frozen term.
+    The oracle runs the same rule from its exact step, with its own FP64
+    errors deciding (each at least 20 % away from the tolerance); the counts
+    must agree and the states meet the FP32 bar 1e-4."""
+    from paper_2105_09688_amd.ssm import SSM, mlp_num_params
+    h = 2.0 ** -9
+    w = _small_w(N=1536, T=24 * h)
+    every, tol = 4, 2.4e-2
+    with SSM(w, precision="fp32_kahan") as s:
+        s.surrogate_load(np.zeros(mlp_num_params(D), dtype=np.float32))
+        s.surrogate_enable(check_every=every, tol=tol, mode="residual", recheck=True)
+        s.run()
+        info = s.info()
+        X_gpu = s.state(0)
+    N, ens, _ = w["systems"][0]
+    g, ell = w["b"]["g"], w["b"]["ell"]
+    X = oracle.init_state(w, ens, N)
+    P_frozen, fallback, checks, rechecks, net = None, False, 0, 0, 0
+    for n in range(24):
+        X_next, Y = oracle.step(w, ens, h, n, X)
+        P = oracle.pair_sum(Y, ell)
+        sched = n % every == 0
+        if sched or fallback:
+            q = np.zeros_like(P) if P_frozen is None else P_frozen
+            err = float(np.sqrt(np.sum((q - P) ** 2) / np.sum(P ** 2)))
+            assert abs(err / tol - 1.0) > 0.2, f"tick {n}: error {err:.3e} too close to the tolerance"
+            checks += 1
+            rechecks += 0 if sched else 1
+            fallback = not err <= tol
+            P_frozen = P
+            X = X_next
+        else:
+            net += 1
+            X = X_next + h * g * (P_frozen - P)
+    _say(f"recheck, zero network: {info['surr_checks']} checks ({info['surr_rechecks']} rechecks), "
+         f"{info['surr_ticks']} network ticks; oracle {checks} ({rechecks}), {net}")
+    assert (info["surr_checks"], info["surr_rechecks"], info["surr_ticks"]) == (checks, rechecks, net)
+    assert rechecks > 0 and net > 0
+    err = np.max(np.abs(X_gpu - X) / np.maximum(1.0, np.abs(X)))
+    _say(f"max rel err vs oracle emulation {err:.3e}")
+    assert err <= 1e-4
+
+
 @pytest.fixture(scope="module")
 def rmse_case(torch_cuda):
     """The reduced surrogate case for the strong-error comparisons: d = 2,
