@@ -516,29 +516,33 @@ def study_surrogate(args, stream):
     # the trained network, and (the scheme without a network) an all-zero
     # network in residual mode: the exact pair term frozen at the last check
     zeros = np.zeros_like(master)
-    cases = (("gain", 1e-3, master, ""), ("gain", 1e-2, master, ""), ("gain", 1e9, master, ""),
-             ("residual", 1e-3, master, ""), ("residual", 1e9, master, ""),
-             ("residual", 1e-3, zeros, "frozen exact term, "), ("residual", 1e9, zeros, "frozen exact term, "))
-    for mode, tol, weights, tag in cases:
-        def setup(s, tol=tol, mode=mode, weights=weights):
+    cases = (("gain", 1e-3, master, "", False), ("gain", 1e-2, master, "", False), ("gain", 1e9, master, "", False),
+             ("residual", 1e-3, master, "", False), ("residual", 1e-3, master, "", True),
+             ("residual", 1e9, master, "", False),
+             ("residual", 1e-3, zeros, "frozen exact term, ", False),
+             ("residual", 1e-3, zeros, "frozen exact term, ", True),
+             ("residual", 1e9, zeros, "frozen exact term, ", False))
+    for mode, tol, weights, tag, recheck in cases:
+        def setup(s, tol=tol, mode=mode, weights=weights, recheck=recheck):
             s.surrogate_load(weights)
-            s.surrogate_enable(check_every=every, tol=tol, mode=mode)
+            s.surrogate_enable(check_every=every, tol=tol, mode=mode, recheck=recheck)
         su, dt_su, _ = timed_run(SSM, w, prec, stream, setup=setup)
         info = su.info()
         X = su.state(0)
         m, v = su.moments(0)
         su.close()
         D = X - X_ex
-        runs[f"{tag}{mode} tol={tol:g}"] = {
+        runs[f"{tag}{mode} tol={tol:g}{' recheck' if recheck else ''}"] = {
             "seconds": dt_su, "particle_steps_per_s": N * n / dt_su, "speedup_vs_exact": dt_ex / dt_su,
-            "checks": info["surr_checks"], "surrogate_ticks": info["surr_ticks"],
+            "checks": info["surr_checks"], "rechecks": info["surr_rechecks"], "surrogate_ticks": info["surr_ticks"],
             "fallback_ticks": info["surr_fallback_ticks"], "check_rel_err_last": info["surr_last_err"],
             "check_rel_err_max": info["surr_max_err"], "check_rel_err_last_without_gain": info["surr_last_raw_err"],
             "gain_last": info["surr_gain"],
             "pathwise_rms_vs_exact": float(np.sqrt(np.sum(D * D) / N)),
             "mean_diff": [float(x) for x in m - m_ex], "var_diff": [float(x) for x in v - v_ex],
         }
-        print(f"[surrogate] {tag}{mode} tol {tol:g}: {dt_su:.2f} s, {info['surr_ticks']} surrogate ticks, "
+        print(f"[surrogate] {tag}{mode} tol {tol:g}{' recheck' if recheck else ''}: {dt_su:.2f} s, "
+              f"{info['surr_ticks']} surrogate ticks, "
               f"last err {info['surr_last_err']:.3e}, max err {info['surr_max_err']:.3e}", file=sys.stderr, flush=True)
     # strong error at fixed h against a 2^-13 proxy solution on the same paths,
     # at N = min(N, 2^18), the size the network was trained at (the proxy run
@@ -549,23 +553,24 @@ def study_surrogate(args, stream):
     ref = SSM(W.with_h(wr, 2.0 ** -13), precision=prec, stream=stream)
     ref.run()
     rm = {}
-    variants = (("exact", None, None, None), ("gain tol=1e-2", "gain", 1e-2, master),
-                ("gain always", "gain", 1e9, master), ("residual tol=1e-3", "residual", 1e-3, master),
-                ("residual always", "residual", 1e9, master),
-                ("frozen exact term tol=1e-3", "residual", 1e-3, zeros),
-                ("frozen exact term always", "residual", 1e9, zeros))
-    for label, mode, tol, weights in variants:
+    variants = (("exact", None, None, None, False), ("gain tol=1e-2", "gain", 1e-2, master, False),
+                ("gain always", "gain", 1e9, master, False), ("residual tol=1e-3", "residual", 1e-3, master, False),
+                ("residual tol=1e-3 recheck", "residual", 1e-3, master, True),
+                ("residual always", "residual", 1e9, master, False),
+                ("frozen exact term tol=1e-3", "residual", 1e-3, zeros, False),
+                ("frozen exact term always", "residual", 1e9, zeros, False))
+    for label, mode, tol, weights, recheck in variants:
         with SSM(wr, precision=prec, stream=stream) as a:
             if tol is not None:
                 a.surrogate_load(weights)
-                a.surrogate_enable(check_every=every, tol=tol, mode=mode)
+                a.surrogate_enable(check_every=every, tol=tol, mode=mode, recheck=recheck)
             a.run()
             rm[label] = math.sqrt(a.sqdiff(0, ref, 0) / Nr)
             if tol is not None:
                 i = a.info()
                 rm[label + " surrogate ticks"] = i["surr_ticks"]
     ref.close()
-    for label, _m, tol, _w in variants[1:]:
+    for label, _m, tol, _w, _r in variants[1:]:
         rm[f"ratio {label} / exact"] = rm[label] / rm["exact"]
     pair_avg = info_ex["pair_ms"] / 1e3 / max(1, info_ex["pair_launches"])
     return {"study": "surrogate", f"rmse_vs_2^-13_at_N={Nr}": rm, "workload": f"d=2 N={N} T=1 h=2^-9, exact check every {every} steps, {prec}",
