@@ -442,6 +442,30 @@ def test_recheck_with_failing_checks_is_the_exact_run(trained_small):
     assert info["surr_rechecks"] == 0 and info["surr_ticks"] == 32 - 8
 
 
+def test_recheck_only_where_every_system_steps(torch_cuda):
+    """In a context of two step sizes (strides 1 and 2) a recheck falls only
+    on ticks where both systems step: with an impossible tolerance, checks on
+    every even tick (8 scheduled every 4 ticks, 8 rechecks), the odd ticks
+    exact as fallback ticks, and the run bitwise the exact one."""
+    from paper_2105_09688_amd.ssm import SSM, mlp_init
+    h = 2.0 ** -9
+    w = W.with_systems(_small_w(N=1024, T=32 * h), [(1024, 0, h), (1000, 1, 2 * h)])
+    with SSM(w, precision="fp32_kahan", persistent=-1) as ex:
+        ex.run()
+        X_ex = ex.states()
+    with SSM(w, precision="fp32_kahan") as s:
+        s.surrogate_load(mlp_init(D, seed=4))
+        s.surrogate_enable(check_every=4, tol=1e-12, mode="residual", recheck=True)
+        s.run()
+        info = s.info()
+        X = s.states()
+    _say(f"two step sizes: {info['surr_checks']} checks ({info['surr_rechecks']} rechecks), "
+         f"{info['surr_fallback_ticks']} fallback ticks")
+    assert (info["surr_checks"], info["surr_rechecks"], info["surr_fallback_ticks"], info["surr_ticks"]) == (16, 8, 16, 0)
+    for a, b in zip(X, X_ex):
+        assert np.array_equal(a, b)
+
+
 def test_recheck_zero_network_matches_oracle(torch_cuda):
     """Residual mode with an all-zero network and rechecks: the prediction
     is the exact term frozen at the last check, so a check's error is the
