@@ -440,6 +440,12 @@ def test_recheck_with_failing_checks_is_the_exact_run(trained_small):
     # an accepting tolerance never falls back, so it never rechecks
     _, info = _surrogate_run(w, master, check_every=4, tol=1e9, recheck=True)
     assert info["surr_rechecks"] == 0 and info["surr_ticks"] == 32 - 8
+    # the switch takes 0 or 1 only
+    from paper_2105_09688_amd import SSMError, _lib
+    from paper_2105_09688_amd.ssm import SSM
+    with SSM(w, precision="fp32_kahan") as s:
+        with pytest.raises(SSMError):
+            _lib.check(_lib.load().ssm_surrogate_recheck(s._h, 2))
 
 
 def test_recheck_only_where_every_system_steps(torch_cuda):
